@@ -1,0 +1,26 @@
+"""Reference oracle for the ChFSI hot path -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, FP64 CPU implementation (numpy/scipy) of what the GPU library
+computes, written from the paper's description of the spectral finite-element
+Kohn-Sham eigenproblem (Sec. 2.4, eq. hep) and of Chebyshev-filtered subspace
+iteration (Sec. 3.3 eq. chebFilter, Sec. 3.4 Alg. 3 CholGS, Sec. 3.5 RR).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP path
+(``paper_1903_10959_amd``) and imports nothing from it; the only module both
+sides use is the seeded input generator ``workload``.
+
+Modules
+-------
+``fem``    GLL rule, Lagrange derivative matrix, cell matrices, numbering,
+           colouring, CSR assembly of the standard-form Hamiltonian and its
+           Kronecker-sum form (Sec. 2.4).
+``chfsi``  Chebyshev filter (paper's unscaled recursion and the normalised
+           one), CholGS (FP64 and the paper's mixed variant), Rayleigh-Ritz,
+           the subspace-iteration loop, dense and Lanczos eigensolves.
+
+Pinning status (what each function is checked against) is listed in the
+module docstrings.  Mixed-precision accuracy is *parity unpinned* by the paper
+(its accuracy table is a full-DFT comparison); it is measured against the FP64
+functions here and reported.
+"""
