@@ -1,0 +1,189 @@
+/*
+ * chfsi.h -- C ABI of the MI355X (gfx950) Chebyshev-filtered subspace
+ * iteration library for the spectral finite-element Kohn-Sham operator.
+ *
+ * The operator is the standard form of the discrete eigenproblem
+ * H psi = eps M psi (Sec. 2.4, eq. hep):
+ *
+ *     Htilde = M^-1/2 H M^-1/2,  H = K + diag(M V),
+ *
+ * on a uniform mesh of n_el^3 hexahedral cells of [0,L]^3 with C0 Lagrange
+ * elements of degree p on Gauss-Lobatto-Legendre nodes, homogeneous Dirichlet
+ * boundary (boundary nodes carry no unknown).  K is the stiffness of
+ * -1/2 Laplacian (eq. discreteHam); GLL quadrature makes M diagonal, so
+ * Htilde X = M^-1/2 (sum_e P_e^T K_e P_e) M^-1/2 X + V .* X, applied cell by
+ * cell (Sec. 3.3, practical implementation of Chebyshev filtering).
+ *
+ * Conventions used by every call:
+ *  - Return value: 0 = OK, < 0 = error (CHFSI_ERR_*), > 0 = warning.  No C++
+ *    exception crosses this interface; chfsi_last_error() gives a message.
+ *  - Blocks of vectors X are FP64, DoF-major ("for each degree of freedom the
+ *    values of all vectors are stored contiguously", Sec. 3.3): element
+ *    (dof i, column j) is X[i*ld + j], ld >= ncols.  All such pointers are
+ *    DEVICE pointers owned by the caller; the library never frees them.
+ *  - Numbering: interior node (I,J,K), 1 <= I,J,K <= n, n = n_el*p - 1, is
+ *    dof (I-1) + n(J-1) + n^2(K-1); cell e = ex + n_el*ey + n_el^2*ez; local
+ *    node l = a + (p+1)b + (p+1)^2 c with I = ex*p + a.
+ *  - Streams: all device work is enqueued on the stream given at create time
+ *    (borrowed, not owned).  Calls that return host data synchronise it.
+ *  - Threads: one context is used by one host thread at a time.  Separate
+ *    contexts on separate streams may run concurrently.
+ *  - Units: Hartree and bohr.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chfsi_ctx chfsi_ctx;   /* opaque; owned by the library */
+
+/* Arithmetic of the filter's cell products.  FP64 = the paper's precision.
+ * FP32: recursion state and products in FP32.  BF16: products with BF16
+ * inputs and FP32 accumulation, recursion state FP32.  BF16X3: BF16 hi/lo
+ * split of both operands, three products accumulated in FP32. */
+typedef enum {
+    CHFSI_FP64 = 0,
+    CHFSI_FP32 = 1,
+    CHFSI_BF16 = 2,
+    CHFSI_BF16X3 = 3
+} chfsi_prec;
+
+enum {
+    CHFSI_OK = 0,
+    CHFSI_ERR_ARG = -1,        /* invalid argument (size, pointer, range)           */
+    CHFSI_ERR_STATE = -2,      /* call order: mesh/potential not set                */
+    CHFSI_ERR_OOM = -3,        /* device allocation failed                          */
+    CHFSI_ERR_HIP = -4,        /* a HIP runtime call failed                         */
+    CHFSI_ERR_NOT_SPD = -5,    /* Cholesky met a non-positive pivot (rank deficient) */
+    CHFSI_ERR_NONFINITE = -6,  /* NaN/Inf produced (e.g. b below lambda_max)        */
+    CHFSI_WARN_NOT_CONVERGED = 1
+};
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; `hip_stream` (a hipStream_t, may be
+ * NULL = the null stream) is borrowed for all later work.  device = -1 creates
+ * a host-only context: set_mesh/set_potential build the host tables and the
+ * bound, the get_* calls work, every device call returns CHFSI_ERR_STATE. */
+int chfsi_create(chfsi_ctx **out, int device, void *hip_stream);
+/* Free everything the context allocated (device buffers, host tables). */
+int chfsi_destroy(chfsi_ctx *ctx);
+
+/* ---- setMesh (Sec. 2.4 eq. fem, Sec. 3.1 mesh; uniform cubes only) ------
+ * Build the GLL rule of degree p (1..12), the reference cell stiffness
+ * 1/2 (h/2)[K1 (x) W (x) W + W (x) K1 (x) W + W (x) W (x) K1] (h = L/n_el,
+ * K1 = D^T W D, W = diag of GLL weights), the cell->dof map, the 8-colour
+ * cell colouring (ex&1)+2(ey&1)+4(ez&1) and the diagonal mass M (GLL rule),
+ * and upload them.  Resets any potential set before.  Requires n_el*p >= 2. */
+int chfsi_set_mesh(chfsi_ctx *ctx, double L, int n_el, int p);
+int chfsi_get_sizes(const chfsi_ctx *ctx, int64_t *n_dof, int64_t *n_cells, int *n_loc);
+/* Host copies of the tables built by set_mesh (caller-owned host buffers). */
+int chfsi_get_cell_dof_map(const chfsi_ctx *ctx, int32_t *host_out);  /* [n_cells*n_loc], -1 = Dirichlet */
+int chfsi_get_cell_colors(const chfsi_ctx *ctx, uint8_t *host_out);   /* [n_cells] */
+int chfsi_get_dof_coords(const chfsi_ctx *ctx, double *host_xyz);     /* [3*n_dof], x,y,z per dof */
+int chfsi_get_mass(const chfsi_ctx *ctx, double *host_m);             /* [n_dof] diagonal of M */
+int chfsi_get_cell_matrix(const chfsi_ctx *ctx, double *host_k);      /* [n_loc*n_loc] cell stiffness */
+
+/* ---- setPotential (Sec. 2.4 eq. discreteHam, GLL quadrature) -----------
+ * Nodal V (Ha) at the n_dof interior nodes, host (v_on_device = 0) or device
+ * pointer; copied.  Also sets the filter's upper bound
+ * b = 3 lambda_max(A_1D) + max V >= lambda_max(Htilde) (Weyl; A_1D is the
+ * assembled 1D operator whose Kronecker sum is the kinetic part). */
+int chfsi_set_potential(chfsi_ctx *ctx, const double *v, int64_t n_dof, int v_on_device);
+int chfsi_get_upper_bound(const chfsi_ctx *ctx, double *b);
+
+/* ---- Htilde X (Sec. 3.3: cell-level products, assembled) -----------------
+ * Y = Htilde X for ncols columns.  X, Y: device, [n_dof x ld], must not alias.
+ * prec selects the cell-product arithmetic (X, Y stay FP64). */
+int chfsi_apply(chfsi_ctx *ctx, const double *X, double *Y, int64_t ld, int ncols, chfsi_prec prec);
+
+/* One recursion step (eq. chebFilter, normalised form):
+ * Y = s1 (Htilde - shift) X + s2 Xprev   (Xprev may be NULL when s2 == 0).
+ * All device FP64 [n_dof x ld]; Y must not alias X or Xprev. */
+int chfsi_cheb_step(chfsi_ctx *ctx, const double *X, const double *Xprev, double *Y,
+                    int64_t ld, int ncols, double s1, double s2, double shift);
+
+/* ---- chebyshevFilter (Sec. 3.3 eq. chebFilter) ----------------------------
+ * In place: X <- T_m(Hbar) X / T_m(xi0), Hbar = (Htilde - c)/e,
+ * c = (a+b)/2, e = (b-a)/2, xi0 = (a0-c)/e, requires a0 < a < b.
+ * Vectors are filtered in blocks of block_width columns (0 = library default)
+ * with three rotating buffers per block.  Returns CHFSI_ERR_NONFINITE if the
+ * result holds NaN/Inf. */
+int chfsi_chebyshev_filter(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int degree,
+                           double a, double b, double a0, chfsi_prec prec, int block_width);
+
+/* ---- orthonormalize (Sec. 3.4 Alg. 3, CholGS) ----------------------------
+ * In place: S = X^T X, S = L L^T, L^-1, X <- X L^-T, so X^T X = I on return.
+ * mixed = 1: the paper's mixed-precision split (eq. overlapmixedprec): FP64
+ * diagonal blocks of S and of L^-T, FP32 off-diagonal blocks.
+ * CHFSI_ERR_NOT_SPD if S is not numerically positive definite (X unchanged). */
+int chfsi_orthonormalize(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int mixed);
+
+/* ---- rayleighRitz (Sec. 3.5 steps i-iii) ---------------------------------
+ * In place, for orthonormal X: HX = Htilde X, Hhat = X^T HX (lower triangle),
+ * Hhat Q = Q D (D ascending, FP64 Jacobi on the device), X <- X Q.
+ * evals, resid: host arrays [ncols]; resid[i] = ||Htilde x_i - D_i x_i||_2.
+ * HX_out (device [n_dof x ld] or NULL) receives Htilde X after rotation. */
+int chfsi_rayleigh_ritz(chfsi_ctx *ctx, double *X, int64_t ld, int ncols,
+                        double *evals, double *resid, double *HX_out);
+
+/* ---- solve (Alg. 2 step 7 with the adaptive repeat of Sec. 3.3) ----------
+ * X: device [n_dof x ld], ld >= nblock, holds the start (or warm-start) block
+ * on entry and the Ritz vectors (tilde space, orthonormal) on exit.
+ * Loop: CholGS + RR on X; then repeat {filter (a = largest Ritz value, b from
+ * set_potential, a0 = smallest), CholGS, RR} until
+ * max_{i < nstates} resid_i <= tol or max_iter filter passes.
+ * evals, resid: host [nblock].  rep (may be NULL) receives counters/timings.
+ * The filter precision follows the ladder: ladder[0] until the largest wanted
+ * residual stops falling by 2x per pass or drops below ladder_switch, then
+ * ladder[1], ... (n_ladder = 0 means FP64 throughout). */
+typedef struct {
+    int nstates;          /* wanted states N                                  */
+    int nblock;           /* block size N_b >= nstates (guard states)         */
+    int degree;           /* Chebyshev degree m                               */
+    int max_iter;         /* cap on filter passes                             */
+    int block_width;      /* filter block width (0 = default)                 */
+    double tol;           /* residual tolerance on the wanted states          */
+    chfsi_prec ladder[4]; /* filter precision ladder                          */
+    int n_ladder;
+    double ladder_switch; /* residual below which the next rung starts (0=off)*/
+    int mixed_cholgs;     /* 1: paper's mixed CholGS                          */
+} chfsi_opts;
+
+typedef struct {
+    int iters;            /* filter passes done                               */
+    int status;           /* same as the return value                         */
+    int rung;             /* ladder rung in use at exit                       */
+    double t_filter, t_cholgs, t_rr;   /* seconds (device events)              */
+    double max_resid;     /* largest wanted residual at exit                  */
+    int64_t dofvecs;      /* Htilde applications x n_dof                      */
+} chfsi_report;
+
+int chfsi_solve(chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
+                double *evals, double *resid, chfsi_report *rep);
+
+/* ---- admission / diagnostics ---------------------------------------------
+ * Device bytes a context needs for (n_el, p) and a solve of nblock vectors with
+ * the given filter block width and precision (pure; no device access). */
+size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_width, chfsi_prec prec);
+const char *chfsi_status_string(int status);
+const char *chfsi_last_error(const chfsi_ctx *ctx);
+/* Timing of the cell-product kernel (the filter's dominant kernel): when
+ * enabled, every launch of it is bracketed by HIP events on the context
+ * stream.  chfsi_last_filter_timing synchronises the stream and returns the
+ * summed device time (ms) and the launch count since the last reset, plus
+ * the cell-product work in those launches as cell-vector products
+ * (cells x columns, so flops = 2 n_loc^2 x that count). */
+int chfsi_set_timing(chfsi_ctx *ctx, int enable);
+int chfsi_reset_timing(chfsi_ctx *ctx);
+int chfsi_last_filter_timing(chfsi_ctx *ctx, double *ms_cells, int *n_launches, int64_t *cell_vecs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHFSI_H */

@@ -1,0 +1,244 @@
+"""MI355X (gfx950) Chebyshev-filtered subspace iteration for the spectral
+finite-element Kohn-Sham operator -- Python binding of libchfsi.so.
+
+Every numerical step runs in the HIP library (include/chfsi.h); this module
+only marshals arguments: torch tensors on the GPU supply device pointers and
+the current HIP stream.  Blocks X are float64, DoF-major (row = degree of
+freedom, column = vector), row stride ``X.stride(0)``.
+
+There is no CPU fallback: if the library is not built, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import PRECISIONS, Opts, Report
+
+__all__ = ["Context", "ChfsiError", "footprint_bytes", "PRECISIONS", "library_path"]
+
+
+class ChfsiError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def footprint_bytes(n_el: int, p: int, nblock: int, block_width: int = 0, prec: str = "fp64") -> int:
+    return int(_lib.load().chfsi_footprint_bytes(n_el, p, nblock, block_width, PRECISIONS[prec]))
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class Context:
+    """One library context: mesh tables, potential and workspaces on one GPU.
+    Work is enqueued on ``stream`` (default: torch's current stream).
+    ``device=-1`` gives a host-only context (tables and bound, no device work)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = _lib.load()
+        self.device = device
+        handle = None
+        if device >= 0:
+            import torch
+
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            handle = stream.cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        st = self._lib.chfsi_create(C.byref(h), device, C.c_void_p(handle))
+        if st != 0:
+            raise ChfsiError(st, "chfsi_create", "invalid device or no GPU")
+        self._h = h
+        self.n_dof = self.n_cells = self.n_loc = 0
+
+    # ---- helpers ---------------------------------------------------------
+    def _check(self, st: int, where: str, ok=(0,)):
+        if st not in ok:
+            msg = self._lib.chfsi_last_error(self._h)
+            raise ChfsiError(st, where, msg.decode() if msg else "")
+        return st
+
+    @staticmethod
+    def _block(X):
+        import torch
+
+        if not isinstance(X, torch.Tensor) or X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2:
+            raise TypeError("expected a 2-D float64 CUDA tensor [n_dof, ncols]")
+        if X.shape[1] > 1 and X.stride(1) != 1:
+            raise ValueError("columns must be contiguous (stride(1) == 1)")
+        return C.c_void_p(X.data_ptr()), int(X.stride(0)), int(X.shape[1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.chfsi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- setMesh ---------------------------------------------------------
+    def set_mesh(self, L: float, n_el: int, p: int):
+        self._check(self._lib.chfsi_set_mesh(self._h, float(L), int(n_el), int(p)), "set_mesh")
+        nd, nc, nl = C.c_int64(), C.c_int64(), C.c_int()
+        self._check(self._lib.chfsi_get_sizes(self._h, C.byref(nd), C.byref(nc), C.byref(nl)), "get_sizes")
+        self.n_dof, self.n_cells, self.n_loc = nd.value, nc.value, nl.value
+        self.L, self.n_el, self.p = float(L), int(n_el), int(p)
+        return self
+
+    def cell_dof_map(self) -> np.ndarray:
+        out = np.empty((self.n_cells, self.n_loc), dtype=np.int32)
+        self._check(self._lib.chfsi_get_cell_dof_map(self._h, out.ctypes.data_as(C.c_void_p)), "get_cell_dof_map")
+        return out
+
+    def cell_colors(self) -> np.ndarray:
+        out = np.empty(self.n_cells, dtype=np.uint8)
+        self._check(self._lib.chfsi_get_cell_colors(self._h, out.ctypes.data_as(C.c_void_p)), "get_cell_colors")
+        return out
+
+    def dof_coords(self) -> np.ndarray:
+        out = np.empty((self.n_dof, 3), dtype=np.float64)
+        self._check(self._lib.chfsi_get_dof_coords(self._h, out.ctypes.data_as(C.c_void_p)), "get_dof_coords")
+        return out
+
+    def mass(self) -> np.ndarray:
+        out = np.empty(self.n_dof, dtype=np.float64)
+        self._check(self._lib.chfsi_get_mass(self._h, out.ctypes.data_as(C.c_void_p)), "get_mass")
+        return out
+
+    def cell_matrix(self) -> np.ndarray:
+        out = np.empty((self.n_loc, self.n_loc), dtype=np.float64)
+        self._check(self._lib.chfsi_get_cell_matrix(self._h, out.ctypes.data_as(C.c_void_p)), "get_cell_matrix")
+        return out
+
+    # ---- setPotential ----------------------------------------------------
+    def set_potential(self, V):
+        import torch
+
+        if isinstance(V, torch.Tensor):
+            if V.dtype != torch.float64 or V.numel() != self.n_dof:
+                raise ValueError("V must be float64 with n_dof entries")
+            V = V.contiguous()
+            st = self._lib.chfsi_set_potential(self._h, C.c_void_p(V.data_ptr()), self.n_dof, 1 if V.is_cuda else 0)
+        else:
+            v = np.ascontiguousarray(V, dtype=np.float64)
+            if v.size != self.n_dof:
+                raise ValueError("V must have n_dof entries")
+            st = self._lib.chfsi_set_potential(self._h, v.ctypes.data_as(C.c_void_p), self.n_dof, 0)
+        self._check(st, "set_potential")
+        return self
+
+    @property
+    def upper_bound(self) -> float:
+        b = C.c_double()
+        self._check(self._lib.chfsi_get_upper_bound(self._h, C.byref(b)), "get_upper_bound")
+        return b.value
+
+    # ---- operator --------------------------------------------------------
+    def apply(self, X, Y=None, prec="fp64"):
+        import torch
+
+        if Y is None:
+            Y = torch.empty_like(X)
+        px, ld, n = self._block(X)
+        py, ldy, ny = self._block(Y)
+        if ldy != ld or ny != n:
+            raise ValueError("X and Y must have the same shape and row stride")
+        self._check(self._lib.chfsi_apply(self._h, px, py, ld, n, _prec(prec)), "apply")
+        return Y
+
+    def cheb_step(self, X, Xprev, Y, s1: float, s2: float, shift: float):
+        px, ld, n = self._block(X)
+        py, ldy, _ = self._block(Y)
+        pp = C.c_void_p(0)
+        if Xprev is not None:
+            pp, ldp, _ = self._block(Xprev)
+            if ldp != ld:
+                raise ValueError("row strides differ")
+        if ldy != ld:
+            raise ValueError("row strides differ")
+        self._check(self._lib.chfsi_cheb_step(self._h, px, pp, py, ld, n, float(s1), float(s2), float(shift)),
+                    "cheb_step")
+        return Y
+
+    # ---- chebyshevFilter -------------------------------------------------
+    def chebyshev_filter(self, X, degree: int, a: float, b: float, a0: float, prec="fp64", block_width: int = 0):
+        px, ld, n = self._block(X)
+        self._check(self._lib.chfsi_chebyshev_filter(self._h, px, ld, n, int(degree), float(a), float(b), float(a0),
+                                                     _prec(prec), int(block_width)), "chebyshev_filter")
+        return X
+
+    # ---- orthonormalize --------------------------------------------------
+    def orthonormalize(self, X, mixed: bool = False):
+        px, ld, n = self._block(X)
+        self._check(self._lib.chfsi_orthonormalize(self._h, px, ld, n, 1 if mixed else 0), "orthonormalize")
+        return X
+
+    # ---- rayleighRitz ----------------------------------------------------
+    def rayleigh_ritz(self, X, HX_out=None):
+        px, ld, n = self._block(X)
+        ev = np.empty(n)
+        rs = np.empty(n)
+        ph = C.c_void_p(0)
+        if HX_out is not None:
+            ph, ldh, nh = self._block(HX_out)
+            if ldh != ld or nh != n:
+                raise ValueError("HX_out must match X")
+        self._check(self._lib.chfsi_rayleigh_ritz(self._h, px, ld, n, ev.ctypes.data_as(C.c_void_p),
+                                                  rs.ctypes.data_as(C.c_void_p), ph), "rayleigh_ritz")
+        return ev, rs
+
+    # ---- solve -----------------------------------------------------------
+    def solve(self, X, nstates: int, degree: int, tol: float, max_iter: int = 200, block_width: int = 0,
+              ladder=("fp64",), ladder_switch: float = 0.0, mixed_cholgs: bool = False):
+        px, ld, nb = self._block(X)
+        o = Opts()
+        o.nstates, o.nblock, o.degree, o.max_iter, o.block_width = int(nstates), nb, int(degree), int(max_iter), \
+            int(block_width)
+        o.tol = float(tol)
+        lad = [_prec(x) for x in ladder][:4]
+        for i, v in enumerate(lad):
+            o.ladder[i] = v
+        o.n_ladder = len(lad)
+        o.ladder_switch = float(ladder_switch)
+        o.mixed_cholgs = 1 if mixed_cholgs else 0
+        ev = np.empty(nb)
+        rs = np.empty(nb)
+        rep = Report()
+        st = self._lib.chfsi_solve(self._h, C.byref(o), px, ld, ev.ctypes.data_as(C.c_void_p),
+                                   rs.ctypes.data_as(C.c_void_p), C.byref(rep))
+        self._check(st, "solve", ok=(0, _lib.WARN_NOT_CONVERGED))
+        return dict(evals=ev, resid=rs, status=st, converged=(st == 0), iters=rep.iters, rung=rep.rung,
+                    t_filter=rep.t_filter, t_cholgs=rep.t_cholgs, t_rr=rep.t_rr, max_resid=rep.max_resid,
+                    dofvecs=rep.dofvecs)
+
+    # ---- timing of the cell-product kernel ---------------------------------
+    def set_timing(self, enable: bool = True):
+        self._check(self._lib.chfsi_set_timing(self._h, 1 if enable else 0), "set_timing")
+
+    def reset_timing(self):
+        self._check(self._lib.chfsi_reset_timing(self._h), "reset_timing")
+
+    def filter_timing(self):
+        ms, n, cv = C.c_double(), C.c_int(), C.c_int64()
+        self._check(self._lib.chfsi_last_filter_timing(self._h, C.byref(ms), C.byref(n), C.byref(cv)),
+                    "last_filter_timing")
+        return dict(ms=ms.value, launches=n.value, cell_vecs=cv.value)

@@ -1,0 +1,658 @@
+// C ABI of the library: context, tables, and the host orchestration of the
+// ChFSI steps (filter, CholGS, Rayleigh-Ritz, solve loop).  Every numerical
+// step runs in the device kernels of hx.hip, dense.hip and small.hip; the host
+// only computes scalars (recursion coefficients, bounds) and control flow.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/chfsi.h"
+#include "kernels.hpp"
+#include "mesh.hpp"
+
+using namespace chfsi;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    else p = nullptr;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+}  // namespace
+
+struct chfsi_ctx {
+  int device = 0;           // -1: host-only context (tables only, no device work)
+  hipStream_t stream = nullptr;
+  std::string err;
+  MeshTables mesh;
+  bool has_mesh = false, has_pot = false;
+  double vmax = 0, ub = 0;
+  // device tables
+  DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32;
+  // workspaces
+  DevBuf fbuf[3];      // filter recursion buffers
+  DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX;
+  std::vector<double> host_scratch = std::vector<double>(16);
+  // timing of the cell-product launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int64_t cell_vecs = 0;
+};
+
+static int fail(chfsi_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                         \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? CHFSI_ERR_OOM : CHFSI_ERR_HIP,                 \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                             \
+  } while (0)
+
+static int set_dev(chfsi_ctx *c) {
+  if (c->device < 0) return fail(c, CHFSI_ERR_STATE, "host-only context: no device work");
+  HIPCHK(c, hipSetDevice(c->device));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// lifetime
+// ---------------------------------------------------------------------------
+extern "C" int chfsi_create(chfsi_ctx **out, int device, void *hip_stream) {
+  if (!out) return CHFSI_ERR_ARG;
+  if (device != -1) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CHFSI_ERR_ARG;
+  }
+  chfsi_ctx *c = new (std::nothrow) chfsi_ctx();
+  if (!c) return CHFSI_ERR_OOM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return 0;
+}
+
+extern "C" int chfsi_destroy(chfsi_ctx *c) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (c->device < 0) {
+    delete c;
+    return 0;
+  }
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32,
+                   &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
+                   &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX};
+  for (DevBuf *b : all) b->release();
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return 0;
+}
+
+extern "C" const char *chfsi_last_error(const chfsi_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" const char *chfsi_status_string(int s) {
+  switch (s) {
+    case CHFSI_OK: return "ok";
+    case CHFSI_ERR_ARG: return "invalid argument";
+    case CHFSI_ERR_STATE: return "mesh or potential not set";
+    case CHFSI_ERR_OOM: return "device out of memory";
+    case CHFSI_ERR_HIP: return "HIP runtime error";
+    case CHFSI_ERR_NOT_SPD: return "overlap matrix not positive definite";
+    case CHFSI_ERR_NONFINITE: return "non-finite values";
+    case CHFSI_WARN_NOT_CONVERGED: return "not converged";
+    default: return "unknown status";
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setMesh / setPotential
+// ---------------------------------------------------------------------------
+extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (c->device >= 0)
+    if (int r = set_dev(c)) return r;
+  MeshTables m;
+  std::string msg = build_mesh(L, n_el, p, m);
+  if (!msg.empty()) return fail(c, CHFSI_ERR_ARG, msg);
+  if (m.np != 16 && m.np != 32 && m.np != 64 && m.np != 128 && m.np != 224 && m.np != 352 && m.np != 512)
+    return fail(c, CHFSI_ERR_ARG, "set_mesh: degree p must be in 1..7 for the device cell kernel");
+  c->has_mesh = c->has_pot = false;
+  c->mesh = std::move(m);
+  if (c->device < 0) {
+    c->has_mesh = true;
+    return 0;
+  }
+  const MeshTables &M = c->mesh;
+  const size_t nl = M.n_loc, np = M.np;
+  HIPCHK(c, c->cmap.ensure(M.cmap.size() * sizeof(int32_t)));
+  HIPCHK(c, c->cells.ensure(M.cell_order.size() * sizeof(int32_t)));
+  HIPCHK(c, c->K64.ensure(np * np * sizeof(double)));
+  HIPCHK(c, c->K32.ensure(np * np * sizeof(float)));
+  HIPCHK(c, c->minv64.ensure(M.n_dof * sizeof(double)));
+  HIPCHK(c, c->minv32.ensure(M.n_dof * sizeof(float)));
+  std::vector<double> kp(np * np, 0.0);
+  std::vector<float> kp32(np * np, 0.f);
+  for (size_t i = 0; i < nl; ++i)
+    for (size_t j = 0; j < nl; ++j) {
+      kp[i * np + j] = M.kcell[i * nl + j];
+      kp32[i * np + j] = (float)M.kcell[i * nl + j];
+    }
+  std::vector<double> mi(M.n_dof);
+  std::vector<float> mi32(M.n_dof);
+  for (int64_t i = 0; i < M.n_dof; ++i) {
+    mi[i] = 1.0 / std::sqrt(M.mass[i]);
+    mi32[i] = (float)mi[i];
+  }
+  HIPCHK(c, hipMemcpy(c->cmap.p, M.cmap.data(), M.cmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->cells.p, M.cell_order.data(), M.cell_order.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->K64.p, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->K32.p, kp32.data(), kp32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->minv64.p, mi.data(), mi.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->minv32.p, mi32.data(), mi32.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->has_mesh = true;
+  return 0;
+}
+
+extern "C" int chfsi_get_sizes(const chfsi_ctx *c, int64_t *n_dof, int64_t *n_cells, int *n_loc) {
+  if (!c || !c->has_mesh) return CHFSI_ERR_STATE;
+  if (n_dof) *n_dof = c->mesh.n_dof;
+  if (n_cells) *n_cells = c->mesh.n_cells;
+  if (n_loc) *n_loc = c->mesh.n_loc;
+  return 0;
+}
+
+extern "C" int chfsi_get_cell_dof_map(const chfsi_ctx *c, int32_t *out) {
+  if (!c || !c->has_mesh) return CHFSI_ERR_STATE;
+  if (!out) return CHFSI_ERR_ARG;
+  std::memcpy(out, c->mesh.cmap.data(), c->mesh.cmap.size() * sizeof(int32_t));
+  return 0;
+}
+
+extern "C" int chfsi_get_cell_colors(const chfsi_ctx *c, uint8_t *out) {
+  if (!c || !c->has_mesh) return CHFSI_ERR_STATE;
+  if (!out) return CHFSI_ERR_ARG;
+  std::memcpy(out, c->mesh.colors.data(), c->mesh.colors.size());
+  return 0;
+}
+
+extern "C" int chfsi_get_dof_coords(const chfsi_ctx *c, double *xyz) {
+  if (!c || !c->has_mesh) return CHFSI_ERR_STATE;
+  if (!xyz) return CHFSI_ERR_ARG;
+  dof_coords(c->mesh, xyz);
+  return 0;
+}
+
+extern "C" int chfsi_get_mass(const chfsi_ctx *c, double *m) {
+  if (!c || !c->has_mesh) return CHFSI_ERR_STATE;
+  if (!m) return CHFSI_ERR_ARG;
+  std::memcpy(m, c->mesh.mass.data(), c->mesh.mass.size() * sizeof(double));
+  return 0;
+}
+
+extern "C" int chfsi_get_cell_matrix(const chfsi_ctx *c, double *k) {
+  if (!c || !c->has_mesh) return CHFSI_ERR_STATE;
+  if (!k) return CHFSI_ERR_ARG;
+  std::memcpy(k, c->mesh.kcell.data(), c->mesh.kcell.size() * sizeof(double));
+  return 0;
+}
+
+extern "C" int chfsi_set_potential(chfsi_ctx *c, const double *v, int64_t n_dof, int v_on_device) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (!c->has_mesh) return fail(c, CHFSI_ERR_STATE, "set_potential before set_mesh");
+  if (!v || n_dof != c->mesh.n_dof) return fail(c, CHFSI_ERR_ARG, "set_potential: size mismatch or null");
+  if (c->device < 0 && v_on_device) return fail(c, CHFSI_ERR_ARG, "host-only context takes a host potential");
+  if (c->device >= 0)
+    if (int r = set_dev(c)) return r;
+  std::vector<double> hv(n_dof);
+  if (v_on_device) HIPCHK(c, hipMemcpy(hv.data(), v, n_dof * sizeof(double), hipMemcpyDeviceToHost));
+  else std::memcpy(hv.data(), v, n_dof * sizeof(double));
+  double vmax = -INFINITY;
+  for (int64_t i = 0; i < n_dof; ++i) {
+    if (!std::isfinite(hv[i])) return fail(c, CHFSI_ERR_ARG, "set_potential: non-finite value");
+    vmax = std::max(vmax, hv[i]);
+  }
+  c->vmax = vmax;
+  c->ub = 3.0 * c->mesh.lam1d_max + vmax;
+  if (c->device < 0) {
+    c->has_pot = true;
+    return 0;
+  }
+  std::vector<float> hv32(n_dof);
+  for (int64_t i = 0; i < n_dof; ++i) hv32[i] = (float)hv[i];
+  HIPCHK(c, c->V64.ensure(n_dof * sizeof(double)));
+  HIPCHK(c, c->V32.ensure(n_dof * sizeof(float)));
+  HIPCHK(c, hipMemcpy(c->V64.p, hv.data(), n_dof * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->V32.p, hv32.data(), n_dof * sizeof(float), hipMemcpyHostToDevice));
+  c->vmax = vmax;
+  c->ub = 3.0 * c->mesh.lam1d_max + vmax;
+  c->has_pot = true;
+  return 0;
+}
+
+extern "C" int chfsi_get_upper_bound(const chfsi_ctx *c, double *b) {
+  if (!c || !c->has_pot) return CHFSI_ERR_STATE;
+  if (!b) return CHFSI_ERR_ARG;
+  *b = c->ub;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+extern "C" int chfsi_set_timing(chfsi_ctx *c, int enable) {
+  if (!c) return CHFSI_ERR_ARG;
+  c->timing = enable != 0;
+  return 0;
+}
+
+extern "C" int chfsi_reset_timing(chfsi_ctx *c) {
+  if (!c) return CHFSI_ERR_ARG;
+  c->ev_used = 0;
+  c->cell_vecs = 0;
+  return 0;
+}
+
+extern "C" int chfsi_last_filter_timing(chfsi_ctx *c, double *ms_cells, int *n_launches, int64_t *cell_vecs) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (int r = set_dev(c)) return r;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double tot = 0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
+    tot += ms;
+  }
+  if (ms_cells) *ms_cells = tot;
+  if (n_launches) *n_launches = (int)(c->ev_used / 2);
+  if (cell_vecs) *cell_vecs = c->cell_vecs;
+  return 0;
+}
+
+static hipEvent_t next_event(chfsi_ctx *c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// ---------------------------------------------------------------------------
+// Htilde-based step on one column block, any working precision T
+// ---------------------------------------------------------------------------
+template <typename T>
+static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64_t ldp, T *Y, int64_t ldy,
+                       int ncols, double s1, double s2, double shift) {
+  const MeshTables &M = c->mesh;
+  const T *V = std::is_same<T, double>::value ? (const T *)c->V64.p : (const T *)c->V32.p;
+  const T *K = std::is_same<T, double>::value ? (const T *)c->K64.p : (const T *)c->K32.p;
+  const T *mi = std::is_same<T, double>::value ? (const T *)c->minv64.p : (const T *)c->minv32.p;
+  hx_diag_launch<T>(X, ldx, Xp, ldp, Y, ldy, V, M.n_dof, ncols, (T)s1, (T)s2, (T)shift, c->stream);
+  HxArgs<T> a;
+  a.X = X;
+  a.ldx = ldx;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.K = K;
+  a.cmap = c->cmap.as<int32_t>();
+  a.n_loc = M.n_loc;
+  a.np = M.np;
+  a.cells = c->cells.as<int32_t>();
+  a.minv = mi;
+  a.ncols = ncols;
+  a.s1 = (T)s1;
+  for (int col = 0; col < 8; ++col) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      e0 = next_event(c);
+      if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+    if (hx_cells_launch<T>(a, M.color_offset[col], M.color_offset[col + 1], c->stream) != 0)
+      return fail(c, CHFSI_ERR_ARG, "no cell kernel for this degree");
+    if (c->timing && e0) {
+      e1 = next_event(c);
+      if (e1) (void)hipEventRecord(e1, c->stream);
+    }
+  }
+  c->cell_vecs += (int64_t)M.n_cells * ncols;
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+static int check_block(chfsi_ctx *c, const void *X, int64_t ld, int ncols) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (c->device < 0) return fail(c, CHFSI_ERR_STATE, "host-only context: no device work");
+  if (!c->has_mesh || !c->has_pot) return fail(c, CHFSI_ERR_STATE, "mesh and potential must be set first");
+  if (!X || ncols < 1 || ld < ncols) return fail(c, CHFSI_ERR_ARG, "bad block arguments (pointer, ncols, ld)");
+  return set_dev(c);
+}
+
+extern "C" int chfsi_cheb_step(chfsi_ctx *c, const double *X, const double *Xp, double *Y, int64_t ld, int ncols,
+                               double s1, double s2, double shift) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (!Y || Y == X || (Xp && Y == Xp)) return fail(c, CHFSI_ERR_ARG, "cheb_step: Y must not alias X or Xprev");
+  return cheb_step_t<double>(c, X, ld, Xp, ld, Y, ld, ncols, s1, s2, shift);
+}
+
+// FP32 copies of a column block live in fbuf[] (ld = width)
+static int ensure_fbufs(chfsi_ctx *c, size_t elem, int width) {
+  const size_t bytes = (size_t)c->mesh.n_dof * width * elem;
+  for (int i = 0; i < 3; ++i) HIPCHK(c, c->fbuf[i].ensure(bytes));
+  return 0;
+}
+
+extern "C" int chfsi_apply(chfsi_ctx *c, const double *X, double *Y, int64_t ld, int ncols, chfsi_prec prec) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (!Y || X == Y) return fail(c, CHFSI_ERR_ARG, "apply: Y must not alias X");
+  if (prec == CHFSI_FP64) return cheb_step_t<double>(c, X, ld, nullptr, 0, Y, ld, ncols, 1.0, 0.0, 0.0);
+  if (prec != CHFSI_FP32) return fail(c, CHFSI_ERR_ARG, "apply: precision not available");
+  const int64_t nd = c->mesh.n_dof;
+  const int bw = std::min(ncols, 256);
+  if (int r = ensure_fbufs(c, sizeof(float), bw)) return r;
+  for (int j0 = 0; j0 < ncols; j0 += bw) {
+    const int w = std::min(bw, ncols - j0);
+    float *a = c->fbuf[0].as<float>(), *b = c->fbuf[1].as<float>();
+    copy_cols_launch<double, float>(X + j0, ld, a, w, nd, w, c->stream);
+    if (int r = cheb_step_t<float>(c, a, w, nullptr, 0, b, w, w, 1.0, 0.0, 0.0)) return r;
+    copy_cols_launch<float, double>(b, w, Y + j0, ld, nd, w, c->stream);
+  }
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// chebyshevFilter
+// ---------------------------------------------------------------------------
+template <typename T>
+static int filter_block(chfsi_ctx *c, T *z0, int64_t ld0, T *w1, T *w2, int64_t ldw, int ncols, int degree,
+                        double a, double b, double a0) {
+  // normalised recursion: rho_1 = 1/xi0, rho_{k+1} = 1/(2 xi0 - rho_k);
+  // Z_1 = (rho_1/e)(H - c) Z_0;  Z_{k+1} = (2 rho_{k+1}/e)(H - c) Z_k - rho_{k+1} rho_k Z_{k-1}
+  const double cc = 0.5 * (a + b), e = 0.5 * (b - a), xi0 = (a0 - cc) / e;
+  T *buf[3] = {z0, w1, w2};
+  const int64_t lds[3] = {ld0, ldw, ldw};
+  int cur = 0, prev = -1;
+  double rho = 1.0 / xi0;
+  for (int k = 0; k < degree; ++k) {
+    double s1, s2;
+    if (k == 0) {
+      s1 = rho / e;
+      s2 = 0.0;
+    } else {
+      double rn = 1.0 / (2.0 * xi0 - rho);
+      s1 = 2.0 * rn / e;
+      s2 = -rn * rho;
+      rho = rn;
+    }
+    int out = 0;
+    while (out == cur || out == prev) ++out;
+    if (int r = cheb_step_t<T>(c, buf[cur], lds[cur], prev >= 0 ? buf[prev] : nullptr, prev >= 0 ? lds[prev] : 0,
+                               buf[out], lds[out], ncols, s1, s2, cc))
+      return r;
+    prev = cur;
+    cur = out;
+  }
+  if (cur != 0) copy_cols_launch<T, T>(buf[cur], lds[cur], z0, ld0, c->mesh.n_dof, ncols, c->stream);
+  return 0;
+}
+
+extern "C" int chfsi_chebyshev_filter(chfsi_ctx *c, double *X, int64_t ld, int ncols, int degree, double a,
+                                      double b, double a0, chfsi_prec prec, int block_width) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (degree < 0 || !(a0 < a) || !(a < b)) return fail(c, CHFSI_ERR_ARG, "filter: need a0 < a < b, degree >= 0");
+  if (prec != CHFSI_FP64 && prec != CHFSI_FP32) return fail(c, CHFSI_ERR_ARG, "filter: precision not available");
+  if (degree == 0) return 0;
+  const int64_t nd = c->mesh.n_dof;
+  int bw = block_width > 0 ? block_width : 128;
+  bw = std::min(bw, ncols);
+  if (prec == CHFSI_FP64) {
+    if (int r = ensure_fbufs(c, sizeof(double), bw)) return r;
+    for (int j0 = 0; j0 < ncols; j0 += bw) {
+      const int w = std::min(bw, ncols - j0);
+      if (int r = filter_block<double>(c, X + j0, ld, c->fbuf[1].as<double>(), c->fbuf[2].as<double>(), w, w,
+                                       degree, a, b, a0))
+        return r;
+    }
+  } else {
+    if (int r = ensure_fbufs(c, sizeof(float), bw)) return r;
+    for (int j0 = 0; j0 < ncols; j0 += bw) {
+      const int w = std::min(bw, ncols - j0);
+      float *f0 = c->fbuf[0].as<float>();
+      copy_cols_launch<double, float>(X + j0, ld, f0, w, nd, w, c->stream);
+      if (int r = filter_block<float>(c, f0, w, c->fbuf[1].as<float>(), c->fbuf[2].as<float>(), w, w, degree, a,
+                                      b, a0))
+        return r;
+      copy_cols_launch<float, double>(f0, w, X + j0, ld, nd, w, c->stream);
+    }
+  }
+  HIPCHK(c, c->flag.ensure(4 * sizeof(int)));
+  zero_int_launch(c->flag.as<int>(), 1, c->stream);
+  nonfinite_launch<double>(X, ld, nd, ncols, c->flag.as<int>(), c->stream);
+  int hflag = 0;
+  HIPCHK(c, hipMemcpyAsync(&hflag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (hflag) return fail(c, CHFSI_ERR_NONFINITE, "filter produced NaN/Inf (upper bound below lambda_max?)");
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// orthonormalize (CholGS)
+// ---------------------------------------------------------------------------
+static int ensure_small(chfsi_ctx *c, int n) {
+  const size_t nn = (size_t)n * n;
+  const int nb = (n + 31) / 32;
+  HIPCHK(c, c->Smat.ensure(nn * sizeof(double)));
+  HIPCHK(c, c->dinv.ensure((size_t)nb * 32 * 32 * sizeof(double)));
+  HIPCHK(c, c->Zmat.ensure(nn * sizeof(double)));
+  HIPCHK(c, c->Wmat.ensure(nn * sizeof(double)));
+  HIPCHK(c, c->jac_work.ensure(jacobi_work_elems(n) * sizeof(double)));
+  HIPCHK(c, c->evals_d.ensure((size_t)n * sizeof(double)));
+  HIPCHK(c, c->resid_d.ensure((size_t)n * sizeof(double)));
+  HIPCHK(c, c->flag.ensure(4 * sizeof(int)));
+  HIPCHK(c, c->gram_part.ensure(gram_part_elems(c->mesh.n_dof, n) * sizeof(double)));
+  HIPCHK(c, c->resid_part.ensure((size_t)resid_nchunk(c->mesh.n_dof) * n * sizeof(double)));
+  return 0;
+}
+
+extern "C" int chfsi_orthonormalize(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (int r = ensure_small(c, ncols)) return r;
+  const int64_t nd = c->mesh.n_dof;
+  double *S = c->Smat.as<double>();
+  gram_launch(X, ld, X, ld, nd, ncols, c->gram_part.as<double>(), S, mixed ? 1 : 0, c->stream);
+  zero_int_launch(c->flag.as<int>(), 1, c->stream);
+  potrf_launch(S, ncols, c->dinv.as<double>(), c->flag.as<int>(), c->stream);
+  int hflag = 0;
+  HIPCHK(c, hipMemcpyAsync(&hflag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (hflag) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "CholGS: overlap not positive definite (pivot %d)", hflag - 1);
+    return fail(c, CHFSI_ERR_NOT_SPD, msg);
+  }
+  trtri_t_launch(S, c->dinv.as<double>(), ncols, c->Zmat.as<double>(), c->Wmat.as<double>(), c->stream);
+  if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->stream) != 0)
+    return fail(c, CHFSI_ERR_ARG, "orthonormalize: block too wide for the row-panel kernel");
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// rayleighRitz
+// ---------------------------------------------------------------------------
+static int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
+                   double *resid, int *sweeps) {
+  const int64_t nd = c->mesh.n_dof;
+  if (int r = cheb_step_t<double>(c, X, ld, nullptr, 0, HX, ldh, ncols, 1.0, 0.0, 0.0)) return r;
+  double *G = c->Smat.as<double>();
+  gram_launch(X, ld, HX, ldh, nd, ncols, c->gram_part.as<double>(), G, 0, c->stream);
+  double *Q = c->Wmat.as<double>();
+  if (jacobi_eigh(G, ncols, c->jac_work.as<double>(), c->evals_d.as<double>(), Q, 1e-14, 40,
+                  c->host_scratch.data(), c->stream, sweeps) != 0)
+    return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
+  if (rmul_launch(X, ld, nd, ncols, Q, 0, 0, c->stream) != 0 ||
+      rmul_launch(HX, ldh, nd, ncols, Q, 0, 0, c->stream) != 0)
+    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
+  resid_launch(X, ld, HX, ldh, c->evals_d.as<double>(), nd, ncols, c->resid_part.as<double>(),
+               c->resid_d.as<double>(), c->stream);
+  HIPCHK(c, hipMemcpyAsync(evals, c->evals_d.p, ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(resid, c->resid_d.p, ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+extern "C" int chfsi_rayleigh_ritz(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *evals, double *resid,
+                                   double *HX_out) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (!evals || !resid) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: evals/resid must be host arrays");
+  if (int r = ensure_small(c, ncols)) return r;
+  double *HX = HX_out;
+  int64_t ldh = ld;
+  if (!HX) {
+    HIPCHK(c, c->HX.ensure((size_t)c->mesh.n_dof * ncols * sizeof(double)));
+    HX = c->HX.as<double>();
+    ldh = ncols;
+  }
+  if (HX == X) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: HX_out must not alias X");
+  return rr_impl(c, X, ld, ncols, HX, ldh, evals, resid, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+static double elapsed_s(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0;
+  return ms * 1e-3;
+}
+
+extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t ld, double *evals, double *resid,
+                           chfsi_report *rep) {
+  if (!o) return fail(c, CHFSI_ERR_ARG, "solve: null options");
+  const int nb = o->nblock;
+  if (int r = check_block(c, X, ld, nb)) return r;
+  if (o->nstates < 1 || o->nstates > nb || o->degree < 1 || o->max_iter < 0 || !(o->tol > 0) || !evals || !resid)
+    return fail(c, CHFSI_ERR_ARG, "solve: invalid options");
+  if (nb > c->mesh.n_dof) return fail(c, CHFSI_ERR_ARG, "solve: more vectors than degrees of freedom");
+  if (int r = ensure_small(c, nb)) return r;
+  HIPCHK(c, c->HX.ensure((size_t)c->mesh.n_dof * nb * sizeof(double)));
+  double *HX = c->HX.as<double>();
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) HIPCHK(c, hipEventCreate(&ev[i]));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  chfsi_report R;
+  std::memset(&R, 0, sizeof R);
+  const int nrung = std::max(1, std::min(o->n_ladder, 4));
+  auto rung_prec = [&](int rg) { return o->n_ladder > 0 ? o->ladder[rg] : CHFSI_FP64; };
+  int rung = 0;
+  const int mixed = o->mixed_cholgs ? 1 : 0;
+  // start: CholGS + RR on the given block
+  HIPCHK(c, hipEventRecord(ev[0], c->stream));
+  int st = chfsi_orthonormalize(c, X, ld, nb, mixed);
+  if (st) return st;
+  HIPCHK(c, hipEventRecord(ev[1], c->stream));
+  if (int r = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr)) return r;
+  HIPCHK(c, hipEventRecord(ev[2], c->stream));
+  HIPCHK(c, hipEventSynchronize(ev[2]));
+  R.t_cholgs += elapsed_s(ev[0], ev[1]);
+  R.t_rr += elapsed_s(ev[1], ev[2]);
+  R.dofvecs += c->mesh.n_dof * (int64_t)nb;
+  auto maxres = [&]() {
+    double m = 0;
+    for (int i = 0; i < o->nstates; ++i) m = std::max(m, resid[i]);
+    return m;
+  };
+  double res = maxres();
+  int it = 0;
+  while (res > o->tol && it < o->max_iter) {
+    const double a = evals[nb - 1], a0 = evals[0], b = c->ub;
+    if (!(a0 < a && a < b)) return fail(c, CHFSI_ERR_NONFINITE, "solve: Ritz values outside the filter bounds");
+    HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    st = chfsi_chebyshev_filter(c, X, ld, nb, o->degree, a, b, a0, rung_prec(rung), o->block_width);
+    if (st) return st;
+    HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    st = chfsi_orthonormalize(c, X, ld, nb, mixed);
+    if (st) return st;
+    HIPCHK(c, hipEventRecord(ev[5], c->stream));
+    if (int r = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr)) return r;
+    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev[0]));
+    R.t_filter += elapsed_s(ev[3], ev[4]);
+    R.t_cholgs += elapsed_s(ev[4], ev[5]);
+    R.t_rr += elapsed_s(ev[5], ev[0]);
+    R.dofvecs += c->mesh.n_dof * (int64_t)nb * (o->degree + 1);
+    ++it;
+    const double nres = maxres();
+    if (o->n_ladder > 1 && rung + 1 < nrung) {
+      const bool stalled = nres > 0.5 * res;
+      const bool below = o->ladder_switch > 0 && nres < o->ladder_switch;
+      if (stalled || below) ++rung;
+    }
+    res = nres;
+  }
+  R.iters = it;
+  R.rung = rung;
+  R.max_resid = res;
+  R.status = res <= o->tol ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
+  if (rep) *rep = R;
+  return R.status;
+}
+
+// ---------------------------------------------------------------------------
+// footprint
+// ---------------------------------------------------------------------------
+extern "C" size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_width, chfsi_prec prec) {
+  if (n_el < 1 || p < 1 || p > 7 || nblock < 1) return 0;
+  const size_t n = (size_t)n_el * p - 1, nd = n * n * n, ncell = (size_t)n_el * n_el * n_el;
+  const size_t nl = (size_t)(p + 1) * (p + 1) * (p + 1), np = (nl + 15) / 16 * 16;
+  const size_t bw = (size_t)std::min(block_width > 0 ? block_width : 128, nblock);
+  const size_t elem = prec == CHFSI_FP64 ? 8 : 4;
+  size_t b = ncell * nl * 4 + ncell * 4 + np * np * 12 + nd * 24;  // tables, K, minv, V
+  b += 3 * nd * bw * elem;                                         // filter buffers
+  b += nd * nblock * 8;                                            // HX
+  const size_t nn = (size_t)nblock * nblock;
+  b += 4 * nn * 8 + jacobi_work_elems(nblock) * 8;                 // S, Z, W, jacobi
+  b += gram_part_elems((int64_t)nd, nblock) * 8;
+  b += (size_t)resid_nchunk((int64_t)nd) * nblock * 8;
+  return b;
+}

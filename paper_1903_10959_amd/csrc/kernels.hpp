@@ -1,0 +1,70 @@
+// Host-side launchers of the device kernels (internal interface of the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace chfsi {
+
+// ---- Chebyshev step (hx.hip) ----------------------------------------------
+template <typename T>
+struct HxArgs {
+  const T *X;          // input block, [n_dof x ldx]
+  int64_t ldx;
+  T *Y;                // output block (already holding the element-wise part)
+  int64_t ldy;
+  const T *K;          // padded cell stiffness [np x np]
+  const int32_t *cmap; // [n_cells x n_loc]
+  int n_loc, np;
+  const int32_t *cells;  // cell ids sorted by colour
+  const T *minv;       // M^-1/2 [n_dof]
+  int ncols;
+  T s1;                // scale of the cell part
+};
+template <typename T>
+int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s);
+template <typename T>
+void hx_diag_launch(const T *X, int64_t ldx, const T *Xp, int64_t ldp, T *Y, int64_t ldy, const T *V,
+                    int64_t n_dof, int ncols, T s1, T s2, T shift, hipStream_t s);
+template <typename Tin, typename Tout>
+void copy_cols_launch(const Tin *in, int64_t ldi, Tout *out, int64_t ldo, int64_t nrows, int ncols,
+                      hipStream_t s);
+template <typename T>
+void nonfinite_launch(const T *X, int64_t ld, int64_t nrows, int ncols, int *flag, hipStream_t s);
+
+// ---- tall-skinny products (dense.hip) ---------------------------------------
+// G = A^T B over nrows rows, lower-triangular 128x128 tiles, split over rows;
+// partial tiles go to `part` ([nsplit x ntiles x 128 x 128]) and are summed in
+// a fixed order into G (n x n, row-major, lower triangle mirrored to upper).
+// mixed: 64x64 diagonal blocks in FP64, the rest with FP32 inputs/products.
+int gram_nsplit(int64_t nrows, int n);
+size_t gram_part_elems(int64_t nrows, int n);
+void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
+                 double *G, int mixed, hipStream_t s);
+// X[r, 0:n] <- X[r, 0:n] W for all rows (in place, row panels staged in LDS).
+// W: n x n row-major.  upper: W upper triangular (skip zero blocks).
+// mixed (requires upper): 64x64 diagonal blocks of W in FP64, the rest FP32.
+int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
+                hipStream_t s);
+// resid[j] = || HX[:,j] - lam[j] X[:,j] ||_2 ; part: [nchunk x n]
+int resid_nchunk(int64_t nrows);
+void resid_launch(const double *X, int64_t ldx, const double *HX, int64_t ldh, const double *lam, int64_t nrows,
+                  int n, double *part, double *resid, hipStream_t s);
+
+// ---- small dense FP64 kernels (small.hip) ---------------------------------
+// In-place blocked Cholesky of the lower triangle of S (n x n row-major):
+// S = L L^T; dinv receives the inverses of the 32x32 diagonal blocks of L;
+// *flag = first failing block + 1 (0 if positive definite).
+void potrf_launch(double *S, int n, double *dinv, int *flag, hipStream_t s);
+// W = L^-T (upper triangular, n x n row-major) from L and dinv; Z scratch n x n.
+void trtri_t_launch(const double *L, const double *dinv, int n, double *Z, double *W, hipStream_t s);
+// Symmetric eigensolver (cyclic Jacobi, round-robin pairs, one launch per round).
+// A: n x n symmetric (row-major, full), destroyed; work: see jacobi_work_elems.
+// On exit: evals ascending (device, n), Q (n x n row-major, columns = vectors).
+size_t jacobi_work_elems(int n);
+int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
+                double *host_scratch, hipStream_t s, int *sweeps_done);
+// Zero the strictly upper triangle, helpers.
+void fill_launch(double *X, int64_t n, double v, hipStream_t s);
+void zero_int_launch(int *p, int n, hipStream_t s);
+
+}  // namespace chfsi

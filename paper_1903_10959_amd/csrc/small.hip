@@ -1,0 +1,401 @@
+// Small dense FP64 kernels on N_b x N_b matrices (N_b up to a few thousand).
+//
+//  * potrf: blocked right-looking Cholesky S = L L^T (Sec. 3.4 Alg. 3 step 2;
+//    the paper uses ScaLAPACK pXpotrf).  32x32 diagonal blocks are factored
+//    in LDS by one work-group, which also inverts them for the panel solve.
+//  * trtri_t: W = L^-T (Alg. 3 step 3; the paper uses pXtrtri), block row by
+//    block row from the diagonal-block inverses.
+//  * jacobi: symmetric eigensolver for the projected Hamiltonian (Sec. 3.5
+//    step ii).  Cyclic Jacobi in round-robin (parallel) order: each round
+//    rotates n/2 disjoint (p,q) planes at once; the 2x2 block of every pair
+//    of planes is updated by one thread from the previous round's matrix
+//    (double buffered), so a round is one launch with no atomics.
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <cmath>
+#include <utility>
+#include <vector>
+
+namespace chfsi {
+
+static constexpr int NB = 32;
+
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double *S, int n, int k0, double *dinv, int *flag) {
+  __shared__ double a[NB][NB + 1];
+  __shared__ double z[NB][NB + 1];
+  const int kw = min(NB, n - k0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+    int i = idx / NB, jj = idx % NB;
+    a[i][jj] = (i < kw && jj < kw && jj <= i) ? S[(int64_t)(k0 + i) * n + k0 + jj] : 0.0;
+    z[i][jj] = 0.0;
+  }
+  __syncthreads();
+  for (int jj = 0; jj < kw; ++jj) {
+    double d = a[jj][jj];
+    __syncthreads();
+    double ljj = sqrt(d);
+    if (!(d > 0.0) || !(ljj - ljj == 0.0)) {
+      if (tid == 0 && *flag == 0) *flag = k0 + jj + 1;
+      ljj = __builtin_nan("");
+    }
+    if (tid == 0) a[jj][jj] = ljj;
+    for (int i = jj + 1 + tid; i < kw; i += blockDim.x) a[i][jj] /= ljj;
+    __syncthreads();
+    const int m = kw - jj - 1;  // trailing size
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      int i = jj + 1 + idx / m, k = jj + 1 + idx % m;
+      if (k <= i) a[i][k] -= a[i][jj] * a[k][jj];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular diagonal block, one column per thread
+  if (tid < kw) {
+    const int c = tid;
+    z[c][c] = 1.0 / a[c][c];
+    for (int i = c + 1; i < kw; ++i) {
+      double s = 0;
+      for (int m = c; m < i; ++m) s += a[i][m] * z[m][c];
+      z[i][c] = -s / a[i][i];
+    }
+  }
+  __syncthreads();
+  double *dz = dinv + (int64_t)(k0 / NB) * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+    int i = idx / NB, jj = idx % NB;
+    if (i < kw && jj < kw && jj <= i) S[(int64_t)(k0 + i) * n + k0 + jj] = a[i][jj];
+    dz[idx] = (i < kw && jj < kw) ? z[i][jj] : 0.0;
+  }
+}
+
+// L[i, k0:k0+kw] = S[i, k0:k0+kw] Z^T for rows i >= k0+kw (Z = inverse diagonal block)
+__global__ __launch_bounds__(256) void potrf_panel_kernel(double *S, int n, int k0, const double *dinv) {
+  __shared__ double z[NB][NB + 1];
+  __shared__ double rows[64][NB + 1];
+  const int kw = min(NB, n - k0);
+  const int r0 = k0 + kw + blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  const double *dz = dinv + (int64_t)(k0 / NB) * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) z[idx / NB][idx % NB] = dz[idx];
+  for (int idx = tid; idx < 64 * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    int i = r0 + r;
+    rows[r][c] = (i < n && c < kw) ? S[(int64_t)i * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int r = tid >> 2;
+  const int cbeg = (tid & 3) * 8;
+  const int i = r0 + r;
+  if (i >= n) return;
+  for (int c = cbeg; c < cbeg + 8 && c < kw; ++c) {
+    double s = 0;
+    for (int t = 0; t <= c; ++t) s += rows[r][t] * z[c][t];
+    S[(int64_t)i * n + k0 + c] = s;
+  }
+}
+
+// S[i][j] -= sum_t L[i][k0+t] L[j][k0+t] on the trailing lower triangle
+__global__ __launch_bounds__(256) void potrf_update_kernel(double *S, int n, int k0) {
+  __shared__ double li[NB][NB + 1];
+  __shared__ double lj[NB][NB + 1];
+  const int kw = min(NB, n - k0);
+  const int k1 = k0 + kw;
+  int t = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int i0 = k1 + ti * NB, j0 = k1 + tj * NB;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    li[r][c] = (i0 + r < n && c < kw) ? S[(int64_t)(i0 + r) * n + k0 + c] : 0.0;
+    lj[r][c] = (j0 + r < n && c < kw) ? S[(int64_t)(j0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    int i = i0 + r, jj = j0 + c;
+    if (i >= n || jj >= n || jj > i) continue;
+    double s = 0;
+    for (int q = 0; q < kw; ++q) s += li[r][q] * lj[c][q];
+    S[(int64_t)i * n + jj] -= s;
+  }
+}
+
+void potrf_launch(double *S, int n, double *dinv, int *flag, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, S, n, k0, dinv, flag);
+    const int k1 = k0 + NB;
+    if (k1 >= n) break;
+    const int rest = n - k1;
+    hipLaunchKernelGGL(potrf_panel_kernel, dim3((rest + 63) / 64), dim3(256), 0, s, S, n, k0, dinv);
+    const int nt = (rest + NB - 1) / NB;
+    hipLaunchKernelGGL(potrf_update_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, S, n, k0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// W = L^-T.  Z = L^-1 is lower triangular with Z_ii = dinv_i and, for ib > jb,
+// Z_{ib,jb} = -dinv_ib * sum_{kb=jb}^{ib-1} L_{ib,kb} Z_{kb,jb}.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void trtri_init_kernel(const double *dinv, int n, double *Z) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx / n), jj = (int)(idx % n);
+    double v = 0;
+    if (i / NB == jj / NB) v = dinv[(int64_t)(i / NB) * NB * NB + (i % NB) * NB + (jj % NB)];
+    Z[idx] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void trtri_row_kernel(const double *L, const double *dinv, int n, int ib,
+                                                        double *Z) {
+  __shared__ double lb[NB][NB + 1];
+  __shared__ double zb[NB][NB + 1];
+  __shared__ double tb[NB][NB + 1];
+  const int jb = blockIdx.x;  // < ib
+  const int tid = threadIdx.x;
+  double acc[4] = {0, 0, 0, 0};
+  for (int kb = jb; kb < ib; ++kb) {
+    for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+      int r = idx / NB, c = idx % NB;
+      int i = ib * NB + r, k = kb * NB + c;
+      lb[r][c] = (i < n && k < n) ? L[(int64_t)i * n + k] : 0.0;
+      int kk = kb * NB + r, jj = jb * NB + c;
+      zb[r][c] = (kk < n && jj < n) ? Z[(int64_t)kk * n + jj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int idx = tid + u * 256;
+      int r = idx / NB, c = idx % NB;
+      double s = 0;
+      for (int q = 0; q < NB; ++q) s += lb[r][q] * zb[q][c];
+      acc[u] += s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int idx = tid + u * 256;
+    tb[idx / NB][idx % NB] = acc[u];
+  }
+  const double *di = dinv + (int64_t)ib * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) lb[idx / NB][idx % NB] = di[idx];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int idx = tid + u * 256;
+    int r = idx / NB, c = idx % NB;
+    double s = 0;
+    for (int q = 0; q < NB; ++q) s += lb[r][q] * tb[q][c];
+    int i = ib * NB + r, jj = jb * NB + c;
+    if (i < n && jj < n) Z[(int64_t)i * n + jj] = -s;
+  }
+}
+
+__global__ __launch_bounds__(256) void transpose_kernel(const double *Z, int n, double *W) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx / n), jj = (int)(idx % n);
+    W[idx] = Z[(int64_t)jj * n + i];
+  }
+}
+
+static unsigned grid_for(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 16384) b = 16384;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+void trtri_t_launch(const double *L, const double *dinv, int n, double *Z, double *W, hipStream_t s) {
+  const int nb = (n + NB - 1) / NB;
+  hipLaunchKernelGGL(trtri_init_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, dinv, n, Z);
+  for (int ib = 1; ib < nb; ++ib)
+    hipLaunchKernelGGL(trtri_row_kernel, dim3(ib), dim3(256), 0, s, L, dinv, n, ib, Z);
+  hipLaunchKernelGGL(transpose_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, Z, n, W);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi eigensolver
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rr_index(int pos, int r, int np) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1);
+}
+
+// Rotation (c, s) that zeroes A_pq: J = [[c, s], [-s, c]] on the (p, q) plane.
+__device__ __forceinline__ void jrot(const double *A, int n, int p, int q, double &c, double &s, double &t) {
+  c = 1.0;
+  s = 0.0;
+  t = 0.0;
+  if (p >= n || q >= n) return;
+  const double apq = A[(int64_t)p * n + q];
+  if (fabs(apq) < 1e-300) return;
+  const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q];
+  const double tau = (aqq - app) / (2.0 * apq);
+  t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const double *__restrict__ A, double *__restrict__ An,
+                                                           const double *__restrict__ V, double *__restrict__ Vn,
+                                                           int n, int np, int r) {
+  const int P = np / 2;
+  const int64_t nA = (int64_t)P * P;
+  const int64_t total = nA + (int64_t)n * P;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (t < nA) {
+      const int I = (int)(t / P), J = (int)(t % P);
+      const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
+      const int pJ = rr_index(J, r, np), qJ = rr_index(np - 1 - J, r, np);
+      double cI, sI, tI, cJ, sJ, tJ;
+      jrot(A, n, pI, qI, cI, sI, tI);
+      jrot(A, n, pJ, qJ, cJ, sJ, tJ);
+      if (I == J) {
+        if (pI >= n || qI >= n) {
+          if (pI < n) An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI];
+          if (qI < n) An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI];
+          continue;
+        }
+        const double apq = A[(int64_t)pI * n + qI];
+        An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI] - tI * apq;
+        An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI] + tI * apq;
+        An[(int64_t)pI * n + qI] = 0.0;
+        An[(int64_t)qI * n + pI] = 0.0;
+        continue;
+      }
+      const bool pIo = pI < n, qIo = qI < n, pJo = pJ < n, qJo = qJ < n;
+      const double b00 = (pIo && pJo) ? A[(int64_t)pI * n + pJ] : 0.0;
+      const double b01 = (pIo && qJo) ? A[(int64_t)pI * n + qJ] : 0.0;
+      const double b10 = (qIo && pJo) ? A[(int64_t)qI * n + pJ] : 0.0;
+      const double b11 = (qIo && qJo) ? A[(int64_t)qI * n + qJ] : 0.0;
+      // rows: R_I^T B
+      const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
+      const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
+      // columns: (R_I^T B) R_J
+      if (pIo && pJo) An[(int64_t)pI * n + pJ] = cJ * r00 - sJ * r01;
+      if (pIo && qJo) An[(int64_t)pI * n + qJ] = sJ * r00 + cJ * r01;
+      if (qIo && pJo) An[(int64_t)qI * n + pJ] = cJ * r10 - sJ * r11;
+      if (qIo && qJo) An[(int64_t)qI * n + qJ] = sJ * r10 + cJ * r11;
+    } else {
+      const int64_t u = t - nA;
+      const int row = (int)(u / P), I = (int)(u % P);
+      const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
+      double c, s, tt;
+      jrot(A, n, pI, qI, c, s, tt);
+      const double vp = pI < n ? V[(int64_t)row * n + pI] : 0.0;
+      const double vq = qI < n ? V[(int64_t)row * n + qI] : 0.0;
+      if (pI < n) Vn[(int64_t)row * n + pI] = c * vp - s * vq;
+      if (qI < n) Vn[(int64_t)row * n + qI] = s * vp + c * vq;
+    }
+  }
+}
+
+// out[0] = sum of squares off the diagonal, out[1] = on the diagonal
+__global__ __launch_bounds__(1024) void offnorm_kernel(const double *A, int n, double *out) {
+  __shared__ double so[1024], sd[1024];
+  double o = 0, d = 0;
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int i = (int)(idx / n), jj = (int)(idx % n);
+    double v = A[idx];
+    if (i == jj) d += v * v;
+    else o += v * v;
+  }
+  so[threadIdx.x] = o;
+  sd[threadIdx.x] = d;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      so[threadIdx.x] += so[threadIdx.x + w];
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = so[0];
+    out[1] = sd[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void eye_kernel(double *V, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+}
+
+// evals ascending; Q[:, rank(i)] = V[:, i]; ties broken by index
+__global__ __launch_bounds__(256) void jacobi_sort_kernel(const double *A, const double *V, int n, double *evals,
+                                                          double *Q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double di = A[(int64_t)i * n + i];
+  int rank = 0;
+  for (int k = 0; k < n; ++k) {
+    double dk = A[(int64_t)k * n + k];
+    if (dk < di || (dk == di && k < i)) ++rank;
+  }
+  evals[rank] = di;
+  for (int row = 0; row < n; ++row) Q[(int64_t)row * n + rank] = V[(int64_t)row * n + i];
+}
+
+size_t jacobi_work_elems(int n) { return (size_t)3 * n * n + 8; }
+
+int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
+                double *host_scratch, hipStream_t s, int *sweeps_done) {
+  const int np = n + (n & 1);
+  double *A1 = work;
+  double *V0 = work + (size_t)n * n;
+  double *V1 = work + (size_t)2 * n * n;
+  double *nrm = work + (size_t)3 * n * n;
+  double *a_cur = A, *a_nxt = A1, *v_cur = V0, *v_nxt = V1;
+  hipLaunchKernelGGL(eye_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, v_cur, n);
+  const int P = np / 2;
+  const int64_t total = (int64_t)P * P + (int64_t)n * P;
+  const unsigned grid = grid_for(total);
+  int sweep = 0;
+  double prev_off = -1;
+  for (; sweep < max_sweeps && n > 1; ++sweep) {
+    hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(1024), 0, s, a_cur, n, nrm);
+    if (hipMemcpyAsync(host_scratch, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    const double off = host_scratch[0], tot = host_scratch[0] + host_scratch[1];
+    if (off <= tol * tol * tot) break;
+    if (prev_off >= 0 && off >= prev_off && off <= 1e-20 * tot) break;  // stagnated at rounding level
+    prev_off = off;
+    for (int r = 0; r < np - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(grid), dim3(256), 0, s, a_cur, a_nxt, v_cur, v_nxt, n, np, r);
+      std::swap(a_cur, a_nxt);
+      std::swap(v_cur, v_nxt);
+    }
+  }
+  if (sweeps_done) *sweeps_done = sweep;
+  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a_cur, v_cur, n, evals, Q);
+  return 0;
+}
+
+__global__ void fill_kernel(double *X, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    X[i] = v;
+}
+void fill_launch(double *X, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, X, n, v);
+}
+
+__global__ void zero_int_kernel(int *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+void zero_int_launch(int *p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+}
+
+}  // namespace chfsi

@@ -1,0 +1,105 @@
+"""GPU parity of the operator and the Chebyshev step against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import chfsi as och
+from oracle import fem
+import workload
+from gpu_util import make_ctx, oracle_apply, tensor_eigvecs, to_gpu, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("n_el,p,ncols,ld", [
+    (4, 4, 24, 24),      # small workload, one 64-column tile, partially used
+    (4, 4, 1, 1),
+    (3, 5, 65, 72),      # ragged second column tile, ld > ncols
+    (2, 6, 130, 130),    # three tiles, last ragged
+    (2, 7, 17, 20),      # p = 7 (two accumulator passes)
+    (5, 3, 64, 64),
+    (3, 2, 33, 40),
+    (4, 1, 9, 9),
+])
+def test_apply_fp64_matches_oracle(n_el, p, ncols, ld):
+    L = 2.5 * n_el
+    wells = workload.draw_wells(4, L, 11 + p, (1.0, 3.0), (0.5, 1.0))
+    c, V = make_ctx(L, n_el, p, wells=wells)
+    X = workload.start_block(c.n_dof, ncols, 1000 + p)
+    Xg = to_gpu(X, ld)
+    Yg = c.apply(Xg)
+    Y = to_host(Yg)
+    Yo = oracle_apply(L, n_el, p, V)(X)
+    assert _rel(Y, Yo) < 1e-13, _rel(Y, Yo)
+    c.close()
+
+
+def test_apply_fp32_close_to_oracle():
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block(c.n_dof, 40, 7)
+    Y = to_host(c.apply(to_gpu(X), prec="fp32"))
+    Yo = oracle_apply(prob.L, prob.n_el, prob.p, V)(X)
+    assert _rel(Y, Yo) < 2e-6, _rel(Y, Yo)
+    c.close()
+
+
+def test_cheb_step_matches_formula():
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block(c.n_dof, 24, 8)
+    Xp = workload.start_block(c.n_dof, 24, 9)
+    Xg, Xpg = to_gpu(X), to_gpu(Xp)
+    Yg = to_gpu(np.zeros_like(X))
+    s1, s2, sh = 0.037, -0.81, 12.5
+    c.cheb_step(Xg, Xpg, Yg, s1, s2, sh)
+    ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
+    Yo = s1 * (ap(X) - sh * X) + s2 * Xp
+    assert _rel(to_host(Yg), Yo) < 1e-13
+    c.close()
+
+
+def test_exact_eigenvectors_at_large_p6_shape():
+    """Htilde x = lambda x for tensor-product eigenvectors (V = 0) at the
+    24^3-cell, degree-6 shape (2,924,207 DoFs)."""
+    prob = workload.PROBLEMS["large_p6"]
+    X, lam, a = tensor_eigvecs(prob.L, prob.n_el, prob.p, [(0, 0, 0), (1, 2, 3), (7, 0, 5), (140, 141, 142)])
+    c, _ = make_ctx(prob.L, prob.n_el, prob.p, V=np.zeros(prob.n_dof))
+    Y = to_host(c.apply(to_gpu(X)))
+    lam_max = 3 * a[-1]
+    err = np.max(np.abs(Y - X * lam[None, :]))
+    assert err < 1e-13 * lam_max, err
+    c.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_filter_scales_exact_eigenvectors(prec, tol):
+    """Filter(x) = T_m(xi)/T_m(xi0) x for exact eigenvectors (eq. chebFilter)."""
+    L, n_el, p = 12.0, 4, 5
+    X, lam, a = tensor_eigvecs(L, n_el, p, [(0, 0, 0), (1, 0, 0), (2, 2, 1), (4, 3, 3), (9, 1, 0), (18, 18, 18)])
+    c, _ = make_ctx(L, n_el, p, V=np.zeros((n_el * p - 1) ** 3))
+    b = c.upper_bound
+    a_lo, a0, m = lam[2] + 0.05, lam[0], 20
+    Xg = to_gpu(X)
+    c.chebyshev_filter(Xg, m, a_lo, b, a0, prec=prec, block_width=4)
+    cc, e = 0.5 * (a_lo + b), 0.5 * (b - a_lo)
+    scale = och.cheb_T(m, (lam - cc) / e) / och.cheb_T(m, np.array([(a0 - cc) / e]))[0]
+    got = to_host(Xg)
+    assert np.max(np.abs(got - X * scale[None, :])) < tol * np.max(np.abs(scale))
+    c.close()
+
+
+def test_filter_matches_oracle_small_workload():
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block(c.n_dof, prob.nblock, prob.x0_seed)
+    b = c.upper_bound
+    a, a0 = 1.5, -1.8
+    Xg = to_gpu(X)
+    c.chebyshev_filter(Xg, prob.degree, a, b, a0, block_width=16)  # two blocks, second ragged
+    Zo = och.cheb_filter_scaled(oracle_apply(prob.L, prob.n_el, prob.p, V), X, prob.degree, a, b, a0)
+    assert _rel(to_host(Xg), Zo) < 1e-11
+    c.close()

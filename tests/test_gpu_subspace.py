@@ -1,0 +1,133 @@
+"""GPU parity of CholGS, Rayleigh-Ritz and the full solve against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import chfsi as och
+from oracle import fem
+import workload
+from gpu_util import make_ctx, oracle_apply, tensor_eigvecs, to_gpu, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ncols,ld,scale_decades", [(24, 24, 3), (40, 48, 2), (130, 130, 1), (200, 200, 1)])
+def test_orthonormalize_matches_householder(ncols, ld, scale_decades):
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    rng = np.random.default_rng(ncols)
+    X = rng.standard_normal((c.n_dof, ncols)) @ np.diag(np.logspace(0, scale_decades, ncols))
+    Xg = to_gpu(X, ld)
+    c.orthonormalize(Xg)
+    Xo = to_host(Xg)
+    Q, R = np.linalg.qr(X)
+    Q = Q * np.sign(np.diag(R))[None, :]
+    kappa = np.linalg.cond(X)
+    assert np.max(np.abs(Xo - Q)) < 1e-13 * kappa ** 2
+    assert np.max(np.abs(Xo.T @ Xo - np.eye(ncols))) < 1e-13 * kappa ** 2
+    np.testing.assert_allclose(Xo, och.cholgs(X), rtol=0, atol=1e-13 * kappa ** 2)
+    c.close()
+
+
+def test_orthonormalize_mixed_matches_oracle_mixed():
+    """Mixed CholGS (eq. overlapmixedprec): parity unpinned by the paper;
+    compared with the oracle's mixed variant and with the FP64 result."""
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block(c.n_dof, 150, 77)
+    Xg = to_gpu(X)
+    c.orthonormalize(Xg, mixed=True)
+    Xm = to_host(Xg)
+    assert np.max(np.abs(Xm.T @ Xm - np.eye(150))) < 5e-6
+    assert np.max(np.abs(Xm - och.cholgs_mixed(X, 64))) < 1e-5
+    assert np.max(np.abs(Xm - och.cholgs(X))) < 1e-5
+    c.close()
+
+
+def test_orthonormalize_rank_deficient_reports_not_spd():
+    import paper_1903_10959_amd as P
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block(c.n_dof, 24, 5)
+    X[:, 7] = X[:, 3]
+    Xg = to_gpu(X)
+    with pytest.raises(P.ChfsiError) as ei:
+        c.orthonormalize(Xg)
+    assert ei.value.status == -5
+    np.testing.assert_array_equal(to_host(Xg), X)     # X untouched on failure
+    c.close()
+
+
+def test_rayleigh_ritz_exact_on_rotated_eigenvectors():
+    L, n_el, p = 9.0, 3, 4
+    picks = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (2, 0, 0), (3, 1, 1), (2, 2, 2),
+             (4, 0, 0), (0, 4, 1), (5, 5, 5), (10, 9, 8)]
+    X, lam, _ = tensor_eigvecs(L, n_el, p, picks)
+    Qr, _ = np.linalg.qr(np.random.default_rng(4).standard_normal((len(picks), len(picks))))
+    c, _ = make_ctx(L, n_el, p, V=np.zeros((n_el * p - 1) ** 3))
+    Xg = to_gpu(X @ Qr)
+    HX = to_gpu(np.zeros_like(X))
+    ev, res = c.rayleigh_ritz(Xg, HX_out=HX)
+    np.testing.assert_allclose(ev, np.sort(lam), rtol=1e-13, atol=1e-13)
+    assert np.max(res) < 1e-12 * np.max(np.abs(lam))
+    np.testing.assert_allclose(to_host(HX), oracle_apply(L, n_el, p, np.zeros(X.shape[0]))(to_host(Xg)),
+                               atol=1e-12 * np.max(np.abs(lam)))
+    c.close()
+
+
+@pytest.mark.parametrize("ncols", [24, 97, 200])
+def test_rayleigh_ritz_matches_oracle(ncols):
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = och.cholgs(workload.start_block(c.n_dof, ncols, 300 + ncols))
+    ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
+    Xr, HXr, D, res = och.rayleigh_ritz(ap, X)
+    Xg = to_gpu(X)
+    ev, rs = c.rayleigh_ritz(Xg)
+    scale = max(1.0, np.max(np.abs(D)))
+    np.testing.assert_allclose(ev, D, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(rs, res, rtol=1e-6, atol=1e-11 * scale)
+    # Ritz vectors up to sign (the projected spectrum of a random block is simple)
+    G = to_host(Xg)
+    sgn = np.sign(np.sum(G * Xr, axis=0))
+    assert np.max(np.abs(G * sgn[None, :] - Xr)) < 1e-8
+    c.close()
+
+
+def test_solve_small_workload_matches_dense_eigh():
+    """The plain definition: lowest 16 eigenpairs of Htilde by LAPACK."""
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    H = fem.htilde_csr(prob.L, prob.n_el, prob.p, V)
+    ev, evec = och.eig_dense(H)
+    X = to_gpu(workload.start_block(c.n_dof, prob.nblock, prob.x0_seed))
+    N = prob.nstates
+    tol = 1e-9 * max(1.0, abs(ev[0]))
+    out = c.solve(X, N, prob.degree, tol, max_iter=200)
+    assert out["converged"], out
+    err = np.abs(out["evals"][:N] - ev[:N]) / np.maximum(np.abs(ev[:N]), 1.0)
+    assert np.max(err) < 1e-10, err
+    Xs = to_host(X)
+    for k in och.cluster_boundaries(ev, N):
+        assert och.subspace_angle(Xs[:, :k], evec[:, :k]) < 1e-8, k
+    # every residual the library reports is the true residual of its vectors
+    ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
+    r_true = np.linalg.norm(ap(Xs) - Xs * out["evals"][None, :], axis=0)
+    np.testing.assert_allclose(out["resid"], r_true, rtol=1e-6, atol=1e-12)
+    c.close()
+
+
+def test_solve_box_closed_form_at_large_p6_shape_subset():
+    """V = 0 on a mid-size mesh: lowest levels equal sums of 1D eigenvalues."""
+    L, n_el, p = 20.0, 8, 6
+    c, _ = make_ctx(L, n_el, p, V=np.zeros((n_el * p - 1) ** 3))
+    a = np.linalg.eigvalsh(fem.operator_1d(L, n_el, p))
+    sums = np.sort((a[:8, None, None] + a[None, :8, None] + a[None, None, :8]).reshape(-1))
+    N = 20   # 1 + 3 + 3 + 3 + 6 + 4 ... stop at a cluster boundary
+    while sums[N] - sums[N - 1] < 1e-6:
+        N += 1
+    nb = workload.block_size(N)
+    X = to_gpu(workload.start_block(c.n_dof, nb, 55))
+    out = c.solve(X, N, 20, 1e-9, max_iter=300)
+    assert out["converged"]
+    np.testing.assert_allclose(out["evals"][:N], sums[:N], rtol=1e-10, atol=1e-10)
+    c.close()

@@ -155,3 +155,16 @@ def fmt_problem(prob: Problem) -> str:
 
 __all__ = ["Wells", "Problem", "PROBLEMS", "block_size", "draw_wells", "problem_wells",
            "eval_wells", "harmonic", "start_block", "perturbed", "batch_problems", "fmt_problem"]
+
+
+def start_block_device(n_dof: int, ncols: int, seed: int, device="cuda:0", ld: int | None = None):
+    """Seeded N(0,1) start block generated on the GPU (torch's Philox generator),
+    DoF-major [n_dof, ld]; used where a host-generated block would be too slow."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    ld = ncols if ld is None else ld
+    x = torch.zeros((n_dof, ld), dtype=torch.float64, device=device)
+    x[:, :ncols] = torch.randn((n_dof, ncols), generator=g, dtype=torch.float64, device=device)
+    return x[:, :ncols] if ld != ncols else x
