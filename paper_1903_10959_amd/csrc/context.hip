@@ -58,7 +58,7 @@ struct chfsi_ctx {
   DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32;
   // workspaces
   DevBuf fbuf[3];      // filter recursion buffers
-  DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX;
+  DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio;
   std::vector<double> host_scratch = std::vector<double>(16);
   // timing of the cell-product launches
   bool timing = false;
@@ -114,7 +114,8 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   else (void)hipDeviceSynchronize();
   DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32,
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
-                   &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX};
+                   &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
+                   &c->diag0, &c->minratio};
   for (DevBuf *b : all) b->release();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -483,31 +484,73 @@ static int ensure_small(chfsi_ctx *c, int n) {
   HIPCHK(c, c->evals_d.ensure((size_t)n * sizeof(double)));
   HIPCHK(c, c->resid_d.ensure((size_t)n * sizeof(double)));
   HIPCHK(c, c->flag.ensure(4 * sizeof(int)));
+  HIPCHK(c, c->diag0.ensure((size_t)n * sizeof(double)));
+  HIPCHK(c, c->minratio.ensure((size_t)nb * sizeof(double)));
+  if ((int)c->host_scratch.size() < nb + 16) c->host_scratch.resize(nb + 16);
   HIPCHK(c, c->gram_part.ensure(gram_part_elems(c->mesh.n_dof, n) * sizeof(double)));
   HIPCHK(c, c->resid_part.ensure((size_t)resid_nchunk(c->mesh.n_dof) * n * sizeof(double)));
   return 0;
 }
 
-extern "C" int chfsi_orthonormalize(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed) {
-  if (int r = check_block(c, X, ld, ncols)) return r;
+// CholGS on X (Alg. 3).  shift_rel > 0 factors S + shift_rel * max(diag S) I
+// (shifted Cholesky QR).  *rmin receives min_j d_j / S_jj over the pivots.
+static int cholgs_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed, double shift_rel, double *rmin) {
   if (int r = ensure_small(c, ncols)) return r;
   const int64_t nd = c->mesh.n_dof;
+  const int nb32 = (ncols + 31) / 32;
   double *S = c->Smat.as<double>();
   gram_launch(X, ld, X, ld, nd, ncols, c->gram_part.as<double>(), S, mixed ? 1 : 0, c->stream);
   zero_int_launch(c->flag.as<int>(), 1, c->stream);
-  potrf_launch(S, ncols, c->dinv.as<double>(), c->flag.as<int>(), c->stream);
+  potrf_launch(S, ncols, c->dinv.as<double>(), c->flag.as<int>(), c->diag0.as<double>(), c->minratio.as<double>(),
+               shift_rel, c->stream);
   int hflag = 0;
+  double *hr = c->host_scratch.data();
   HIPCHK(c, hipMemcpyAsync(&hflag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hr, c->minratio.p, nb32 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  double m = 1.0;
+  for (int i = 0; i < nb32; ++i) m = std::min(m, hr[i]);
+  if (rmin) *rmin = m;
   if (hflag) {
-    char msg[128];
-    std::snprintf(msg, sizeof msg, "CholGS: overlap not positive definite (pivot %d)", hflag - 1);
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "CholGS: overlap not numerically positive definite (pivot %d, ratio %.3g)",
+                  hflag - 1, m);
     return fail(c, CHFSI_ERR_NOT_SPD, msg);
   }
   trtri_t_launch(S, c->dinv.as<double>(), ncols, c->Zmat.as<double>(), c->Wmat.as<double>(), c->stream);
   if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "orthonormalize: block too wide for the row-panel kernel");
   HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+extern "C" int chfsi_orthonormalize(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  return cholgs_impl(c, X, ld, ncols, mixed, 0.0, nullptr);
+}
+
+// The solve's orthonormalisation: CholGS, repeated while the smallest relative
+// pivot shows lost orthogonality (CholeskyQR2), with the shifted Cholesky QR
+// of Fukaya et al. when the overlap is numerically singular.
+static int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes) {
+  double rmin = 1.0;
+  int np = 1;
+  int st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin);
+  if (st == CHFSI_ERR_NOT_SPD) {
+    const double u = 1.1102230246251565e-16;
+    const double m = (double)c->mesh.n_dof, n = nb;
+    const double shift_rel = 11.0 * (m * n + n * (n + 1.0)) * u * n;
+    st = cholgs_impl(c, X, ld, nb, mixed, shift_rel, &rmin);
+    rmin = 0.0;
+    ++np;
+  }
+  if (st) return st;
+  for (int k = 0; k < 3 && rmin < 1e-2; ++k) {
+    st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin);
+    ++np;
+    if (st) return st;
+  }
+  if (passes) *passes = np;
   return 0;
 }
 
@@ -588,7 +631,8 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
   const int mixed = o->mixed_cholgs ? 1 : 0;
   // start: CholGS + RR on the given block
   HIPCHK(c, hipEventRecord(ev[0], c->stream));
-  int st = chfsi_orthonormalize(c, X, ld, nb, mixed);
+  int passes = 0;
+  int st = orth_robust(c, X, ld, nb, mixed, &passes);
   if (st) return st;
   HIPCHK(c, hipEventRecord(ev[1], c->stream));
   if (int r = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr)) return r;
@@ -611,7 +655,7 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
     st = chfsi_chebyshev_filter(c, X, ld, nb, o->degree, a, b, a0, rung_prec(rung), o->block_width);
     if (st) return st;
     HIPCHK(c, hipEventRecord(ev[4], c->stream));
-    st = chfsi_orthonormalize(c, X, ld, nb, mixed);
+    st = orth_robust(c, X, ld, nb, mixed, &passes);
     if (st) return st;
     HIPCHK(c, hipEventRecord(ev[5], c->stream));
     if (int r = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr)) return r;

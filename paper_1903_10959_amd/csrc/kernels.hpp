@@ -52,9 +52,12 @@ void resid_launch(const double *X, int64_t ldx, const double *HX, int64_t ldh, c
 
 // ---- small dense FP64 kernels (small.hip) ---------------------------------
 // In-place blocked Cholesky of the lower triangle of S (n x n row-major):
-// S = L L^T; dinv receives the inverses of the 32x32 diagonal blocks of L;
-// *flag = first failing block + 1 (0 if positive definite).
-void potrf_launch(double *S, int n, double *dinv, int *flag, hipStream_t s);
+// S + shift_rel*max(diag S)*I = L L^T; dinv receives the inverses of the 32x32
+// diagonal blocks of L; *flag = first failing pivot + 1 (0 if every pivot
+// d_j > 1e-14 * diag_j); diag0 [n] scratch; minratio[ceil(n/32)] = per-block
+// minimum of d_j / diag_j.
+void potrf_launch(double *S, int n, double *dinv, int *flag, double *diag0, double *minratio, double shift_rel,
+                  hipStream_t s);
 // W = L^-T (upper triangular, n x n row-major) from L and dinv; Z scratch n x n.
 void trtri_t_launch(const double *L, const double *dinv, int n, double *Z, double *W, hipStream_t s);
 // Symmetric eigensolver (cyclic Jacobi, round-robin pairs, one launch per round).

@@ -21,7 +21,35 @@ namespace chfsi {
 
 static constexpr int NB = 32;
 
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double *S, int n, int k0, double *dinv, int *flag) {
+// Relative pivot below which the overlap counts as numerically singular.
+static constexpr double PIVOT_FLOOR = 1e-14;
+
+// Before the factorisation: diag0 = diag(S) (after an optional shift of
+// shift_rel * max diag(S) added to the diagonal, the shifted Cholesky remedy).
+__global__ __launch_bounds__(1024) void potrf_prep_kernel(double *S, int n, double shift_rel, double *diag0) {
+  __shared__ double red[1024];
+  double m = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, S[(int64_t)i * n + i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double sh = shift_rel * red[0];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double d = S[(int64_t)i * n + i] + sh;
+    S[(int64_t)i * n + i] = d;
+    diag0[i] = d;
+  }
+}
+
+// Factor one 32x32 diagonal block in LDS.  Pivot j is accepted when
+// d_j > PIVOT_FLOOR * diag0_j; minratio[block] = min_j d_j / diag0_j
+// (d_j / S_jj is the squared sine of the angle between column j and the span
+// of the columns before it, the loss-of-orthogonality indicator).
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double *S, int n, int k0, double *dinv, int *flag,
+                                                         const double *diag0, double *minratio) {
   __shared__ double a[NB][NB + 1];
   __shared__ double z[NB][NB + 1];
   const int kw = min(NB, n - k0);
@@ -32,11 +60,15 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double *S, int n, int k
     z[i][jj] = 0.0;
   }
   __syncthreads();
+  double rmin = 1.0;
   for (int jj = 0; jj < kw; ++jj) {
     double d = a[jj][jj];
     __syncthreads();
+    const double ref = diag0[k0 + jj];
+    const double ratio = ref > 0.0 ? d / ref : -1.0;
+    rmin = fmin(rmin, ratio);
     double ljj = sqrt(d);
-    if (!(d > 0.0) || !(ljj - ljj == 0.0)) {
+    if (!(ratio > PIVOT_FLOOR) || !(ljj - ljj == 0.0)) {
       if (tid == 0 && *flag == 0) *flag = k0 + jj + 1;
       ljj = __builtin_nan("");
     }
@@ -50,6 +82,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double *S, int n, int k
     }
     __syncthreads();
   }
+  if (tid == 0) minratio[k0 / NB] = rmin;
   // inverse of the lower-triangular diagonal block, one column per thread
   if (tid < kw) {
     const int c = tid;
@@ -124,9 +157,11 @@ __global__ __launch_bounds__(256) void potrf_update_kernel(double *S, int n, int
   }
 }
 
-void potrf_launch(double *S, int n, double *dinv, int *flag, hipStream_t s) {
+void potrf_launch(double *S, int n, double *dinv, int *flag, double *diag0, double *minratio, double shift_rel,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(potrf_prep_kernel, dim3(1), dim3(1024), 0, s, S, n, shift_rel, diag0);
   for (int k0 = 0; k0 < n; k0 += NB) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, S, n, k0, dinv, flag);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, S, n, k0, dinv, flag, diag0, minratio);
     const int k1 = k0 + NB;
     if (k1 >= n) break;
     const int rest = n - k1;

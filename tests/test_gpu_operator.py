@@ -26,7 +26,7 @@ def _rel(a, b):
 ])
 def test_apply_fp64_matches_oracle(n_el, p, ncols, ld):
     L = 2.5 * n_el
-    wells = workload.draw_wells(4, L, 11 + p, (1.0, 3.0), (0.5, 1.0))
+    wells = workload.draw_wells(4, L, 11 + p, (1.0, 3.0), (0.3, 0.6))
     c, V = make_ctx(L, n_el, p, wells=wells)
     X = workload.start_block(c.n_dof, ncols, 1000 + p)
     Xg = to_gpu(X, ld)
