@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
+    ap.add_argument("--calib-bytes", type=int, default=0,
+                    help="first run a plain elementwise copy (y = x * 1) of this many bytes, three times: "
+                         "the reference for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (run with --gpus 1)",
@@ -81,6 +84,15 @@ def main():
     prob = workload.PROBLEMS[args.workload]
     bw = args.block_width or prob.block_width
     dev = torch.device("cuda:0")
+    if args.calib_bytes > 0:
+        xc = torch.ones(args.calib_bytes // 8, dtype=torch.float64, device=dev)
+        yc = torch.empty_like(xc)
+        for _ in range(3):
+            torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {args.calib_bytes} bytes read + written, 3 launches", file=sys.stderr,
+              flush=True)
+        del xc, yc
     print(f"[bench] {workload.fmt_problem(prob)} B={bw} prec={args.prec} on {torch.cuda.get_device_name(0)}",
           file=sys.stderr, flush=True)
     ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)

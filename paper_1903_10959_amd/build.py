@@ -20,7 +20,10 @@ SOURCES = ["mesh.cpp", "hx.hip", "dense.hip", "small.hip", "context.hip"]
 ARCH = os.environ.get("CHFSI_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled for all device code (the compiler may
 # otherwise form v_pk_* FP32 ops from scalar or float2 code).
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                # MFMA accumulators in ordinary VGPRs: avoids AGPR<->VGPR copies of
+                # loop-carried accumulators in the cell and Gram kernels
+                "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", f"-I{INCLUDE}"]
 
 

@@ -58,7 +58,8 @@ struct chfsi_ctx {
   DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32;
   // workspaces
   DevBuf fbuf[3];      // filter recursion buffers
-  DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio;
+  DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
+      rscratch;
   std::vector<double> host_scratch = std::vector<double>(16);
   // timing of the cell-product launches
   bool timing = false;
@@ -115,7 +116,7 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32,
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
                    &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
-                   &c->diag0, &c->minratio};
+                   &c->diag0, &c->minratio, &c->rscratch};
   for (DevBuf *b : all) b->release();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -486,6 +487,7 @@ static int ensure_small(chfsi_ctx *c, int n) {
   HIPCHK(c, c->flag.ensure(4 * sizeof(int)));
   HIPCHK(c, c->diag0.ensure((size_t)n * sizeof(double)));
   HIPCHK(c, c->minratio.ensure((size_t)nb * sizeof(double)));
+  HIPCHK(c, c->rscratch.ensure((size_t)rmul_chunk_rows(n) * n * sizeof(double)));
   if ((int)c->host_scratch.size() < nb + 16) c->host_scratch.resize(nb + 16);
   HIPCHK(c, c->gram_part.ensure(gram_part_elems(c->mesh.n_dof, n) * sizeof(double)));
   HIPCHK(c, c->resid_part.ensure((size_t)resid_nchunk(c->mesh.n_dof) * n * sizeof(double)));
@@ -518,7 +520,7 @@ static int cholgs_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed
     return fail(c, CHFSI_ERR_NOT_SPD, msg);
   }
   trtri_t_launch(S, c->dinv.as<double>(), ncols, c->Zmat.as<double>(), c->Wmat.as<double>(), c->stream);
-  if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->stream) != 0)
+  if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->rscratch.as<double>(), c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "orthonormalize: block too wide for the row-panel kernel");
   HIPCHK(c, hipGetLastError());
   return 0;
@@ -567,8 +569,8 @@ static int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, i
   if (jacobi_eigh(G, ncols, c->jac_work.as<double>(), c->evals_d.as<double>(), Q, 1e-14, 40,
                   c->host_scratch.data(), c->stream, sweeps) != 0)
     return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
-  if (rmul_launch(X, ld, nd, ncols, Q, 0, 0, c->stream) != 0 ||
-      rmul_launch(HX, ldh, nd, ncols, Q, 0, 0, c->stream) != 0)
+  if (rmul_launch(X, ld, nd, ncols, Q, 0, 0, c->rscratch.as<double>(), c->stream) != 0 ||
+      rmul_launch(HX, ldh, nd, ncols, Q, 0, 0, c->rscratch.as<double>(), c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
   resid_launch(X, ld, HX, ldh, c->evals_d.as<double>(), nd, ncols, c->resid_part.as<double>(),
                c->resid_d.as<double>(), c->stream);
@@ -697,6 +699,7 @@ extern "C" size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_w
   const size_t nn = (size_t)nblock * nblock;
   b += 4 * nn * 8 + jacobi_work_elems(nblock) * 8;                 // S, Z, W, jacobi
   b += gram_part_elems((int64_t)nd, nblock) * 8;
+  b += (size_t)rmul_chunk_rows(nblock) * nblock * 8;
   b += (size_t)resid_nchunk((int64_t)nd) * nblock * 8;
   return b;
 }

@@ -143,89 +143,142 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
 }
 
 // ---------------------------------------------------------------------------
-// In-place right multiplication by row panels.
+// Right multiplication X <- X W.  Rows are processed in chunks: an LDS-tiled
+// MFMA GEMM writes C = X_chunk W into a scratch chunk, a coalesced copy puts
+// it back (the paper's outer blocking over rows, which needs only a chunk of
+// extra memory).  Work-group tile 128 x 128 (4 waves x 64 x 64), K staged in
+// LDS 16 at a time, double buffered.  upper: W upper triangular, so output
+// column tile [n0, n0+128) only needs k < n0 + 128.  mixed (upper only): k in
+// the 64-wide diagonal block of a wave's columns in FP64, smaller k in FP32.
 // ---------------------------------------------------------------------------
-template <int R>
-__global__ __launch_bounds__(256) void rmul_kernel(double *__restrict__ X, int64_t ld, int64_t nrows, int n,
-                                                   const double *__restrict__ W, int upper, int mixed, int ldsn) {
-  extern __shared__ double panel[];  // R x ldsn
-  const int64_t row0 = (int64_t)blockIdx.x * R;
-  for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
-    int r = idx / n, c = idx - r * n;
-    int64_t row = row0 + r;
-    panel[r * ldsn + c] = row < nrows ? X[row * ld + c] : 0.0;
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+static constexpr int MT = 128, NTL = 128, KC = 16;
+static constexpr int ALD = KC + 1;   // padded LDS row of the A tile (odd -> no bank conflicts)
+
+__global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict__ X, int64_t ld, int64_t row0,
+                                                        int64_t nrows, int n, const double *__restrict__ W,
+                                                        int upper, int mixed, double *__restrict__ C, int64_t ldc) {
+  __shared__ double As[2][MT * ALD];
+  __shared__ double Ws[2][KC * NTL];
+  const int nt = (n + NTL - 1) / NTL;
+  const int mt = blockIdx.x / nt;
+  const int ntile = blockIdx.x - mt * nt;
+  const int64_t r0 = row0 + (int64_t)mt * MT;    // first X row of this tile
+  const int n0 = ntile * NTL;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wi = wave >> 1, wj = wave & 1;
   const int j = lane & 15, kq = lane >> 4;
-  const int ncb = (n + 15) / 16;
-  constexpr int RB = R / 16;
-  for (int cb = wave; cb < ncb; cb += 4) {
-    const int col = cb * 16 + j;
-    const bool cok = col < n;
-    const int kend = upper ? (((cb + 1) * 16 < n) ? (cb + 1) * 16 : n) : n;
-    // mixed: k in [kd, kend) is the 64x64 diagonal block of this column block
-    const int kd = mixed ? (cb * 16 / 64) * 64 : 0;
-    v4d acc[RB];
-    v4f acc32[RB];
+  const int kend = upper ? min(n, n0 + NTL) : n;
+  const int c0 = n0 + wj * 64;                   // first column of this wave
+  const int kdiag = mixed ? (c0 / 64) * 64 : 0;  // mixed: k >= kdiag is the FP64 diagonal block
+
+  v4d acc[4][4];
+  v4f acc32[4][4];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      acc[r] = v4d{0, 0, 0, 0};
-      acc32[r] = v4f{0, 0, 0, 0};
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc[a][b] = v4d{0, 0, 0, 0};
+      acc32[a][b] = v4f{0, 0, 0, 0};
     }
-    for (int k = 0; k < kd; k += 4) {  // FP32 part (mixed only)
-      const int kk = k + kq;
-      float b = (kk < kend && cok) ? (float)W[(int64_t)kk * n + col] : 0.f;
+
+  auto stage = [&](int buf, int k0) {
+    // A tile: 128 rows x 16 columns (each row 128 contiguous bytes)
+    for (int idx = tid; idx < MT * KC; idx += 256) {
+      const int r = idx / KC, c = idx - r * KC;
+      const int64_t row = r0 + r;
+      const int k = k0 + c;
+      As[buf][r * ALD + c] = (row < row0 + nrows && k < n) ? X[row * ld + k] : 0.0;
+    }
+    // W tile: 16 rows x 128 columns
+    for (int idx = tid; idx < KC * NTL; idx += 256) {
+      const int r = idx / NTL, c = idx - r * NTL;
+      const int k = k0 + r, col = n0 + c;
+      Ws[buf][r * NTL + c] = (k < kend && col < n) ? W[(int64_t)k * n + col] : 0.0;
+    }
+  };
+
+  const int nk = (kend + KC - 1) / KC;
+  if (nk > 0) stage(0, 0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) stage(buf ^ 1, (kc + 1) * KC);
+    const int kbase = kc * KC;
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        float a = kk < n ? (float)panel[(r * 16 + j) * ldsn + kk] : 0.f;
-        acc32[r] = mfma16x4(a, b, acc32[r]);
+    for (int ks = 0; ks < KC; ks += 4) {
+      const int kk = ks + kq;
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][(wi * 64 + a * 16 + j) * ALD + kk];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Ws[buf][kk * NTL + wj * 64 + b * 16 + j];
+      if (kbase + ks >= kdiag) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4(av[a], bv[b], acc[a][b]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc32[a][b] = mfma16x4((float)av[a], (float)bv[b], acc32[a][b]);
       }
     }
-    for (int k = kd; k < kend; k += 4) {  // FP64 part
-      const int kk = k + kq;
-      double b = (kk < kend && cok) ? W[(int64_t)kk * n + col] : 0.0;
+    __syncthreads();
+  }
+  if (mixed && kdiag > 0) {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        double a = kk < n ? panel[(r * 16 + j) * ldsn + kk] : 0.0;
-        acc[r] = mfma16x4(a, b, acc[r]);
-      }
-    }
-    if (mixed && kd > 0) {
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        v4d t = f32acc_to_f64_layout(acc32[r], lane);
-        acc[r] += t;
-      }
-    }
-    if (!cok) continue;
+      for (int b = 0; b < 4; ++b) acc[a][b] += f32acc_to_f64_layout(acc32[a][b], lane);
+  }
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int64_t row = row0 + r * 16 + acc_row<double>(kq, q);
-        if (row < nrows) X[row * ld + col] = acc[r][q];
+        const int64_t rr = (int64_t)mt * MT + wi * 64 + a * 16 + acc_row<double>(kq, q);  // chunk-local row
+        const int col = c0 + b * 16 + j;
+        if (rr < nrows && col < n) C[rr * ldc + col] = acc[a][b][q];
       }
+}
+
+__global__ __launch_bounds__(256) void copy_back_kernel(const double *__restrict__ C, int64_t ldc, double *X,
+                                                        int64_t ld, int64_t row0, int64_t nrows, int n) {
+  const int64_t total = nrows * (int64_t)n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / n;
+    const int c = (int)(t - r * n);
+    X[(row0 + r) * ld + c] = C[r * ldc + c];
   }
 }
 
+int64_t rmul_chunk_rows(int n) {
+  // about 256 MiB of scratch, a multiple of the 128-row tile
+  int64_t rows = ((int64_t)1 << 25) / (n > 0 ? n : 1);
+  rows = rows / MT * MT;
+  if (rows < MT) rows = MT;
+  return rows;
+}
+
 int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
-                hipStream_t s) {
+                double *scratch, hipStream_t s) {
   if (mixed && !upper) return -1;
-  const int ldsn = (n % 2 == 0) ? n + 1 : n;
-  const size_t lds32 = (size_t)32 * ldsn * sizeof(double);
-  const size_t lds16 = (size_t)16 * ldsn * sizeof(double);
-  const size_t cap = 160 * 1024;
-  if (lds32 <= cap) {
-    unsigned grid = (unsigned)((nrows + 31) / 32);
-    if (grid == 0) return 0;
-    hipLaunchKernelGGL((rmul_kernel<32>), dim3(grid), dim3(256), lds32, s, X, ld, nrows, n, W, upper, mixed, ldsn);
-  } else if (lds16 <= cap) {
-    unsigned grid = (unsigned)((nrows + 15) / 16);
-    if (grid == 0) return 0;
-    hipLaunchKernelGGL((rmul_kernel<16>), dim3(grid), dim3(256), lds16, s, X, ld, nrows, n, W, upper, mixed, ldsn);
-  } else {
-    return -1;
+  const int64_t chunk = rmul_chunk_rows(n);
+  const int nt = (n + NTL - 1) / NTL;
+  for (int64_t r = 0; r < nrows; r += chunk) {
+    const int64_t rows = (nrows - r < chunk) ? nrows - r : chunk;
+    const int64_t mts = (rows + MT - 1) / MT;
+    hipLaunchKernelGGL(rmul_gemm_kernel, dim3((unsigned)(mts * nt)), dim3(256), 0, s, X, ld, r, rows, n, W, upper,
+                       mixed, scratch, (int64_t)n);
+    int64_t total = rows * n;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(copy_back_kernel, dim3((unsigned)blocks), dim3(256), 0, s, scratch, (int64_t)n, X, ld, r,
+                       rows, n);
   }
   return 0;
 }

@@ -39,12 +39,23 @@ __global__ __launch_bounds__(256) void hx_diag_kernel(const T *__restrict__ X, i
 
 // ---------------------------------------------------------------------------
 // Cell products of one colour.  Work-group = one cell x 64 columns; wave w owns
-// columns [n0, n0+16) with n0 = 64*tile + 16*w and all NP/16 output row blocks.
-// B operand: gathered, M^-1/2-scaled X rows of the cell (direct from global,
-// each row segment 16 contiguous values).  A operand: K_ref (symmetric, padded
-// to NP with zeros) read row-wise, so A[i][k] = K[k][i] is contiguous in i.
+// columns [n0, n0+16) with n0 = 64*tile + 16*w.  The cell's dof indices and
+// M^-1/2 values are staged in LDS, so the B operand (gathered, M^-1/2-scaled
+// X rows, 16 contiguous values per row) costs one LDS read and one global load
+// with no data-dependent branch.  A operand: K_ref (symmetric, zero padded to
+// NP) read row-wise, A[i][k] = K[k][i] contiguous in i.  Output row blocks are
+// processed RBP at a time so the accumulators stay in registers.
 // Epilogue: Y[dof, col] += s1 * minv[dof] * acc.
 // ---------------------------------------------------------------------------
+template <typename T, int NP>
+struct CellTile {
+  static constexpr int RB = NP / 16;
+  // FP64 accumulators are 8 registers per 16x16 block: at most 11 blocks live
+  static constexpr int RBP = sizeof(T) == 8 ? (RB % 11 == 0 ? 11 : (RB % 8 == 0 ? 8 : (RB % 7 == 0 ? 7 : RB)))
+                                            : RB;
+  static_assert(RB % RBP == 0, "row-block pass must divide the row blocks");
+};
+
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, int64_t ldx,
                                                        T *__restrict__ Y, int64_t ldy,
@@ -54,51 +65,58 @@ __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, 
                                                        const T *__restrict__ minv, int ncols,
                                                        int ntiles, T s1) {
   typedef typename acc4<T>::type acc_t;
-  constexpr int RB = NP / 16;  // output row blocks
+  constexpr int RB = CellTile<T, NP>::RB;
+  constexpr int RBP = CellTile<T, NP>::RBP;
+  __shared__ int32_t dof_s[NP];
+  __shared__ T mi_s[NP];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cell_slot = blockIdx.x / ntiles;
   const int tile = blockIdx.x - cell_slot * ntiles;
   const int e = cells[cell_slot];
+  for (int r = threadIdx.x; r < NP; r += blockDim.x) {
+    int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
+    dof_s[r] = d < 0 ? 0 : d;              // clamped: row 0 is always readable
+    mi_s[r] = d < 0 ? T(0) : minv[d];      // zero weight removes Dirichlet / padding rows
+  }
+  __syncthreads();
   const int j = lane & 15, kq = lane >> 4;
   const int col = tile * 64 + wave * 16 + j;
   const bool col_ok = col < ncols;
-  const int32_t *__restrict__ cm = cmap + (int64_t)e * n_loc;
+  const int colc = col_ok ? col : ncols - 1;   // clamped column, in bounds
+  const T cscale = col_ok ? T(1) : T(0);
 
-  // FP64 with NP = 512 would need 256 accumulator registers: two passes of 16 row blocks
-  constexpr int RBP = (sizeof(T) == 8 && RB > 22) ? RB / 2 : RB;
-  auto load_b = [&](int k) -> T {
-    int row = 4 * k + kq;
-    int d = row < n_loc ? cm[row] : -1;
-    return (d >= 0 && col_ok) ? X[(int64_t)d * ldx + col] * minv[d] : T(0);
-  };
-
+#pragma unroll 1
   for (int rb0 = 0; rb0 < RB; rb0 += RBP) {
     acc_t acc[RBP];
 #pragma unroll
     for (int r = 0; r < RBP; ++r) acc[r] = acc_t{0, 0, 0, 0};
+    const T *__restrict__ Kp = K + kq * NP + rb0 * 16 + j;
 
-    // software pipeline: operands of step k+1 are loaded while step k issues
-    T b_cur = load_b(0);
-    T a_cur[RBP];
+    // two operand sets in ping-pong: the loads of step k+1 are in flight while
+    // the MFMAs of step k issue (NP/4 is even for every NP used)
+    auto load_b = [&](int k) -> T {
+      const int row = 4 * k + kq;
+      return X[(int64_t)dof_s[row] * ldx + colc] * (mi_s[row] * cscale);
+    };
+    T b0 = load_b(0), b1;
+    T a0[RBP], a1[RBP];
 #pragma unroll
-    for (int r = 0; r < RBP; ++r) a_cur[r] = K[(int64_t)kq * NP + (rb0 + r) * 16 + j];
+    for (int r = 0; r < RBP; ++r) a0[r] = Kp[r * 16];
 
-    for (int k = 0; k < NP / 4; ++k) {
-      T b_nxt = T(0);
-      T a_nxt[RBP];
+#pragma unroll 1
+    for (int k = 0; k < NP / 4; k += 2) {
+      b1 = load_b(k + 1);
 #pragma unroll
-      for (int r = 0; r < RBP; ++r) a_nxt[r] = T(0);
-      if (k + 1 < NP / 4) {
-        b_nxt = load_b(k + 1);
+      for (int r = 0; r < RBP; ++r) a1[r] = Kp[(int64_t)(4 * (k + 1)) * NP + r * 16];
 #pragma unroll
-        for (int r = 0; r < RBP; ++r) a_nxt[r] = K[(int64_t)(4 * (k + 1) + kq) * NP + (rb0 + r) * 16 + j];
-      }
+      for (int r = 0; r < RBP; ++r) acc[r] = mfma16x4(a0[r], b0, acc[r]);
+      const int k2 = (k + 2 < NP / 4) ? k + 2 : k;   // last pair re-reads step k (in bounds, unused)
+      b0 = load_b(k2);
 #pragma unroll
-      for (int r = 0; r < RBP; ++r) acc[r] = mfma16x4(a_cur[r], b_cur, acc[r]);
-      b_cur = b_nxt;
+      for (int r = 0; r < RBP; ++r) a0[r] = Kp[(int64_t)(4 * k2) * NP + r * 16];
 #pragma unroll
-      for (int r = 0; r < RBP; ++r) a_cur[r] = a_nxt[r];
+      for (int r = 0; r < RBP; ++r) acc[r] = mfma16x4(a1[r], b1, acc[r]);
     }
 
     if (col_ok) {
@@ -106,12 +124,12 @@ __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, 
       for (int r = 0; r < RBP; ++r) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          int row = (rb0 + r) * 16 + acc_row<T>(kq, q);
+          const int row = (rb0 + r) * 16 + acc_row<T>(kq, q);
           if (row < n_loc) {
-            int d = cm[row];
-            if (d >= 0) {
-              T *yp = Y + (int64_t)d * ldy + col;
-              *yp += s1 * minv[d] * acc[r][q];
+            const T w = mi_s[row];
+            if (w != T(0)) {
+              T *yp = Y + (int64_t)dof_s[row] * ldy + col;
+              *yp += s1 * w * acc[r][q];
             }
           }
         }

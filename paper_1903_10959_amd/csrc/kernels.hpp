@@ -40,11 +40,13 @@ int gram_nsplit(int64_t nrows, int n);
 size_t gram_part_elems(int64_t nrows, int n);
 void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                  double *G, int mixed, hipStream_t s);
-// X[r, 0:n] <- X[r, 0:n] W for all rows (in place, row panels staged in LDS).
-// W: n x n row-major.  upper: W upper triangular (skip zero blocks).
-// mixed (requires upper): 64x64 diagonal blocks of W in FP64, the rest FP32.
+// X[r, 0:n] <- X[r, 0:n] W for all rows, chunk by chunk through `scratch`
+// (rmul_chunk_rows(n) x n doubles).  W: n x n row-major.  upper: W upper
+// triangular (zero blocks skipped).  mixed (requires upper): the 64-wide
+// diagonal blocks of W in FP64, the rest with FP32 inputs and products.
+int64_t rmul_chunk_rows(int n);
 int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
-                hipStream_t s);
+                double *scratch, hipStream_t s);
 // resid[j] = || HX[:,j] - lam[j] X[:,j] ||_2 ; part: [nchunk x n]
 int resid_nchunk(int64_t nrows);
 void resid_launch(const double *X, int64_t ldx, const double *HX, int64_t ldh, const double *lam, int64_t nrows,

@@ -131,3 +131,24 @@ def test_solve_box_closed_form_at_large_p6_shape_subset():
     assert out["converged"]
     np.testing.assert_allclose(out["evals"][:N], sums[:N], rtol=1e-10, atol=1e-10)
     c.close()
+
+
+def test_cholgs_and_rr_at_568_columns_across_row_chunks():
+    """568 columns (the large_p6 block) on 59,319 DoFs: more rows than one
+    row chunk of the rotation kernel, so the chunked path and its ragged last
+    chunk are both exercised."""
+    L, n_el, p = 20.0, 8, 5
+    wells = workload.draw_wells(8, L, 21, (1.0, 3.0), (0.5, 1.5))
+    c, V = make_ctx(L, n_el, p, wells=wells)
+    X = workload.start_block(c.n_dof, 568, 31)
+    Xg = to_gpu(X)
+    c.orthonormalize(Xg)
+    Xo = och.cholgs(X)
+    kappa = np.linalg.cond(X)
+    assert np.max(np.abs(to_host(Xg) - Xo)) < 1e-13 * kappa ** 2
+    ev, rs = c.rayleigh_ritz(Xg)
+    Xr, HXr, D, res = och.rayleigh_ritz(oracle_apply(L, n_el, p, V), Xo)
+    scale = max(1.0, np.max(np.abs(D)))
+    np.testing.assert_allclose(ev, D, rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(rs, res, rtol=1e-5, atol=1e-10 * scale)
+    c.close()
