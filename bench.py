@@ -55,6 +55,79 @@ def cpu_baseline(prob, ncols: int, budget_s: float = 30.0):
             "seconds": dt}
 
 
+def profiled_traffic(tag: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary profiles/<tag>.md, or None when that summary is missing or
+    the kernel source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{tag}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_1903_10959_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ["hx.hip", "common.hpp"])
+    if vals.get("kernel_source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_to_solution(args, prob, bw):
+    """Wall time of chfsi_solve from the seeded start block until every wanted
+    residual is <= tol (|Ritz value - exact eigenvalue| <= residual for a
+    symmetric operator), FP64 path vs the mixed path (FP32 filter falling back
+    to FP64 when the residual stalls, mixed-precision CholGS)."""
+    import numpy as np
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
+    V = workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords())
+    ctx.set_potential(V)
+    runs = {}
+    variants = [("fp64", dict(ladder=("fp64",), mixed_cholgs=False)),
+                ("mixed", dict(ladder=("fp32", "fp64"), mixed_cholgs=True))]
+    for name, kw in variants:
+        X = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = ctx.solve(X, prob.nstates, prob.degree, args.tol, max_iter=args.max_iter, block_width=bw, **kw)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        runs[name] = dict(seconds=dt, iters=out["iters"], converged=out["converged"], rung=out["rung"],
+                          max_resid=out["max_resid"], t_filter=out["t_filter"], t_cholgs=out["t_cholgs"],
+                          t_rr=out["t_rr"], evals_head=[float(x) for x in out["evals"][:4]],
+                          evals=out["evals"][:prob.nstates].tolist())
+        print(f"[bench] tts {name}: {dt:.2f} s, {out['iters']} passes, converged={out['converged']}, "
+              f"max resid {out['max_resid']:.2e}", file=sys.stderr, flush=True)
+        del X
+        torch.cuda.empty_cache()
+    e64 = np.array(runs["fp64"].pop("evals"))
+    emx = np.array(runs["mixed"].pop("evals"))
+    res = {
+        "metric": "ChFSI time to eigenpairs with residual <= 1e-6 Ha (FP64 path vs mixed path)",
+        "value": runs["fp64"]["seconds"] / runs["mixed"]["seconds"],
+        "unit": "speedup (FP64 time / mixed time)",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "data": "synthetic",
+        "dtype": "f64 vs fp32-filter/mixed-CholGS",
+        "config": {"workload": workload.fmt_problem(prob), "tol_Ha": args.tol, "filter_block": bw},
+        "fp64": runs["fp64"], "mixed": runs["mixed"],
+        "max_abs_eval_diff_mixed_vs_fp64": float(np.max(np.abs(e64 - emx))),
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,7 +138,11 @@ def main():
     ap.add_argument("--mixed-cholgs", action="store_true")
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=8)
+    ap.add_argument("--cpu-cols", type=int, default=16)
+    ap.add_argument("--mode", default="step", choices=["step", "tts"],
+                    help="step: throughput of whole ChFSI iterations (default); tts: time to solution")
+    ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
+    ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run a plain elementwise copy (y = x * 1) of this many bytes, three times: "
                          "the reference for scaling HBM byte counters")
@@ -95,6 +172,8 @@ def main():
         del xc, yc
     print(f"[bench] {workload.fmt_problem(prob)} B={bw} prec={args.prec} on {torch.cuda.get_device_name(0)}",
           file=sys.stderr, flush=True)
+    if args.mode == "tts":
+        return time_to_solution(args, prob, bw)
     ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
     V = workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords())
     ctx.set_potential(V)
@@ -163,7 +242,8 @@ def main():
                                f"N_b={nb}, Chebyshev degree {prob.degree}, filter block {bw}",
                    "filter_precision": args.prec, "mixed_cholgs": bool(args.mixed_cholgs)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": profiled_traffic(f"hx_cells_{prob.name}_{args.prec}"),
                      "kernel": f"hx_cells_kernel<{'double' if args.prec == 'fp64' else 'float'},"
                                f"{(n_loc + 15) // 16 * 16}>",
                      "launches": tim["launches"], "avg_launch_ms": avg_launch_ms,
