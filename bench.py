@@ -80,6 +80,7 @@ def profiled_traffic(tag: str):
 
 
 def time_to_solution(args, prob, bw):
+    os.environ.setdefault("CHFSI_VERBOSE", "1")   # the solve prints one line per pass
     """Wall time of chfsi_solve from the seeded start block until every wanted
     residual is <= tol (|Ritz value - exact eigenvalue| <= residual for a
     symmetric operator), FP64 path vs the mixed path (FP32 filter falling back
@@ -96,7 +97,7 @@ def time_to_solution(args, prob, bw):
     ctx.set_potential(V)
     runs = {}
     variants = [("fp64", dict(ladder=("fp64",), mixed_cholgs=False)),
-                ("mixed", dict(ladder=("fp32", "fp64"), mixed_cholgs=True))]
+                ("mixed", dict(ladder=("bf16", "fp32", "fp64"), mixed_cholgs=True))]
     for name, kw in variants:
         X = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=dev)
         torch.cuda.synchronize()
@@ -134,7 +135,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large_p6")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16x3"])
     ap.add_argument("--mixed-cholgs", action="store_true")
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -220,10 +221,20 @@ def main():
     dofvecs_step = prob.n_dof * nb * (prob.degree + 1)
     value = dofvecs_step / (dt / args.steps)
     n_loc = (prob.p + 1) ** 3
-    flops = 2.0 * n_loc * n_loc * tim["cell_vecs"]
+    n_cells = prob.n_el ** 3
     avg_launch_ms = tim["ms"] / max(tim["launches"], 1)
-    achieved = flops / (tim["ms"] * 1e-3) / 1e12
-    peak = PEAK[args.prec]
+    if args.prec in ("fp64", "fp32"):
+        # MFMA-bound: the method's dense cell products, 2 n_loc^2 flops per cell-vector
+        flops = 2.0 * n_loc * n_loc * tim["cell_vecs"]
+        achieved = flops / (tim["ms"] * 1e-3) / 1e12
+        peak, bound, unit = PEAK[args.prec], "mfma", "TFLOP/s"
+        kname = f"hx_cells_kernel<{'double' if args.prec == 'fp64' else 'float'},{(n_loc + 15) // 16 * 16}>"
+    else:
+        # HBM-bound: 3 x 4 B of FP32 recursion state per DoF-vec (read X_k, X_k-1, write X_k+1)
+        dofvecs = tim["cell_vecs"] * prob.n_dof / n_cells
+        achieved = 12.0 * dofvecs / (tim["ms"] * 1e-3) / 1e9
+        peak, bound, unit = HBM_PEAK, "hbm", "GB/s"
+        kname = f"hx_cells_bf16_kernel<{(n_loc + 31) // 32 * 32},{'true' if args.prec == 'bf16x3' else 'false'}>"
     out = {
         "metric": "ChFSI H.X DoF-vecs/s (whole ChFSI iteration: filter + CholGS + RR)",
         "value": value,
@@ -241,11 +252,10 @@ def main():
                                f"{prob.n_dof} DoFs, {prob.n_wells} seeded Gaussian wells, N={prob.nstates}, "
                                f"N_b={nb}, Chebyshev degree {prob.degree}, filter block {bw}",
                    "filter_precision": args.prec, "mixed_cholgs": bool(args.mixed_cholgs)},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak,
                      "traffic": profiled_traffic(f"hx_cells_{prob.name}_{args.prec}"),
-                     "kernel": f"hx_cells_kernel<{'double' if args.prec == 'fp64' else 'float'},"
-                               f"{(n_loc + 15) // 16 * 16}>",
+                     "kernel": kname,
                      "launches": tim["launches"], "avg_launch_ms": avg_launch_ms,
                      "flop_per_cell_vec": 2 * n_loc * n_loc},
         "filter_dofvecs_per_s": prob.n_dof * nb * prob.degree / (t_filter / args.steps),

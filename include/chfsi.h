@@ -139,9 +139,15 @@ int chfsi_rayleigh_ritz(chfsi_ctx *ctx, double *X, int64_t ld, int ncols,
  * set_potential, a0 = smallest), CholGS, RR} until
  * max_{i < nstates} resid_i <= tol or max_iter filter passes.
  * evals, resid: host [nblock].  rep (may be NULL) receives counters/timings.
- * The filter precision follows the ladder: ladder[0] until the largest wanted
- * residual stops falling by 2x per pass or drops below ladder_switch, then
- * ladder[1], ... (n_ladder = 0 means FP64 throughout). */
+ * The filter precision follows the ladder: rung k (ladder[k]) is left for
+ * rung k+1 when the largest wanted residual drops below ladder_tol[k], or
+ * stagnates (a pass reduces it by less than 2 %).  ladder_tol[k] <= 0 selects
+ * 4 u_k b, with u_k the unit roundoff of the rung's products (BF16 2^-8,
+ * BF16X3 2^-16, FP32 2^-24) and b the spectral upper bound: a reduced-
+ * precision filter leaves residuals of about u ||Htilde||.  n_ladder = 0 means
+ * FP64 throughout.  mixed_cholgs selects the paper's mixed CholGS
+ * (eq. overlapmixedprec) on every rung but the last one of a ladder of two or
+ * more rungs (with n_ladder <= 1: throughout). */
 typedef struct {
     int nstates;          /* wanted states N                                  */
     int nblock;           /* block size N_b >= nstates (guard states)         */
@@ -151,7 +157,7 @@ typedef struct {
     double tol;           /* residual tolerance on the wanted states          */
     chfsi_prec ladder[4]; /* filter precision ladder                          */
     int n_ladder;
-    double ladder_switch; /* residual below which the next rung starts (0=off)*/
+    double ladder_tol[4]; /* residual that ends rung k (<= 0: 4 u_k b)         */
     int mixed_cholgs;     /* 1: paper's mixed CholGS                          */
 } chfsi_opts;
 

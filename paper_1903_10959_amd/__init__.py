@@ -208,7 +208,7 @@ class Context:
 
     # ---- solve -----------------------------------------------------------
     def solve(self, X, nstates: int, degree: int, tol: float, max_iter: int = 200, block_width: int = 0,
-              ladder=("fp64",), ladder_switch: float = 0.0, mixed_cholgs: bool = False):
+              ladder=("fp64",), ladder_tol=None, mixed_cholgs: bool = False):
         px, ld, nb = self._block(X)
         o = Opts()
         o.nstates, o.nblock, o.degree, o.max_iter, o.block_width = int(nstates), nb, int(degree), int(max_iter), \
@@ -218,7 +218,8 @@ class Context:
         for i, v in enumerate(lad):
             o.ladder[i] = v
         o.n_ladder = len(lad)
-        o.ladder_switch = float(ladder_switch)
+        for k, v in enumerate(list(ladder_tol or [])[:4]):
+            o.ladder_tol[k] = float(v)
         o.mixed_cholgs = 1 if mixed_cholgs else 0
         ev = np.empty(nb)
         rs = np.empty(nb)

@@ -17,7 +17,7 @@ WARN_NOT_CONVERGED = 1
 class Opts(C.Structure):
     _fields_ = [("nstates", C.c_int), ("nblock", C.c_int), ("degree", C.c_int), ("max_iter", C.c_int),
                 ("block_width", C.c_int), ("tol", C.c_double), ("ladder", C.c_int * 4), ("n_ladder", C.c_int),
-                ("ladder_switch", C.c_double), ("mixed_cholgs", C.c_int)]
+                ("ladder_tol", C.c_double * 4), ("mixed_cholgs", C.c_int)]
 
 
 class Report(C.Structure):

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -55,7 +56,8 @@ struct chfsi_ctx {
   bool has_mesh = false, has_pot = false;
   double vmax = 0, ub = 0;
   // device tables
-  DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32;
+  DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
+  int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
   // workspaces
   DevBuf fbuf[3];      // filter recursion buffers
   DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
@@ -66,7 +68,23 @@ struct chfsi_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   int64_t cell_vecs = 0;
+  bool verbose = false;   // CHFSI_VERBOSE: one progress line per solve pass on stderr
 };
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+static float bf16_to_float(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
 
 static int fail(chfsi_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -100,6 +118,8 @@ extern "C" int chfsi_create(chfsi_ctx **out, int device, void *hip_stream) {
   if (!c) return CHFSI_ERR_OOM;
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const char *v = std::getenv("CHFSI_VERBOSE");
+  c->verbose = v && v[0] && v[0] != '0';
   *out = c;
   return 0;
 }
@@ -113,7 +133,7 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32,
+  DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32, &c->Kbh, &c->Kbl,
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
                    &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
                    &c->diag0, &c->minratio, &c->rscratch};
@@ -185,6 +205,21 @@ extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) {
   HIPCHK(c, hipMemcpy(c->K32.p, kp32.data(), kp32.size() * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->minv64.p, mi.data(), mi.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->minv32.p, mi32.data(), mi32.size() * sizeof(float), hipMemcpyHostToDevice));
+  // BF16 hi/lo split of the cell matrix, padded to a multiple of 32 (BF16 MFMA depth)
+  c->npb = (int)((nl + 31) / 32 * 32);
+  const size_t nb2 = (size_t)c->npb * c->npb;
+  std::vector<uint16_t> kh(nb2, 0), kl(nb2, 0);
+  for (size_t i = 0; i < nl; ++i)
+    for (size_t j = 0; j < nl; ++j) {
+      const float x = (float)M.kcell[i * nl + j];
+      const uint16_t h = bf16_rne(x);
+      kh[i * c->npb + j] = h;
+      kl[i * c->npb + j] = bf16_rne(x - bf16_to_float(h));
+    }
+  HIPCHK(c, c->Kbh.ensure(nb2 * 2));
+  HIPCHK(c, c->Kbl.ensure(nb2 * 2));
+  HIPCHK(c, hipMemcpy(c->Kbh.p, kh.data(), nb2 * 2, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->Kbl.p, kl.data(), nb2 * 2, hipMemcpyHostToDevice));
   c->has_mesh = true;
   return 0;
 }
@@ -316,35 +351,69 @@ static hipEvent_t next_event(chfsi_ctx *c) {
 // ---------------------------------------------------------------------------
 // Htilde-based step on one column block, any working precision T
 // ---------------------------------------------------------------------------
+// bf: 0 = products in T; 1 = BF16 inputs (T = float); 2 = BF16 hi/lo split (T = float)
 template <typename T>
 static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64_t ldp, T *Y, int64_t ldy,
-                       int ncols, double s1, double s2, double shift) {
+                       int ncols, double s1, double s2, double shift, int bf = 0) {
   const MeshTables &M = c->mesh;
   const T *V = std::is_same<T, double>::value ? (const T *)c->V64.p : (const T *)c->V32.p;
   const T *K = std::is_same<T, double>::value ? (const T *)c->K64.p : (const T *)c->K32.p;
   const T *mi = std::is_same<T, double>::value ? (const T *)c->minv64.p : (const T *)c->minv32.p;
-  hx_diag_launch<T>(X, ldx, Xp, ldp, Y, ldy, V, M.n_dof, ncols, (T)s1, (T)s2, (T)shift, c->stream);
   HxArgs<T> a;
   a.X = X;
   a.ldx = ldx;
+  a.Xp = Xp;
+  a.ldp = ldp;
   a.Y = Y;
   a.ldy = ldy;
   a.K = K;
   a.cmap = c->cmap.as<int32_t>();
   a.n_loc = M.n_loc;
   a.np = M.np;
+  a.q = M.q;
+  a.n_el = M.n_el;
   a.cells = c->cells.as<int32_t>();
   a.minv = mi;
+  a.V = V;
   a.ncols = ncols;
   a.s1 = (T)s1;
+  a.s2 = (T)s2;
+  a.shift = (T)shift;
   for (int col = 0; col < 8; ++col) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
       e0 = next_event(c);
       if (e0) (void)hipEventRecord(e0, c->stream);
     }
-    if (hx_cells_launch<T>(a, M.color_offset[col], M.color_offset[col + 1], c->stream) != 0)
-      return fail(c, CHFSI_ERR_ARG, "no cell kernel for this degree");
+    int lr;
+    if (bf) {
+      HxBf16Args b;
+      b.X = (const float *)X;
+      b.ldx = ldx;
+      b.Xp = (const float *)Xp;
+      b.ldp = ldp;
+      b.Y = (float *)Y;
+      b.ldy = ldy;
+      b.Kh = c->Kbh.as<const __bf16>();
+      b.Kl = c->Kbl.as<const __bf16>();
+      b.cmap = a.cmap;
+      b.n_loc = M.n_loc;
+      b.npb = c->npb;
+      b.q = M.q;
+      b.n_el = M.n_el;
+      b.cells = a.cells;
+      b.minv = c->minv32.as<float>();
+      b.V = c->V32.as<float>();
+      b.ncols = ncols;
+      b.s1 = (float)s1;
+      b.s2 = (float)s2;
+      b.shift = (float)shift;
+      b.split = bf == 2;
+      lr = hx_cells_bf16_launch(b, M.color_offset[col], M.color_offset[col + 1], c->stream);
+    } else {
+      lr = hx_cells_launch<T>(a, M.color_offset[col], M.color_offset[col + 1], c->stream);
+    }
+    if (lr != 0) return fail(c, CHFSI_ERR_ARG, "no cell kernel for this degree");
     if (c->timing && e0) {
       e1 = next_event(c);
       if (e1) (void)hipEventRecord(e1, c->stream);
@@ -381,7 +450,9 @@ extern "C" int chfsi_apply(chfsi_ctx *c, const double *X, double *Y, int64_t ld,
   if (int r = check_block(c, X, ld, ncols)) return r;
   if (!Y || X == Y) return fail(c, CHFSI_ERR_ARG, "apply: Y must not alias X");
   if (prec == CHFSI_FP64) return cheb_step_t<double>(c, X, ld, nullptr, 0, Y, ld, ncols, 1.0, 0.0, 0.0);
-  if (prec != CHFSI_FP32) return fail(c, CHFSI_ERR_ARG, "apply: precision not available");
+  if (prec != CHFSI_FP32 && prec != CHFSI_BF16 && prec != CHFSI_BF16X3)
+    return fail(c, CHFSI_ERR_ARG, "apply: unknown precision");
+  const int bf = prec == CHFSI_BF16 ? 1 : (prec == CHFSI_BF16X3 ? 2 : 0);
   const int64_t nd = c->mesh.n_dof;
   const int bw = std::min(ncols, 256);
   if (int r = ensure_fbufs(c, sizeof(float), bw)) return r;
@@ -389,7 +460,7 @@ extern "C" int chfsi_apply(chfsi_ctx *c, const double *X, double *Y, int64_t ld,
     const int w = std::min(bw, ncols - j0);
     float *a = c->fbuf[0].as<float>(), *b = c->fbuf[1].as<float>();
     copy_cols_launch<double, float>(X + j0, ld, a, w, nd, w, c->stream);
-    if (int r = cheb_step_t<float>(c, a, w, nullptr, 0, b, w, w, 1.0, 0.0, 0.0)) return r;
+    if (int r = cheb_step_t<float>(c, a, w, nullptr, 0, b, w, w, 1.0, 0.0, 0.0, bf)) return r;
     copy_cols_launch<float, double>(b, w, Y + j0, ld, nd, w, c->stream);
   }
   HIPCHK(c, hipGetLastError());
@@ -401,7 +472,7 @@ extern "C" int chfsi_apply(chfsi_ctx *c, const double *X, double *Y, int64_t ld,
 // ---------------------------------------------------------------------------
 template <typename T>
 static int filter_block(chfsi_ctx *c, T *z0, int64_t ld0, T *w1, T *w2, int64_t ldw, int ncols, int degree,
-                        double a, double b, double a0) {
+                        double a, double b, double a0, int bf = 0) {
   // normalised recursion: rho_1 = 1/xi0, rho_{k+1} = 1/(2 xi0 - rho_k);
   // Z_1 = (rho_1/e)(H - c) Z_0;  Z_{k+1} = (2 rho_{k+1}/e)(H - c) Z_k - rho_{k+1} rho_k Z_{k-1}
   const double cc = 0.5 * (a + b), e = 0.5 * (b - a), xi0 = (a0 - cc) / e;
@@ -423,7 +494,7 @@ static int filter_block(chfsi_ctx *c, T *z0, int64_t ld0, T *w1, T *w2, int64_t 
     int out = 0;
     while (out == cur || out == prev) ++out;
     if (int r = cheb_step_t<T>(c, buf[cur], lds[cur], prev >= 0 ? buf[prev] : nullptr, prev >= 0 ? lds[prev] : 0,
-                               buf[out], lds[out], ncols, s1, s2, cc))
+                               buf[out], lds[out], ncols, s1, s2, cc, bf))
       return r;
     prev = cur;
     cur = out;
@@ -436,7 +507,9 @@ extern "C" int chfsi_chebyshev_filter(chfsi_ctx *c, double *X, int64_t ld, int n
                                       double b, double a0, chfsi_prec prec, int block_width) {
   if (int r = check_block(c, X, ld, ncols)) return r;
   if (degree < 0 || !(a0 < a) || !(a < b)) return fail(c, CHFSI_ERR_ARG, "filter: need a0 < a < b, degree >= 0");
-  if (prec != CHFSI_FP64 && prec != CHFSI_FP32) return fail(c, CHFSI_ERR_ARG, "filter: precision not available");
+  if (prec != CHFSI_FP64 && prec != CHFSI_FP32 && prec != CHFSI_BF16 && prec != CHFSI_BF16X3)
+    return fail(c, CHFSI_ERR_ARG, "filter: unknown precision");
+  const int bf = prec == CHFSI_BF16 ? 1 : (prec == CHFSI_BF16X3 ? 2 : 0);
   if (degree == 0) return 0;
   const int64_t nd = c->mesh.n_dof;
   int bw = block_width > 0 ? block_width : 128;
@@ -456,7 +529,7 @@ extern "C" int chfsi_chebyshev_filter(chfsi_ctx *c, double *X, int64_t ld, int n
       float *f0 = c->fbuf[0].as<float>();
       copy_cols_launch<double, float>(X + j0, ld, f0, w, nd, w, c->stream);
       if (int r = filter_block<float>(c, f0, w, c->fbuf[1].as<float>(), c->fbuf[2].as<float>(), w, w, degree, a,
-                                      b, a0))
+                                      b, a0, bf))
         return r;
       copy_cols_launch<float, double>(f0, w, X + j0, ld, nd, w, c->stream);
     }
@@ -630,7 +703,17 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
   const int nrung = std::max(1, std::min(o->n_ladder, 4));
   auto rung_prec = [&](int rg) { return o->n_ladder > 0 ? o->ladder[rg] : CHFSI_FP64; };
   int rung = 0;
-  const int mixed = o->mixed_cholgs ? 1 : 0;
+  // mixed CholGS runs on the reduced-precision rungs; with a ladder the last
+  // rung is FP64 throughout (FP32 rounding of the overlap inputs leaves a
+  // residual floor near 1e-7 relative)
+  auto rung_tol = [&](int rg) {
+    if (o->ladder_tol[rg] > 0) return o->ladder_tol[rg];
+    const chfsi_prec pr = rung_prec(rg);
+    const double u = pr == CHFSI_BF16 ? 0x1p-8 : pr == CHFSI_BF16X3 ? 0x1p-16 : pr == CHFSI_FP32 ? 0x1p-24 : 0.0;
+    return 4.0 * u * c->ub;
+  };
+  auto mixed_now = [&]() { return (o->mixed_cholgs && (o->n_ladder <= 1 || rung + 1 < nrung)) ? 1 : 0; };
+  int mixed = mixed_now();
   // start: CholGS + RR on the given block
   HIPCHK(c, hipEventRecord(ev[0], c->stream));
   int passes = 0;
@@ -670,11 +753,17 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
     ++it;
     const double nres = maxres();
     if (o->n_ladder > 1 && rung + 1 < nrung) {
-      const bool stalled = nres > 0.5 * res;
-      const bool below = o->ladder_switch > 0 && nres < o->ladder_switch;
+      const bool stalled = nres > 0.98 * res;
+      const bool below = nres < rung_tol(rung);
       if (stalled || below) ++rung;
+      mixed = mixed_now();
     }
     res = nres;
+    if (c->verbose) {
+      std::fprintf(stderr, "[chfsi] pass %d: max wanted residual %.3e, rung %d, filter %.3f s, cholgs %.3f s, rr %.3f s\n",
+                   it, res, rung, R.t_filter, R.t_cholgs, R.t_rr);
+      std::fflush(stderr);
+    }
   }
   R.iters = it;
   R.rung = rung;

@@ -6,36 +6,20 @@
 // global block, multiply, assemble.  On a uniform mesh every cell carries the
 // same stiffness K_ref, so the cell products form one dense contraction
 // K_ref [n_loc x n_loc] x X_e [n_loc x ncols] per cell, done here on MFMA.
-// Under GLL quadrature the potential part is diagonal and is applied in the
-// element-wise pass (hx_diag), which also initialises Y.
+// Under GLL quadrature the potential part is diagonal.
 //
 // Assembly is atomic-free: cells are launched colour by colour (8 colours,
 // (ex&1)+2(ey&1)+4(ez&1)); cells of one colour share no DoF, so each output
-// row is read-modified-written by exactly one work-group per launch.
+// row is touched by exactly one work-group per launch.  The element-wise part
+// s1 (V - shift) X + s2 Xprev is fused into the first touch: colours run in
+// increasing order, and the first colour containing a node is the one whose
+// parity bit is 0 in every direction where the node lies on a cell face; the
+// single cell of that colour containing the node writes Y (element-wise part
+// plus its product), every later cell adds to Y.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace chfsi {
-
-// ---------------------------------------------------------------------------
-// Element-wise pass: Y[i,j] = s1 (V[i] - shift) X[i,j] + s2 Xprev[i,j]
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void hx_diag_kernel(const T *__restrict__ X, int64_t ldx,
-                                                      const T *__restrict__ Xp, int64_t ldp,
-                                                      T *__restrict__ Y, int64_t ldy,
-                                                      const T *__restrict__ V, int64_t n_dof, int ncols,
-                                                      T s1, T s2, T shift) {
-  const int64_t total = n_dof * (int64_t)ncols;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i = t / ncols;
-    int j = (int)(t - i * ncols);
-    T y = s1 * (V[i] - shift) * X[i * ldx + j];
-    if (Xp) y += s2 * Xp[i * ldp + j];
-    Y[i * ldy + j] = y;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Cell products of one colour.  Work-group = one cell x 64 columns; wave w owns
@@ -56,19 +40,33 @@ struct CellTile {
   static_assert(RB % RBP == 0, "row-block pass must divide the row blocks");
 };
 
+// 1 when this cell is the first (in colour order) to touch local node r
+__device__ __forceinline__ int first_touch(int r, int q, int e, int n_el) {
+  const int a = r % q, b = (r / q) % q, c = r / (q * q);
+  const int ex = e % n_el, ey = (e / n_el) % n_el, ez = e / (n_el * n_el);
+  const bool fx = (a > 0 && a < q - 1) || !(ex & 1);
+  const bool fy = (b > 0 && b < q - 1) || !(ey & 1);
+  const bool fz = (c > 0 && c < q - 1) || !(ez & 1);
+  return (fx && fy && fz) ? 1 : 0;
+}
+
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, int64_t ldx,
+                                                       const T *__restrict__ Xp, int64_t ldp,
                                                        T *__restrict__ Y, int64_t ldy,
                                                        const T *__restrict__ K,
                                                        const int32_t *__restrict__ cmap, int n_loc,
+                                                       int q, int n_el,
                                                        const int32_t *__restrict__ cells,
-                                                       const T *__restrict__ minv, int ncols,
-                                                       int ntiles, T s1) {
+                                                       const T *__restrict__ minv, const T *__restrict__ V,
+                                                       int ncols, int ntiles, T s1, T s2, T shift) {
   typedef typename acc4<T>::type acc_t;
   constexpr int RB = CellTile<T, NP>::RB;
   constexpr int RBP = CellTile<T, NP>::RBP;
   __shared__ int32_t dof_s[NP];
   __shared__ T mi_s[NP];
+  __shared__ T vd_s[NP];     // s1 (V - shift) on first-touch rows, NaN marker elsewhere unused
+  __shared__ int8_t ft_s[NP];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cell_slot = blockIdx.x / ntiles;
@@ -78,6 +76,9 @@ __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, 
     int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
     dof_s[r] = d < 0 ? 0 : d;              // clamped: row 0 is always readable
     mi_s[r] = d < 0 ? T(0) : minv[d];      // zero weight removes Dirichlet / padding rows
+    const int ft = d < 0 ? 0 : first_touch(r, q, e, n_el);
+    ft_s[r] = (int8_t)ft;
+    vd_s[r] = ft ? s1 * (V[d] - shift) : T(0);
   }
   __syncthreads();
   const int j = lane & 15, kq = lane >> 4;
@@ -123,13 +124,21 @@ __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, 
 #pragma unroll
       for (int r = 0; r < RBP; ++r) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = (rb0 + r) * 16 + acc_row<T>(kq, q);
+        for (int qq = 0; qq < 4; ++qq) {
+          const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
           if (row < n_loc) {
             const T w = mi_s[row];
             if (w != T(0)) {
-              T *yp = Y + (int64_t)dof_s[row] * ldy + col;
-              *yp += s1 * w * acc[r][q];
+              const int64_t d = dof_s[row];
+              T *yp = Y + d * ldy + col;
+              const T prod = s1 * w * acc[r][qq];
+              if (ft_s[row]) {
+                T y = vd_s[row] * X[d * ldx + col] + prod;
+                if (Xp) y += s2 * Xp[d * ldp + col];
+                *yp = y;
+              } else {
+                *yp += prod;
+              }
             }
           }
         }
@@ -138,14 +147,164 @@ __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 cell products (FP32 state, FP32 accumulation): v_mfma_f32_16x16x32_bf16.
+// The cell's gathered, M^-1/2-scaled X rows (64 columns) are converted to BF16
+// (round to nearest even) and staged in LDS transposed, [column][local node],
+// so a B fragment (8 consecutive local nodes of one column) is one 16-byte LDS
+// read.  SPLIT: X = hi + lo and K = hi + lo in BF16, three products
+// hi*hi + hi*lo + lo*hi accumulated in FP32.  NPB: n_loc rounded up to 32.
+// ---------------------------------------------------------------------------
+template <int NPB, bool SPLIT>
+__global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
+                                                            const float *__restrict__ Xp, int64_t ldp,
+                                                            float *__restrict__ Y, int64_t ldy,
+                                                            const __bf16 *__restrict__ Kh,
+                                                            const __bf16 *__restrict__ Kl,
+                                                            const int32_t *__restrict__ cmap, int n_loc, int q,
+                                                            int n_el, const int32_t *__restrict__ cells,
+                                                            const float *__restrict__ minv,
+                                                            const float *__restrict__ V, int ncols, int ntiles,
+                                                            float s1, float s2, float shift) {
+  constexpr int RB = NPB / 16;
+  constexpr int LDX = NPB + 8;            // row of the transposed tile, 16-byte aligned
+  constexpr int NPART = SPLIT ? 2 : 1;
+  __shared__ int32_t dof_s[NPB];
+  __shared__ float mi_s[NPB];
+  __shared__ float vd_s[NPB];
+  __shared__ int8_t ft_s[NPB];
+  __shared__ __attribute__((aligned(16))) __bf16 xs[NPART][64 * LDX];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int cell_slot = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - cell_slot * ntiles;
+  const int e = cells[cell_slot];
+  const int col0 = tile * 64;
+  for (int r = threadIdx.x; r < NPB; r += blockDim.x) {
+    int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
+    dof_s[r] = d < 0 ? 0 : d;
+    mi_s[r] = d < 0 ? 0.f : minv[d];
+    const int ft = d < 0 ? 0 : first_touch(r, q, e, n_el);
+    ft_s[r] = (int8_t)ft;
+    vd_s[r] = ft ? s1 * (V[d] - shift) : 0.f;
+  }
+  __syncthreads();
+  // stage: 4 consecutive columns per thread per row (16-byte global loads when aligned)
+  const bool vec_ok = ((ldx & 3) == 0) && ((col0 & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
+  for (int idx = threadIdx.x; idx < NPB * 16; idx += blockDim.x) {
+    const int r = idx >> 4, c4 = (idx & 15) * 4;
+    const float w = mi_s[r];
+    float v[4];
+    const float *src = X + (int64_t)dof_s[r] * ldx + col0 + c4;
+    if (vec_ok && col0 + c4 + 3 < ncols) {
+      const float4 t = *reinterpret_cast<const float4 *>(src);
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (col0 + c4 + u < ncols) ? src[u] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float x = v[u] * w;
+      const __bf16 h = (__bf16)x;
+      xs[0][(c4 + u) * LDX + r] = h;
+      if (SPLIT) xs[NPART - 1][(c4 + u) * LDX + r] = (__bf16)(x - (float)h);
+    }
+  }
+  __syncthreads();
+  const int j = lane & 15, kq = lane >> 4;
+  const int lcol = wave * 16 + j;               // column within the tile
+  const int col = col0 + lcol;
+  v4f acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = v4f{0, 0, 0, 0};
+  typedef __attribute__((ext_vector_type(4))) int v4i;
+  for (int k = 0; k < NPB; k += 32) {
+    const int kk = k + 8 * kq;
+    v8bf bh, bl;
+    {
+      v4i t = *reinterpret_cast<const v4i *>(&xs[0][lcol * LDX + kk]);
+      bh = __builtin_bit_cast(v8bf, t);
+      if (SPLIT) {
+        v4i t2 = *reinterpret_cast<const v4i *>(&xs[NPART - 1][lcol * LDX + kk]);
+        bl = __builtin_bit_cast(v8bf, t2);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      // A[i][k..k+7] = K[i][k..k+7] (row i = 16 r + j): one 16-byte load
+      const v4i ta = *reinterpret_cast<const v4i *>(Kh + (int64_t)(r * 16 + j) * NPB + kk);
+      const v8bf ah = __builtin_bit_cast(v8bf, ta);
+      acc[r] = mfma16x32bf(ah, bh, acc[r]);
+      if (SPLIT) {
+        const v4i tl = *reinterpret_cast<const v4i *>(Kl + (int64_t)(r * 16 + j) * NPB + kk);
+        const v8bf al = __builtin_bit_cast(v8bf, tl);
+        acc[r] = mfma16x32bf(ah, bl, acc[r]);
+        acc[r] = mfma16x32bf(al, bh, acc[r]);
+      }
+    }
+  }
+  if (col >= ncols) return;
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int row = r * 16 + acc_row<float>(kq, qq);
+      if (row < n_loc) {
+        const float w = mi_s[row];
+        if (w != 0.f) {
+          const int64_t d = dof_s[row];
+          float *yp = Y + d * ldy + col;
+          const float prod = s1 * w * acc[r][qq];
+          if (ft_s[row]) {
+            float y = vd_s[row] * X[d * ldx + col] + prod;
+            if (Xp) y += s2 * Xp[d * ldp + col];
+            *yp = y;
+          } else {
+            *yp += prod;
+          }
+        }
+      }
+    }
+}
+
+template <int NPB, bool SPLIT>
+static void launch_bf16(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
+  int ntiles = (a.ncols + 63) / 64;
+  int ncell = color_end - color_begin;
+  if (ncell <= 0 || ntiles <= 0) return;
+  hipLaunchKernelGGL((hx_cells_bf16_kernel<NPB, SPLIT>), dim3((unsigned)(ncell * ntiles)), dim3(256), 0, s, a.X,
+                     a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.Kh, a.Kl, a.cmap, a.n_loc, a.q, a.n_el,
+                     a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
+}
+
+template <bool SPLIT>
+static int dispatch_bf16(const HxBf16Args &a, int cb, int ce, hipStream_t s) {
+  switch (a.npb) {
+    case 32: launch_bf16<32, SPLIT>(a, cb, ce, s); break;
+    case 64: launch_bf16<64, SPLIT>(a, cb, ce, s); break;
+    case 128: launch_bf16<128, SPLIT>(a, cb, ce, s); break;
+    case 224: launch_bf16<224, SPLIT>(a, cb, ce, s); break;
+    case 352: launch_bf16<352, SPLIT>(a, cb, ce, s); break;
+    case 512: launch_bf16<512, SPLIT>(a, cb, ce, s); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
+  return a.split ? dispatch_bf16<true>(a, color_begin, color_end, s) : dispatch_bf16<false>(a, color_begin, color_end, s);
+}
+
 template <typename T, int NP>
 static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
   int ntiles = (a.ncols + 63) / 64;
   int ncell = color_end - color_begin;
   if (ncell <= 0 || ntiles <= 0) return;
   dim3 grid((unsigned)(ncell * ntiles)), block(256);
-  hipLaunchKernelGGL((hx_cells_kernel<T, NP>), grid, block, 0, s, a.X, a.ldx, a.Y, a.ldy, a.K, a.cmap,
-                     a.n_loc, a.cells + color_begin, a.minv, a.ncols, ntiles, a.s1);
+  hipLaunchKernelGGL((hx_cells_kernel<T, NP>), grid, block, 0, s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K,
+                     a.cmap, a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2,
+                     a.shift);
 }
 
 template <typename T>
@@ -163,23 +322,8 @@ int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStrea
   return 0;
 }
 
-template <typename T>
-void hx_diag_launch(const T *X, int64_t ldx, const T *Xp, int64_t ldp, T *Y, int64_t ldy, const T *V,
-                    int64_t n_dof, int ncols, T s1, T s2, T shift, hipStream_t s) {
-  int64_t total = n_dof * ncols;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL((hx_diag_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, X, ldx, Xp, ldp, Y, ldy, V,
-                     n_dof, ncols, s1, s2, shift);
-}
-
 template int hx_cells_launch<double>(const HxArgs<double> &, int, int, hipStream_t);
 template int hx_cells_launch<float>(const HxArgs<float> &, int, int, hipStream_t);
-template void hx_diag_launch<double>(const double *, int64_t, const double *, int64_t, double *, int64_t,
-                                     const double *, int64_t, int, double, double, double, hipStream_t);
-template void hx_diag_launch<float>(const float *, int64_t, const float *, int64_t, float *, int64_t,
-                                    const float *, int64_t, int, float, float, float, hipStream_t);
-
 // ---------------------------------------------------------------------------
 // Precision conversion and column-block copies (strided, DoF-major)
 // ---------------------------------------------------------------------------

@@ -6,25 +6,46 @@
 namespace chfsi {
 
 // ---- Chebyshev step (hx.hip) ----------------------------------------------
+// One Chebyshev step Y = s1 (Htilde - shift) X + s2 Xp, launched colour by colour
+// (colours 0..7 in order; the first colour writes Y, later colours add).
 template <typename T>
 struct HxArgs {
   const T *X;          // input block, [n_dof x ldx]
   int64_t ldx;
-  T *Y;                // output block (already holding the element-wise part)
+  const T *Xp;         // previous block or nullptr (s2 ignored)
+  int64_t ldp;
+  T *Y;                // output block
   int64_t ldy;
   const T *K;          // padded cell stiffness [np x np]
   const int32_t *cmap; // [n_cells x n_loc]
-  int n_loc, np;
+  int n_loc, np, q, n_el;
   const int32_t *cells;  // cell ids sorted by colour
   const T *minv;       // M^-1/2 [n_dof]
+  const T *V;          // potential [n_dof]
   int ncols;
-  T s1;                // scale of the cell part
+  T s1, s2, shift;
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s);
-template <typename T>
-void hx_diag_launch(const T *X, int64_t ldx, const T *Xp, int64_t ldp, T *Y, int64_t ldy, const T *V,
-                    int64_t n_dof, int ncols, T s1, T s2, T shift, hipStream_t s);
+// BF16 cell products: FP32 X/Y/minv, K_ref as BF16 hi (and lo when split),
+// padded to npb = round_up(n_loc, 32).
+struct HxBf16Args {
+  const float *X;
+  int64_t ldx;
+  const float *Xp;
+  int64_t ldp;
+  float *Y;
+  int64_t ldy;
+  const __bf16 *Kh, *Kl;
+  const int32_t *cmap;
+  int n_loc, npb, q, n_el;
+  const int32_t *cells;
+  const float *minv, *V;
+  int ncols;
+  float s1, s2, shift;
+  int split;
+};
+int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s);
 template <typename Tin, typename Tout>
 void copy_cols_launch(const Tin *in, int64_t ldi, Tout *out, int64_t ldo, int64_t nrows, int ncols,
                       hipStream_t s);

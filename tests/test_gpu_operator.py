@@ -103,3 +103,44 @@ def test_filter_matches_oracle_small_workload():
     Zo = och.cheb_filter_scaled(oracle_apply(prob.L, prob.n_el, prob.p, V), X, prob.degree, a, b, a0)
     assert _rel(to_host(Xg), Zo) < 1e-11
     c.close()
+
+
+@pytest.mark.parametrize("n_el,p,ncols", [(4, 4, 24), (3, 6, 70), (2, 7, 33), (4, 5, 64)])
+def test_apply_bf16_and_split_accuracy(n_el, p, ncols):
+    """BF16 inputs with FP32 accumulation: error at the BF16 rounding level
+    (2^-8 relative per operand); the hi/lo split recovers about 2^-16."""
+    L = 2.5 * n_el
+    wells = workload.draw_wells(4, L, 31 + p, (1.0, 3.0), (0.3, 0.6))
+    c, V = make_ctx(L, n_el, p, wells=wells)
+    X = workload.start_block(c.n_dof, ncols, 2000 + p)
+    Yo = oracle_apply(L, n_el, p, V)(X)
+    e_bf = _rel(to_host(c.apply(to_gpu(X), prec="bf16")), Yo)
+    e_x3 = _rel(to_host(c.apply(to_gpu(X), prec="bf16x3")), Yo)
+    e_32 = _rel(to_host(c.apply(to_gpu(X), prec="fp32")), Yo)
+    assert e_bf < 3e-2, e_bf
+    assert e_x3 < 2e-4, e_x3
+    assert e_x3 < e_bf / 20
+    assert e_32 < 2e-6
+    c.close()
+
+
+def test_filter_bf16_keeps_wanted_subspace_small_workload():
+    """One degree-20 BF16 filter pass followed by FP64 CholGS + RR moves the
+    Ritz values of the wanted states close to the FP64 filter's."""
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block(c.n_dof, prob.nblock, prob.x0_seed)
+    b = c.upper_bound
+    evs = {}
+    for prec in ["fp64", "bf16", "bf16x3"]:
+        Xg = to_gpu(X)
+        c.orthonormalize(Xg)
+        ev0, _ = c.rayleigh_ritz(Xg)
+        for _ in range(3):
+            c.chebyshev_filter(Xg, prob.degree, ev0[-1], b, ev0[0], prec=prec)
+            c.orthonormalize(Xg)
+            ev0, _ = c.rayleigh_ritz(Xg)
+        evs[prec] = ev0[:prob.nstates]
+    assert np.max(np.abs(evs["bf16"] - evs["fp64"])) < 5e-2
+    assert np.max(np.abs(evs["bf16x3"] - evs["fp64"])) < 1e-4
+    c.close()

@@ -152,3 +152,21 @@ def test_cholgs_and_rr_at_568_columns_across_row_chunks():
     np.testing.assert_allclose(ev, D, rtol=0, atol=1e-11 * scale)
     np.testing.assert_allclose(rs, res, rtol=1e-5, atol=1e-10 * scale)
     c.close()
+
+
+@pytest.mark.parametrize("ladder,mixed", [(("bf16", "fp32", "fp64"), False), (("fp32", "fp64"), True)])
+def test_solve_precision_ladder_reaches_fp64_accuracy(ladder, mixed):
+    """Reduced-precision filter rungs, then FP64: the converged eigenvalues
+    match dense eigh to the FP64 tolerance."""
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    ev = np.linalg.eigvalsh(fem.htilde_csr(prob.L, prob.n_el, prob.p, V).toarray())
+    X = to_gpu(workload.start_block(c.n_dof, prob.nblock, prob.x0_seed))
+    N = prob.nstates
+    out = c.solve(X, N, prob.degree, 1e-9 * max(1.0, abs(ev[0])), max_iter=300, ladder=ladder,
+                  mixed_cholgs=mixed)
+    assert out["converged"]
+    assert out["rung"] == len(ladder) - 1        # finished on the FP64 rung
+    err = np.abs(out["evals"][:N] - ev[:N]) / np.maximum(np.abs(ev[:N]), 1.0)
+    assert np.max(err) < (1e-10 if not mixed else 1e-8), err
+    c.close()
