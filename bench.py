@@ -79,6 +79,87 @@ def profiled_traffic(tag: str):
         return None
 
 
+def batch_throughput(args):
+    """The batched workload: 64 independent problems (n_el 4..12, p 4..7,
+    16..256 states) through chfsi_solve_batch for a fixed number of passes
+    (FP32 filter of degree 20, FP64 CholGS/RR), against the same passes solved
+    one problem at a time with chfsi_solve."""
+    import numpy as np
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    probs = workload.batch_problems(64, 4)
+    passes = args.steps
+    dev = torch.device("cuda:0")
+    ctxs, Xs, Ns = [], [], []
+    t0 = time.time()
+    for pr in probs:
+        c = P.Context(0, stream=torch.cuda.Stream(dev)).set_mesh(pr.L, pr.n_el, pr.p)
+        c.set_potential(workload.eval_wells(workload.problem_wells(pr), c.dof_coords()))
+        ctxs.append(c)
+        Xs.append(workload.start_block_device(pr.n_dof, pr.nblock, pr.x0_seed, device=dev))
+        Ns.append(pr.nstates)
+    torch.cuda.synchronize()
+    tot_dofs = sum(pr.n_dof for pr in probs)
+    print(f"[bench] batch: {len(probs)} problems, {tot_dofs} DoFs in all, setup {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    starts = [X.clone() for X in Xs]
+    # one pass first: build, graph capture and first-touch allocations
+    P.solve_batch(ctxs, [X.clone() for X in Xs], Ns, 20, 1e-30, max_iter=1, prec="fp32")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    res = P.solve_batch(ctxs, Xs, Ns, 20, 1e-30, max_iter=passes, prec="fp32")
+    torch.cuda.synchronize()
+    t_batch = time.time() - t0
+    dofvecs = sum(pr.n_dof * pr.nblock * (20 * r["iters"] + r["iters"] + 1) for pr, r in zip(probs, res))
+    print(f"[bench] batch: {passes} passes in {t_batch:.2f} s", file=sys.stderr, flush=True)
+    t0 = time.time()
+    for c, X0, pr in zip(ctxs, starts, probs):
+        c.solve(X0, pr.nstates, 20, 1e-30, max_iter=passes, ladder=("fp32",))
+    torch.cuda.synchronize()
+    t_seq = time.time() - t0
+    print(f"[bench] one at a time: {t_seq:.2f} s", file=sys.stderr, flush=True)
+    out = {"metric": "batched ChFSI H.X DoF-vecs/s (64 independent problems, FP32 filter, FP64 CholGS/RR)",
+           "value": dofvecs / t_batch, "unit": "DoF-vecs/s", "n_gpus": 1, "steps": passes, "warmup": 1,
+           "ms_per_step": t_batch / passes * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32-filter/f64", "data": "synthetic",
+           "config": {"workload": "batch: 64 problems, n_el in 4..12, p in 4..7, N in 16..256, L = 2.5 n_el, "
+                                  f"{tot_dofs} DoFs in all, Chebyshev degree 20"},
+           "one_at_a_time_seconds": t_seq, "batch_seconds": t_batch, "speedup_vs_one_at_a_time": t_seq / t_batch}
+    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
+
+
+def served_stream(args):
+    """Served stream: seeded Poisson arrivals of solve requests (sizes of the
+    batched workload), 5 warm-started solves each with a 1 % perturbed
+    potential, HBM-footprint admission, concurrent slots; p50/p99 latency."""
+    import torch
+
+    from paper_1903_10959_amd import serve as S
+
+    reqs = S.make_stream(args.requests, args.rate, seed=5)
+    t0 = time.time()
+    S.serve(reqs, slots=args.slots, hbm_budget=args.hbm_budget, solves=5, tol=args.tol, degree=20,
+            ladder=("fp32", "fp64"),
+            log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    st = S.latency_stats(reqs, wall)
+    dofvecs = sum(r.problem.n_dof * r.problem.nblock * (20 + 1) * sum(r.iters) for r in reqs)
+    out = {"metric": "served ChFSI stream: p99 end-to-end request latency (5 warm-started solves per request)",
+           "value": st["e2e_p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+           "dtype": "fp32-filter->f64", "data": "synthetic",
+           "config": {"workload": f"served: {args.requests} requests, Poisson rate {args.rate}/s, sizes of the "
+                                  f"batched workload, 5 solves each to residual {args.tol} Ha, {args.slots} slots, "
+                                  f"HBM budget {args.hbm_budget / 1e9:.0f} GB"},
+           "latency": st, "throughput_dofvecs_per_s": dofvecs / wall, "wall_s": wall}
+    print(json.dumps(out), flush=True)
+
+
 def time_to_solution(args, prob, bw):
     os.environ.setdefault("CHFSI_VERBOSE", "1")   # the solve prints one line per pass
     """Wall time of chfsi_solve from the seeded start block until every wanted
@@ -144,6 +225,10 @@ def main():
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution")
     ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
     ap.add_argument("--max-iter", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate per second")
+    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent slots")
+    ap.add_argument("--hbm-budget", type=float, default=160e9, help="serve: device bytes for admitted requests")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run a plain elementwise copy (y = x * 1) of this many bytes, three times: "
                          "the reference for scaling HBM byte counters")
@@ -159,6 +244,10 @@ def main():
     import paper_1903_10959_amd as P
     import workload
 
+    if args.workload == "batch":
+        return batch_throughput(args)
+    if args.workload == "serve":
+        return served_stream(args)
     prob = workload.PROBLEMS[args.workload]
     bw = args.block_width or prob.block_width
     dev = torch.device("cuda:0")

@@ -173,6 +173,22 @@ typedef struct {
 int chfsi_solve(chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
                 double *evals, double *resid, chfsi_report *rep);
 
+/* ---- solveBatch (many independent problems; the paper's k-point groups,
+ * Sec. 3.7, placed on one device) ---------------------------------------------
+ * ctxs[i] holds problem i's mesh and potential (one context per problem, all
+ * on the same device; distinct streams let the per-problem CholGS/RR overlap).
+ * Every problem uses the same Chebyshev degree and filter precision
+ * (opts[i].ladder[0]: FP64 or FP32; CholGS/RR are FP64).  Each pass runs one
+ * Chebyshev step of all active problems in shared launches (one per padded
+ * cell size and colour) captured once per active set in a HIP graph, then
+ * CholGS + RR per problem on host threads; a problem leaves the batch when its
+ * wanted residuals are <= opts[i].tol or after opts[i].max_iter passes.
+ * X[i]: device [n_dof_i x ld[i]] start block in, Ritz vectors out;
+ * evals[i], resid[i]: host [nblock_i]; reps (may be NULL) [n].
+ * Returns CHFSI_WARN_NOT_CONVERGED if any problem did not converge. */
+int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts *opts, double *const *X,
+                      const int64_t *ld, double *const *evals, double *const *resid, chfsi_report *reps);
+
 /* ---- admission / diagnostics ---------------------------------------------
  * Device bytes a context needs for (n_el, p) and a solve of nblock vectors with
  * the given filter block width and precision (pure; no device access). */

@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, Opts, Report
 
-__all__ = ["Context", "ChfsiError", "footprint_bytes", "PRECISIONS", "library_path"]
+__all__ = ["Context", "ChfsiError", "footprint_bytes", "solve_batch", "PRECISIONS", "library_path"]
 
 
 class ChfsiError(RuntimeError):
@@ -36,6 +36,62 @@ def footprint_bytes(n_el: int, p: int, nblock: int, block_width: int = 0, prec: 
 
 def _prec(p) -> int:
     return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _opts(nstates, nblock, degree, tol, max_iter, block_width=0, ladder=("fp64",), ladder_tol=None,
+          mixed_cholgs=False) -> Opts:
+    o = Opts()
+    o.nstates, o.nblock, o.degree, o.max_iter, o.block_width = int(nstates), int(nblock), int(degree), \
+        int(max_iter), int(block_width)
+    o.tol = float(tol)
+    lad = [_prec(x) for x in ladder][:4]
+    for i, v in enumerate(lad):
+        o.ladder[i] = v
+    o.n_ladder = len(lad)
+    for k, v in enumerate(list(ladder_tol or [])[:4]):
+        o.ladder_tol[k] = float(v)
+    o.mixed_cholgs = 1 if mixed_cholgs else 0
+    return o
+
+
+def _report(rep: Report, st: int) -> dict:
+    return dict(status=st, converged=(st == 0), iters=rep.iters, rung=rep.rung, t_filter=rep.t_filter,
+                t_cholgs=rep.t_cholgs, t_rr=rep.t_rr, max_resid=rep.max_resid, dofvecs=rep.dofvecs)
+
+
+def solve_batch(contexts, blocks, nstates, degree: int, tol: float, max_iter: int = 200, prec: str = "fp32",
+                mixed_cholgs: bool = False):
+    """chfsi_solve_batch over problems i (context contexts[i], block blocks[i],
+    nstates[i] wanted states).  Returns a list of per-problem result dicts."""
+    lib = _lib.load()
+    n = len(contexts)
+    if len(blocks) != n or len(nstates) != n:
+        raise ValueError("contexts, blocks and nstates must have the same length")
+    opts = (Opts * n)()
+    ctxs = (C.c_void_p * n)()
+    xs = (C.c_void_p * n)()
+    lds = (C.c_int64 * n)()
+    evs = [np.empty(int(b.shape[1])) for b in blocks]
+    rss = [np.empty(int(b.shape[1])) for b in blocks]
+    evp = (C.c_void_p * n)(*[e.ctypes.data for e in evs])
+    rsp = (C.c_void_p * n)(*[r.ctypes.data for r in rss])
+    reps = (Report * n)()
+    for i, (c, X, N) in enumerate(zip(contexts, blocks, nstates)):
+        px, ld, nb = Context._block(X)
+        opts[i] = _opts(N, nb, degree, tol, max_iter, 0, (prec,), None, mixed_cholgs)
+        ctxs[i] = c._h.value
+        xs[i] = px.value
+        lds[i] = ld
+    st = lib.chfsi_solve_batch(ctxs, n, opts, xs, lds, evp, rsp, reps)
+    if st not in (0, _lib.WARN_NOT_CONVERGED):
+        msg = lib.chfsi_last_error(contexts[0]._h)
+        raise ChfsiError(st, "solve_batch", msg.decode() if msg else "")
+    out = []
+    for i in range(n):
+        d = _report(reps[i], reps[i].status)
+        d.update(evals=evs[i], resid=rss[i])
+        out.append(d)
+    return out
 
 
 class Context:
@@ -210,17 +266,7 @@ class Context:
     def solve(self, X, nstates: int, degree: int, tol: float, max_iter: int = 200, block_width: int = 0,
               ladder=("fp64",), ladder_tol=None, mixed_cholgs: bool = False):
         px, ld, nb = self._block(X)
-        o = Opts()
-        o.nstates, o.nblock, o.degree, o.max_iter, o.block_width = int(nstates), nb, int(degree), int(max_iter), \
-            int(block_width)
-        o.tol = float(tol)
-        lad = [_prec(x) for x in ladder][:4]
-        for i, v in enumerate(lad):
-            o.ladder[i] = v
-        o.n_ladder = len(lad)
-        for k, v in enumerate(list(ladder_tol or [])[:4]):
-            o.ladder_tol[k] = float(v)
-        o.mixed_cholgs = 1 if mixed_cholgs else 0
+        o = _opts(nstates, nb, degree, tol, max_iter, block_width, ladder, ladder_tol, mixed_cholgs)
         ev = np.empty(nb)
         rs = np.empty(nb)
         rep = Report()

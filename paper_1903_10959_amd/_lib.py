@@ -46,6 +46,7 @@ SIGNATURES = {
     "chfsi_orthonormalize": (_int, [_vp, _dp, _i64, _int, _int]),
     "chfsi_rayleigh_ritz": (_int, [_vp, _dp, _i64, _int, _vp, _vp, _dp]),
     "chfsi_solve": (_int, [_vp, C.POINTER(Opts), _dp, _i64, _vp, _vp, C.POINTER(Report)]),
+    "chfsi_solve_batch": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "chfsi_footprint_bytes": (C.c_size_t, [_int, _int, _int, _int, _int]),
     "chfsi_status_string": (C.c_char_p, [_int]),
     "chfsi_last_error": (C.c_char_p, [_vp]),

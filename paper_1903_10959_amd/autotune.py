@@ -1,0 +1,80 @@
+"""Autotuner for the filter's vector-block width.
+
+The paper picks its filtering block size B^f by experiment (Sec. 3.3: too small
+wastes memory bandwidth and latency, too large costs memory and batched-GEMM
+efficiency).  Here the same trade-off is measured on the device: for a live
+problem, a short filter (a few Chebyshev steps) is timed at each candidate
+width and the fastest is cached per (architecture, degree p, block size N_b,
+precision).  Timing uses the context's HIP events on the cell-product kernel
+plus wall time around the call (the filter returns synchronised).
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chfsi_autotune.json")
+
+
+def _key(arch: str, p: int, nblock: int, prec: str) -> str:
+    return f"{arch}|p{p}|nb{nblock}|{prec}"
+
+
+def candidates(nblock: int):
+    c = [w for w in (64, 128, 192, 256, 384, 512) if w < nblock]
+    c.append(nblock)
+    return sorted(set(c))
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str = DEFAULT_CACHE):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def pick(timings: dict) -> int:
+    """Fastest width (ties: the smaller one, which needs less memory)."""
+    return min(timings, key=lambda w: (timings[w], w))
+
+
+def tune_block_width(ctx, X, bounds, prec: str = "fp64", steps: int = 3, arch: str = None,
+                     cache_path: str = DEFAULT_CACHE, refresh: bool = False, timer=None):
+    """Best filter block width for ctx's problem and X's column count.
+
+    bounds = (a, b, a0) of the filter.  X is filtered in place by each trial,
+    so pass a scratch copy.  `timer(width) -> seconds` replaces the device
+    measurement (used by the tests)."""
+    if arch is None:
+        import torch
+
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if timer is None else "test"
+    nb = int(X.shape[1]) if timer is None else int(X)
+    key = _key(arch, int(getattr(ctx, "p", 0)), nb, prec)
+    cache = load_cache(cache_path)
+    if not refresh and key in cache:
+        return int(cache[key]["width"])
+    timings = {}
+    for w in candidates(nb):
+        if timer is not None:
+            timings[w] = float(timer(w))
+            continue
+        a, b, a0 = bounds
+        ctx.chebyshev_filter(X, 1, a, b, a0, prec=prec, block_width=w)   # warm the workspaces
+        t0 = time.perf_counter()
+        ctx.chebyshev_filter(X, steps, a, b, a0, prec=prec, block_width=w)
+        timings[w] = time.perf_counter() - t0
+    best = pick(timings)
+    cache[key] = {"width": best, "timings_s": {str(k): v for k, v in timings.items()}}
+    save_cache(cache, cache_path)
+    return best

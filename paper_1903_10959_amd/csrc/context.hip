@@ -15,61 +15,13 @@
 #include <vector>
 
 #include "../../include/chfsi.h"
+#include "ctx.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
 
 using namespace chfsi;
 
 namespace {
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  hipError_t ensure(size_t want) {
-    if (want <= bytes) return hipSuccess;
-    if (p) {
-      hipError_t e = hipFree(p);
-      p = nullptr;
-      bytes = 0;
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipMalloc(&p, want);
-    if (e == hipSuccess) bytes = want;
-    else p = nullptr;
-    return e;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
-};
-
-}  // namespace
-
-struct chfsi_ctx {
-  int device = 0;           // -1: host-only context (tables only, no device work)
-  hipStream_t stream = nullptr;
-  std::string err;
-  MeshTables mesh;
-  bool has_mesh = false, has_pot = false;
-  double vmax = 0, ub = 0;
-  // device tables
-  DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
-  int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
-  // workspaces
-  DevBuf fbuf[3];      // filter recursion buffers
-  DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
-      rscratch;
-  std::vector<double> host_scratch = std::vector<double>(16);
-  // timing of the cell-product launches
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  int64_t cell_vecs = 0;
-  bool verbose = false;   // CHFSI_VERBOSE: one progress line per solve pass on stderr
-};
 
 // FP32 -> BF16 bits, round to nearest even (finite inputs)
 static uint16_t bf16_rne(float f) {
@@ -86,24 +38,22 @@ static float bf16_to_float(uint16_t h) {
   return f;
 }
 
-static int fail(chfsi_ctx *c, int code, const std::string &msg) {
+}  // namespace
+
+namespace chfsi {
+int fail(chfsi_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
   return code;
 }
 
-#define HIPCHK(ctx, call)                                                                         \
-  do {                                                                                            \
-    hipError_t e_ = (call);                                                                       \
-    if (e_ != hipSuccess)                                                                         \
-      return fail(ctx, e_ == hipErrorOutOfMemory ? CHFSI_ERR_OOM : CHFSI_ERR_HIP,                 \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                             \
-  } while (0)
 
-static int set_dev(chfsi_ctx *c) {
+
+int set_dev(chfsi_ctx *c) {
   if (c->device < 0) return fail(c, CHFSI_ERR_STATE, "host-only context: no device work");
   HIPCHK(c, hipSetDevice(c->device));
   return 0;
 }
+}  // namespace chfsi
 
 // ---------------------------------------------------------------------------
 // lifetime
@@ -198,13 +148,13 @@ extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) {
     mi[i] = 1.0 / std::sqrt(M.mass[i]);
     mi32[i] = (float)mi[i];
   }
-  HIPCHK(c, hipMemcpy(c->cmap.p, M.cmap.data(), M.cmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->cells.p, M.cell_order.data(), M.cell_order.size() * sizeof(int32_t),
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->K64.p, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->K32.p, kp32.data(), kp32.size() * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->minv64.p, mi.data(), mi.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->minv32.p, mi32.data(), mi32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpyAsync(c->cmap.p, M.cmap.data(), M.cmap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->cells.p, M.cell_order.data(), M.cell_order.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->K64.p, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->K32.p, kp32.data(), kp32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->minv64.p, mi.data(), mi.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->minv32.p, mi32.data(), mi32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
   // BF16 hi/lo split of the cell matrix, padded to a multiple of 32 (BF16 MFMA depth)
   c->npb = (int)((nl + 31) / 32 * 32);
   const size_t nb2 = (size_t)c->npb * c->npb;
@@ -218,8 +168,9 @@ extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) {
     }
   HIPCHK(c, c->Kbh.ensure(nb2 * 2));
   HIPCHK(c, c->Kbl.ensure(nb2 * 2));
-  HIPCHK(c, hipMemcpy(c->Kbh.p, kh.data(), nb2 * 2, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->Kbl.p, kl.data(), nb2 * 2, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpyAsync(c->Kbh.p, kh.data(), nb2 * 2, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->Kbl.p, kl.data(), nb2 * 2, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
   c->has_mesh = true;
   return 0;
 }
@@ -275,7 +226,10 @@ extern "C" int chfsi_set_potential(chfsi_ctx *c, const double *v, int64_t n_dof,
   if (c->device >= 0)
     if (int r = set_dev(c)) return r;
   std::vector<double> hv(n_dof);
-  if (v_on_device) HIPCHK(c, hipMemcpy(hv.data(), v, n_dof * sizeof(double), hipMemcpyDeviceToHost));
+  if (v_on_device) {
+    HIPCHK(c, hipMemcpyAsync(hv.data(), v, n_dof * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   else std::memcpy(hv.data(), v, n_dof * sizeof(double));
   double vmax = -INFINITY;
   for (int64_t i = 0; i < n_dof; ++i) {
@@ -292,8 +246,9 @@ extern "C" int chfsi_set_potential(chfsi_ctx *c, const double *v, int64_t n_dof,
   for (int64_t i = 0; i < n_dof; ++i) hv32[i] = (float)hv[i];
   HIPCHK(c, c->V64.ensure(n_dof * sizeof(double)));
   HIPCHK(c, c->V32.ensure(n_dof * sizeof(float)));
-  HIPCHK(c, hipMemcpy(c->V64.p, hv.data(), n_dof * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->V32.p, hv32.data(), n_dof * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpyAsync(c->V64.p, hv.data(), n_dof * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->V32.p, hv32.data(), n_dof * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->vmax = vmax;
   c->ub = 3.0 * c->mesh.lam1d_max + vmax;
   c->has_pot = true;
@@ -424,7 +379,7 @@ static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64
   return 0;
 }
 
-static int check_block(chfsi_ctx *c, const void *X, int64_t ld, int ncols) {
+int chfsi::check_block(chfsi_ctx *c, const void *X, int64_t ld, int ncols) {
   if (!c) return CHFSI_ERR_ARG;
   if (c->device < 0) return fail(c, CHFSI_ERR_STATE, "host-only context: no device work");
   if (!c->has_mesh || !c->has_pot) return fail(c, CHFSI_ERR_STATE, "mesh and potential must be set first");
@@ -547,7 +502,7 @@ extern "C" int chfsi_chebyshev_filter(chfsi_ctx *c, double *X, int64_t ld, int n
 // ---------------------------------------------------------------------------
 // orthonormalize (CholGS)
 // ---------------------------------------------------------------------------
-static int ensure_small(chfsi_ctx *c, int n) {
+int chfsi::ensure_small(chfsi_ctx *c, int n) {
   const size_t nn = (size_t)n * n;
   const int nb = (n + 31) / 32;
   HIPCHK(c, c->Smat.ensure(nn * sizeof(double)));
@@ -607,7 +562,7 @@ extern "C" int chfsi_orthonormalize(chfsi_ctx *c, double *X, int64_t ld, int nco
 // The solve's orthonormalisation: CholGS, repeated while the smallest relative
 // pivot shows lost orthogonality (CholeskyQR2), with the shifted Cholesky QR
 // of Fukaya et al. when the overlap is numerically singular.
-static int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes) {
+int chfsi::orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes) {
   double rmin = 1.0;
   int np = 1;
   int st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin);
@@ -632,7 +587,7 @@ static int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, i
 // ---------------------------------------------------------------------------
 // rayleighRitz
 // ---------------------------------------------------------------------------
-static int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
+int chfsi::rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
                    double *resid, int *sweeps) {
   const int64_t nd = c->mesh.n_dof;
   if (int r = cheb_step_t<double>(c, X, ld, nullptr, 0, HX, ldh, ncols, 1.0, 0.0, 0.0)) return r;

@@ -1,0 +1,86 @@
+// Internal: the context object behind the opaque chfsi_ctx handle and the
+// helpers shared by the single-problem (context.hip) and batched (batch.hip)
+// drivers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/chfsi.h"
+#include "mesh.hpp"
+
+namespace chfsi {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    else p = nullptr;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+
+}  // namespace chfsi
+
+struct chfsi_ctx {
+  int device = 0;           // -1: host-only context (tables only, no device work)
+  hipStream_t stream = nullptr;
+  std::string err;
+  chfsi::MeshTables mesh;
+  bool has_mesh = false, has_pot = false;
+  double vmax = 0, ub = 0;
+  // device tables
+  chfsi::DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
+  int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
+  // workspaces
+  chfsi::DevBuf fbuf[3];      // filter recursion buffers
+  chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
+      rscratch;
+  std::vector<double> host_scratch = std::vector<double>(16);
+  // timing of the cell-product launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int64_t cell_vecs = 0;
+  bool verbose = false;   // CHFSI_VERBOSE: one progress line per solve pass on stderr
+};
+
+
+namespace chfsi {
+
+int fail(chfsi_ctx *c, int code, const std::string &msg);
+int set_dev(chfsi_ctx *c);
+int check_block(chfsi_ctx *c, const void *X, int64_t ld, int ncols);
+int ensure_small(chfsi_ctx *c, int n);
+// the solve's CholGS (CholeskyQR2 / shifted Cholesky QR when needed)
+int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes);
+// Rayleigh-Ritz with HX in a caller buffer; evals/resid on the host
+int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals, double *resid,
+            int *sweeps);
+
+}  // namespace chfsi
+
+#define HIPCHK(ctx, call)                                                                         \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return chfsi::fail(ctx, e_ == hipErrorOutOfMemory ? CHFSI_ERR_OOM : CHFSI_ERR_HIP,          \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                      \
+  } while (0)

@@ -50,28 +50,23 @@ __device__ __forceinline__ int first_touch(int r, int q, int e, int n_el) {
   return (fx && fy && fz) ? 1 : 0;
 }
 
+// The product of one cell and one 64-column tile (called by the single-problem
+// and the batched kernels).
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, int64_t ldx,
-                                                       const T *__restrict__ Xp, int64_t ldp,
-                                                       T *__restrict__ Y, int64_t ldy,
-                                                       const T *__restrict__ K,
-                                                       const int32_t *__restrict__ cmap, int n_loc,
-                                                       int q, int n_el,
-                                                       const int32_t *__restrict__ cells,
-                                                       const T *__restrict__ minv, const T *__restrict__ V,
-                                                       int ncols, int ntiles, T s1, T s2, T shift) {
+__device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp,
+                                          int64_t ldp, T *__restrict__ Y, int64_t ldy, const T *__restrict__ K,
+                                          const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, int e,
+                                          int tile, const T *__restrict__ minv, const T *__restrict__ V, int ncols,
+                                          T s1, T s2, T shift) {
   typedef typename acc4<T>::type acc_t;
   constexpr int RB = CellTile<T, NP>::RB;
   constexpr int RBP = CellTile<T, NP>::RBP;
   __shared__ int32_t dof_s[NP];
   __shared__ T mi_s[NP];
-  __shared__ T vd_s[NP];     // s1 (V - shift) on first-touch rows, NaN marker elsewhere unused
+  __shared__ T vd_s[NP];     // s1 (V - shift) on first-touch rows
   __shared__ int8_t ft_s[NP];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int cell_slot = blockIdx.x / ntiles;
-  const int tile = blockIdx.x - cell_slot * ntiles;
-  const int e = cells[cell_slot];
   for (int r = threadIdx.x; r < NP; r += blockDim.x) {
     int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
     dof_s[r] = d < 0 ? 0 : d;              // clamped: row 0 is always readable
@@ -121,27 +116,38 @@ __global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, 
     }
 
     if (col_ok) {
+      // epilogue in chunks of 4 row blocks: every load of a chunk is issued
+      // before its stores, so 16 rows per lane are in flight at once
 #pragma unroll
-      for (int r = 0; r < RBP; ++r) {
+      for (int r0 = 0; r0 < RBP; r0 += 4) {
+        T old[4][4];
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-          const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
-          if (row < n_loc) {
-            const T w = mi_s[row];
-            if (w != T(0)) {
+        for (int r = r0; r < r0 + 4 && r < RBP; ++r)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
+            T v = T(0);
+            if (row < n_loc && mi_s[row] != T(0)) {
               const int64_t d = dof_s[row];
-              T *yp = Y + d * ldy + col;
-              const T prod = s1 * w * acc[r][qq];
               if (ft_s[row]) {
-                T y = vd_s[row] * X[d * ldx + col] + prod;
-                if (Xp) y += s2 * Xp[d * ldp + col];
-                *yp = y;
+                v = vd_s[row] * X[d * ldx + col];
+                if (Xp) v += s2 * Xp[d * ldp + col];
               } else {
-                *yp += prod;
+                v = Y[d * ldy + col];
               }
             }
+            old[r - r0][qq] = v;
           }
-        }
+#pragma unroll
+        for (int r = r0; r < r0 + 4 && r < RBP; ++r)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
+            if (row < n_loc) {
+              const T w = mi_s[row];
+              if (w != T(0)) Y[(int64_t)dof_s[row] * ldy + col] = old[r - r0][qq] + s1 * w * acc[r][qq];
+            }
+          }
       }
     }
   }
@@ -189,26 +195,42 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
     vd_s[r] = ft ? s1 * (V[d] - shift) : 0.f;
   }
   __syncthreads();
-  // stage: 4 consecutive columns per thread per row (16-byte global loads when aligned)
+  // stage: 4 consecutive columns per thread per row (16-byte global loads when
+  // aligned), SU rows per thread per round with every load issued first
   const bool vec_ok = ((ldx & 3) == 0) && ((col0 & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
-  for (int idx = threadIdx.x; idx < NPB * 16; idx += blockDim.x) {
-    const int r = idx >> 4, c4 = (idx & 15) * 4;
-    const float w = mi_s[r];
-    float v[4];
-    const float *src = X + (int64_t)dof_s[r] * ldx + col0 + c4;
-    if (vec_ok && col0 + c4 + 3 < ncols) {
-      const float4 t = *reinterpret_cast<const float4 *>(src);
-      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    } else {
+  constexpr int SU = 8;
+  for (int base = threadIdx.x; base < NPB * 16; base += SU * 256) {
+    float v[SU][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = (col0 + c4 + u < ncols) ? src[u] : 0.f;
+    for (int u = 0; u < SU; ++u) {
+      const int idx = base + u * 256;
+      v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.f;
+      if (idx < NPB * 16) {
+        const int r = idx >> 4, c4 = (idx & 15) * 4;
+        const float *src = X + (int64_t)dof_s[r] * ldx + col0 + c4;
+        if (vec_ok && col0 + c4 + 3 < ncols) {
+          const float4 t = *reinterpret_cast<const float4 *>(src);
+          v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
+        } else {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) v[u][w] = (col0 + c4 + w < ncols) ? src[w] : 0.f;
+        }
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float x = v[u] * w;
-      const __bf16 h = (__bf16)x;
-      xs[0][(c4 + u) * LDX + r] = h;
-      if (SPLIT) xs[NPART - 1][(c4 + u) * LDX + r] = (__bf16)(x - (float)h);
+    for (int u = 0; u < SU; ++u) {
+      const int idx = base + u * 256;
+      if (idx < NPB * 16) {
+        const int r = idx >> 4, c4 = (idx & 15) * 4;
+        const float w = mi_s[r];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float x = v[u][t] * w;
+          const __bf16 h = (__bf16)x;
+          xs[0][(c4 + t) * LDX + r] = h;
+          if (SPLIT) xs[NPART - 1][(c4 + t) * LDX + r] = (__bf16)(x - (float)h);
+        }
+      }
     }
   }
   __syncthreads();
@@ -246,26 +268,36 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   }
   if (col >= ncols) return;
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
+  for (int r0 = 0; r0 < RB; r0 += 4) {
+    float old[4][4];
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int row = r * 16 + acc_row<float>(kq, qq);
-      if (row < n_loc) {
-        const float w = mi_s[row];
-        if (w != 0.f) {
+    for (int r = r0; r < r0 + 4 && r < RB; ++r)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int row = r * 16 + acc_row<float>(kq, qq);
+        float v = 0.f;
+        if (row < n_loc && mi_s[row] != 0.f) {
           const int64_t d = dof_s[row];
-          float *yp = Y + d * ldy + col;
-          const float prod = s1 * w * acc[r][qq];
           if (ft_s[row]) {
-            float y = vd_s[row] * X[d * ldx + col] + prod;
-            if (Xp) y += s2 * Xp[d * ldp + col];
-            *yp = y;
+            v = vd_s[row] * X[d * ldx + col];
+            if (Xp) v += s2 * Xp[d * ldp + col];
           } else {
-            *yp += prod;
+            v = Y[d * ldy + col];
           }
         }
+        old[r - r0][qq] = v;
       }
-    }
+#pragma unroll
+    for (int r = r0; r < r0 + 4 && r < RB; ++r)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int row = r * 16 + acc_row<float>(kq, qq);
+        if (row < n_loc) {
+          const float w = mi_s[row];
+          if (w != 0.f) Y[(int64_t)dof_s[row] * ldy + col] = old[r - r0][qq] + s1 * w * acc[r][qq];
+        }
+      }
+  }
 }
 
 template <int NPB, bool SPLIT>
@@ -295,6 +327,65 @@ static int dispatch_bf16(const HxBf16Args &a, int cb, int ce, hipStream_t s) {
 int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
   return a.split ? dispatch_bf16<true>(a, color_begin, color_end, s) : dispatch_bf16<false>(a, color_begin, color_end, s);
 }
+
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, int64_t ldx,
+                                                       const T *__restrict__ Xp, int64_t ldp,
+                                                       T *__restrict__ Y, int64_t ldy,
+                                                       const T *__restrict__ K,
+                                                       const int32_t *__restrict__ cmap, int n_loc,
+                                                       int q, int n_el,
+                                                       const int32_t *__restrict__ cells,
+                                                       const T *__restrict__ minv, const T *__restrict__ V,
+                                                       int ncols, int ntiles, T s1, T s2, T shift) {
+  const int cell_slot = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - cell_slot * ntiles;
+  cell_tile<T, NP>(X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V, ncols, s1, s2,
+                   shift);
+}
+
+// Batched: work item = (problem, cell, column tile); the step's buffer roles
+// (input, previous, output) are the same for every problem, its coefficients
+// come from the problem's table (s1, s2, shift per step).
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void hx_cells_batch_kernel(const BatchProblem<T> *__restrict__ probs,
+                                                             const int4 *__restrict__ work, int step, int cur,
+                                                             int prev, int out) {
+  const int4 w = work[blockIdx.x];
+  const BatchProblem<T> &P = probs[w.x];
+  const T *coef = P.coef + 3 * step;
+  cell_tile<T, NP>(P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
+                   P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el, w.y, w.z, P.minv, P.V, P.ncols,
+                   coef[0], coef[1], coef[2]);
+}
+
+template <typename T, int NP>
+static void launch_batch(const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur, int prev,
+                         int out, hipStream_t s) {
+  if (nwork <= 0) return;
+  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP>), dim3((unsigned)nwork), dim3(256), 0, s, probs, work, step, cur,
+                     prev, out);
+}
+
+template <typename T>
+int hx_cells_batch_launch(int np, const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur,
+                          int prev, int out, hipStream_t s) {
+  switch (np) {
+    case 16: launch_batch<T, 16>(probs, work, nwork, step, cur, prev, out, s); break;
+    case 32: launch_batch<T, 32>(probs, work, nwork, step, cur, prev, out, s); break;
+    case 64: launch_batch<T, 64>(probs, work, nwork, step, cur, prev, out, s); break;
+    case 128: launch_batch<T, 128>(probs, work, nwork, step, cur, prev, out, s); break;
+    case 224: launch_batch<T, 224>(probs, work, nwork, step, cur, prev, out, s); break;
+    case 352: launch_batch<T, 352>(probs, work, nwork, step, cur, prev, out, s); break;
+    case 512: launch_batch<T, 512>(probs, work, nwork, step, cur, prev, out, s); break;
+    default: return -1;
+  }
+  return 0;
+}
+template int hx_cells_batch_launch<double>(int, const BatchProblem<double> *, const int4 *, int, int, int, int, int,
+                                           hipStream_t);
+template int hx_cells_batch_launch<float>(int, const BatchProblem<float> *, const int4 *, int, int, int, int, int,
+                                          hipStream_t);
 
 template <typename T, int NP>
 static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {

@@ -27,6 +27,24 @@ struct HxArgs {
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s);
+
+// One problem of a batched filter sweep (device-resident descriptor).
+template <typename T>
+struct BatchProblem {
+  T *buf[3];           // the three rotating recursion buffers
+  int64_t ld[3];
+  const T *K;          // padded cell stiffness
+  const int32_t *cmap;
+  const T *minv, *V;
+  const T *coef;       // [degree x 3]: s1, s2, shift per step
+  int n_loc, q, n_el, ncols;
+};
+// Launch one Chebyshev step for a list of (problem, cell, column tile) work
+// items (int4: x = problem, y = cell, z = tile) whose problems share the padded
+// cell size np.
+template <typename T>
+int hx_cells_batch_launch(int np, const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur,
+                          int prev, int out, hipStream_t s);
 // BF16 cell products: FP32 X/Y/minv, K_ref as BF16 hi (and lo when split),
 // padded to npb = round_up(n_loc, 32).
 struct HxBf16Args {

@@ -1,0 +1,35 @@
+"""Autotuner cache and selection logic (CPU, with a synthetic timer)."""
+from paper_1903_10959_amd import autotune as AT
+
+
+class _Ctx:
+    p = 6
+
+
+def test_candidates_cover_the_block():
+    assert AT.candidates(568) == [64, 128, 192, 256, 384, 512, 568]
+    assert AT.candidates(24) == [24]
+
+
+def test_tuner_picks_fastest_and_caches(tmp_path):
+    path = str(tmp_path / "cache.json")
+    calls = []
+
+    def timer(w):
+        calls.append(w)
+        return abs(w - 192) + 1.0      # fastest at 192
+
+    assert AT.tune_block_width(_Ctx(), 568, None, "fp64", cache_path=path, timer=timer, arch="gfx950") == 192
+    n = len(calls)
+    # cached: no new timings
+    assert AT.tune_block_width(_Ctx(), 568, None, "fp64", cache_path=path, timer=timer, arch="gfx950") == 192
+    assert len(calls) == n
+    # a different precision is a different key
+    AT.tune_block_width(_Ctx(), 568, None, "fp32", cache_path=path, timer=timer, arch="gfx950")
+    assert len(calls) > n
+    c = AT.load_cache(path)
+    assert set(c) == {"gfx950|p6|nb568|fp64", "gfx950|p6|nb568|fp32"}
+
+
+def test_ties_prefer_the_smaller_width():
+    assert AT.pick({128: 1.0, 256: 1.0, 64: 2.0}) == 128
