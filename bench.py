@@ -136,15 +136,14 @@ def batch_throughput(args):
 def served_stream(args):
     """Served stream: seeded Poisson arrivals of solve requests (sizes of the
     batched workload), 5 warm-started solves each with a 1 % perturbed
-    potential, HBM-footprint admission, concurrent slots; p50/p99 latency."""
+    potential, HBM-footprint admission, continuous batching; p50/p99 latency."""
     import torch
 
     from paper_1903_10959_amd import serve as S
 
     reqs = S.make_stream(args.requests, args.rate, seed=5)
     t0 = time.time()
-    S.serve(reqs, slots=args.slots, hbm_budget=args.hbm_budget, solves=5, tol=args.tol, degree=20,
-            ladder=("fp32", "fp64"),
+    S.serve(reqs, hbm_budget=args.hbm_budget, solves=5, tol=args.tol, degree=20, ladder=("fp32", "fp64"),
             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     wall = time.time() - t0
@@ -154,7 +153,7 @@ def served_stream(args):
            "value": st["e2e_p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
            "dtype": "fp32-filter->f64", "data": "synthetic",
            "config": {"workload": f"served: {args.requests} requests, Poisson rate {args.rate}/s, sizes of the "
-                                  f"batched workload, 5 solves each to residual {args.tol} Ha, {args.slots} slots, "
+                                  f"batched workload, 5 solves each to residual {args.tol} Ha, continuous batching, "
                                   f"HBM budget {args.hbm_budget / 1e9:.0f} GB"},
            "latency": st, "throughput_dofvecs_per_s": dofvecs / wall, "wall_s": wall}
     print(json.dumps(out), flush=True)
@@ -227,7 +226,6 @@ def main():
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate per second")
-    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent slots")
     ap.add_argument("--hbm-budget", type=float, default=160e9, help="serve: device bytes for admitted requests")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run a plain elementwise copy (y = x * 1) of this many bytes, three times: "

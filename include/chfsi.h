@@ -177,8 +177,8 @@ int chfsi_solve(chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
  * Sec. 3.7, placed on one device) ---------------------------------------------
  * ctxs[i] holds problem i's mesh and potential (one context per problem, all
  * on the same device; distinct streams let the per-problem CholGS/RR overlap).
- * Every problem uses the same Chebyshev degree and filter precision
- * (opts[i].ladder[0]: FP64 or FP32; CholGS/RR are FP64).  Each pass runs one
+ * Every problem uses the same Chebyshev degree; each follows its own ladder
+ * of FP32/FP64 filter rungs (CholGS/RR are FP64).  Each pass runs one
  * Chebyshev step of all active problems in shared launches (one per padded
  * cell size and colour) captured once per active set in a HIP graph, then
  * CholGS + RR per problem on host threads; a problem leaves the batch when its
@@ -188,6 +188,30 @@ int chfsi_solve(chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
  * Returns CHFSI_WARN_NOT_CONVERGED if any problem did not converge. */
 int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts *opts, double *const *X,
                       const int64_t *ld, double *const *evals, double *const *resid, chfsi_report *reps);
+
+/* ---- batch session (continuous batching) ----------------------------------
+ * A session holds a changing set of problems that share the batched sweeps of
+ * chfsi_solve_batch.  chfsi_batch_add puts a problem in (its context, options,
+ * block and host result arrays must stay valid until it leaves); it starts at
+ * the next pass with CholGS + RR of its block (a warm start needs nothing
+ * else).  chfsi_batch_pass runs one pass for every problem in the session:
+ * a degree-m filter (problems on their FP32 rung share one graph-captured
+ * sweep, problems on the FP64 rung another), then CholGS + RR per problem;
+ * problems whose wanted residuals are <= tol, or that reached max_iter, leave
+ * and their ids are written to done_ids (at most max_done; the rest are
+ * reported by later calls).  Each problem follows its own precision ladder
+ * (FP32 and FP64 rungs only; rung thresholds as in chfsi_solve).
+ * A problem's results do not depend on which other problems share its passes. */
+typedef struct chfsi_batch chfsi_batch;
+int chfsi_batch_create(chfsi_batch **out, int device);
+int chfsi_batch_destroy(chfsi_batch *b);
+/* returns the problem id (>= 0) or an error status (< 0) */
+int chfsi_batch_add(chfsi_batch *b, chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
+                    double *evals, double *resid);
+/* returns the number of problems still in the session (>= 0) or an error */
+int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int max_done);
+int chfsi_batch_report(const chfsi_batch *b, int id, chfsi_report *rep);
+const char *chfsi_batch_last_error(const chfsi_batch *b);
 
 /* ---- admission / diagnostics ---------------------------------------------
  * Device bytes a context needs for (n_el, p) and a solve of nblock vectors with

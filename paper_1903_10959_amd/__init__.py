@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, Opts, Report
 
-__all__ = ["Context", "ChfsiError", "footprint_bytes", "solve_batch", "PRECISIONS", "library_path"]
+__all__ = ["Context", "ChfsiError", "footprint_bytes", "solve_batch", "BatchSession", "PRECISIONS", "library_path"]
 
 
 class ChfsiError(RuntimeError):
@@ -57,6 +57,63 @@ def _opts(nstates, nblock, degree, tol, max_iter, block_width=0, ladder=("fp64",
 def _report(rep: Report, st: int) -> dict:
     return dict(status=st, converged=(st == 0), iters=rep.iters, rung=rep.rung, t_filter=rep.t_filter,
                 t_cholgs=rep.t_cholgs, t_rr=rep.t_rr, max_resid=rep.max_resid, dofvecs=rep.dofvecs)
+
+
+class BatchSession:
+    """chfsi_batch_*: problems join (add) and leave (when converged) between
+    passes; every pass runs their filters in shared graph-captured sweeps."""
+
+    def __init__(self, device: int = 0):
+        self._lib = _lib.load()
+        h = C.c_void_p()
+        st = self._lib.chfsi_batch_create(C.byref(h), device)
+        if st != 0:
+            raise ChfsiError(st, "chfsi_batch_create", "invalid device or no GPU")
+        self._h = h
+        self._keep = {}     # id -> (opts, evals, resid, X, ctx): alive while in the session
+        self._done = (C.c_int * 4096)()
+
+    def add(self, ctx, X, nstates: int, degree: int, tol: float, max_iter: int = 200, ladder=("fp32", "fp64"),
+            mixed_cholgs: bool = False) -> int:
+        px, ld, nb = Context._block(X)
+        o = _opts(nstates, nb, degree, tol, max_iter, 0, ladder, None, mixed_cholgs)
+        ev, rs = np.empty(nb), np.empty(nb)
+        pid = self._lib.chfsi_batch_add(self._h, ctx._h, C.byref(o), px, ld, ev.ctypes.data_as(C.c_void_p),
+                                       rs.ctypes.data_as(C.c_void_p))
+        if pid < 0:
+            msg = self._lib.chfsi_batch_last_error(self._h)
+            raise ChfsiError(pid, "chfsi_batch_add", msg.decode() if msg else "")
+        self._keep[pid] = (o, ev, rs, X, ctx)
+        return pid
+
+    def step(self):
+        """One pass; returns (remaining, [(id, result dict), ...] of problems that left)."""
+        nd = C.c_int()
+        rem = self._lib.chfsi_batch_pass(self._h, self._done, C.byref(nd), len(self._done))
+        if rem < 0:
+            msg = self._lib.chfsi_batch_last_error(self._h)
+            raise ChfsiError(rem, "chfsi_batch_pass", msg.decode() if msg else "")
+        out = []
+        for k in range(nd.value):
+            pid = int(self._done[k])
+            rep = Report()
+            self._lib.chfsi_batch_report(self._h, pid, C.byref(rep))
+            o, ev, rs, X, ctx = self._keep.pop(pid)
+            d = _report(rep, rep.status)
+            d.update(evals=ev, resid=rs)
+            out.append((pid, d))
+        return rem, out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.chfsi_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve_batch(contexts, blocks, nstates, degree: int, tol: float, max_iter: int = 200, prec: str = "fp32",

@@ -47,6 +47,12 @@ SIGNATURES = {
     "chfsi_rayleigh_ritz": (_int, [_vp, _dp, _i64, _int, _vp, _vp, _dp]),
     "chfsi_solve": (_int, [_vp, C.POINTER(Opts), _dp, _i64, _vp, _vp, C.POINTER(Report)]),
     "chfsi_solve_batch": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "chfsi_batch_create": (_int, [C.POINTER(C.c_void_p), _int]),
+    "chfsi_batch_destroy": (_int, [_vp]),
+    "chfsi_batch_add": (_int, [_vp, _vp, C.POINTER(Opts), _dp, _i64, _vp, _vp]),
+    "chfsi_batch_pass": (_int, [_vp, _vp, C.POINTER(C.c_int), _int]),
+    "chfsi_batch_report": (_int, [_vp, _int, C.POINTER(Report)]),
+    "chfsi_batch_last_error": (C.c_char_p, [_vp]),
     "chfsi_footprint_bytes": (C.c_size_t, [_int, _int, _int, _int, _int]),
     "chfsi_status_string": (C.c_char_p, [_int]),
     "chfsi_last_error": (C.c_char_p, [_vp]),

@@ -1,11 +1,12 @@
-// Batched ChFSI over many independent problems (the paper's k-point groups on
-// one device): one Chebyshev step of every active problem runs in shared
-// launches, one per (padded cell size, colour), from a device work list of
-// (problem, cell, column tile) items.  The whole degree-m sweep of an active
-// set is captured once in a HIP graph and replayed every pass; only the
-// per-problem recursion coefficients change between passes and are copied to
-// the device before each replay.  CholGS and Rayleigh-Ritz run per problem on
-// host threads, each problem on its own context (and stream).
+// Batched ChFSI over many independent problems (the paper's k-point groups,
+// placed on one device), as a session whose membership changes between passes
+// (continuous batching).  One Chebyshev step of every problem in a precision
+// group runs in shared launches, one per (padded cell size, colour), from a
+// device work list of (problem, cell, column tile) items.  The degree-m sweep
+// of a group is captured once per membership in a HIP graph and replayed each
+// pass; only the per-problem recursion coefficients change between passes and
+// are copied to the device before the replay.  CholGS and Rayleigh-Ritz run
+// per problem on host threads, each problem on its own context and stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <thread>
 #include <vector>
@@ -24,21 +26,20 @@ using namespace chfsi;
 
 namespace {
 
-struct Item {
-  int idx;          // problem index in the batch
-  chfsi_ctx *c;
-  const chfsi_opts *o;
-  double *X;
-  int64_t ld;
-  double *evals, *resid;
+struct Prob {
+  int id = -1;
+  chfsi_ctx *c = nullptr;
+  chfsi_opts o;
+  double *X = nullptr;
+  int64_t ld = 0;
+  double *evals = nullptr, *resid = nullptr;
   chfsi_report rep;
-  int status = 0;
-  bool active = true;
+  bool started = false, done = false;
+  int rung = 0;
   double res = INFINITY;
 };
 
-// run fn(i) for i in [0, n) on up to `threads` host threads; returns the
-// first non-zero status
+// run fn(i) for i in [0, n) on up to `threads` host threads; first non-zero status
 template <typename F>
 int parallel_for(int n, int threads, F fn) {
   std::atomic<int> next(0), first_err(0);
@@ -61,36 +62,20 @@ int parallel_for(int n, int threads, F fn) {
   return first_err.load();
 }
 
-double max_wanted(const Item &it) {
+chfsi_prec rung_prec(const Prob &p) { return p.o.n_ladder > 0 ? p.o.ladder[p.rung] : CHFSI_FP64; }
+int n_rungs(const Prob &p) { return std::max(1, std::min(p.o.n_ladder, 4)); }
+int mixed_now(const Prob &p) {
+  return (p.o.mixed_cholgs && (p.o.n_ladder <= 1 || p.rung + 1 < n_rungs(p))) ? 1 : 0;
+}
+double rung_tol(const Prob &p) {
+  if (p.o.ladder_tol[p.rung] > 0) return p.o.ladder_tol[p.rung];
+  return rung_prec(p) == CHFSI_FP32 ? 4.0 * 0x1p-24 * p.c->ub : 0.0;
+}
+double max_wanted(const Prob &p) {
   double m = 0;
-  for (int i = 0; i < it.o->nstates; ++i) m = std::max(m, it.resid[i]);
+  for (int i = 0; i < p.o.nstates; ++i) m = std::max(m, p.resid[i]);
   return m;
 }
-
-template <typename T>
-struct Sweep {
-  int degree = 0;
-  hipStream_t stream = nullptr;
-  DevBuf probs, work, coef;
-  std::vector<int> members;                          // item indices in this active set
-  std::vector<std::pair<int, int>> groups;           // (np, colour) -> launch
-  std::vector<int> goff, gcnt;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int final_buf = 0;
-  void drop_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-  }
-  ~Sweep() {
-    drop_graph();
-    probs.release();
-    work.release();
-    coef.release();
-  }
-};
 
 // recursion roles at step k: (cur, prev, out) of the three buffers
 void roles(int degree, std::vector<int> &cur, std::vector<int> &prev, std::vector<int> &out, int &final_buf) {
@@ -111,24 +96,71 @@ void roles(int degree, std::vector<int> &cur, std::vector<int> &prev, std::vecto
 }
 
 template <typename T>
-int build_sweep(Sweep<T> &S, std::vector<Item> &items, chfsi_ctx *c0) {
+struct Sweep {
+  DevBuf probs, work, coef;
+  std::vector<int> members;      // problem ids of the captured graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<T> hcoef;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    members.clear();
+  }
+  void release() {
+    drop_graph();
+    probs.release();
+    work.release();
+    coef.release();
+  }
+};
+
+}  // namespace
+
+struct chfsi_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int degree = 0;
+  std::vector<Prob> probs;       // indexed by id
+  std::deque<int> finished;      // ids that left and are not reported yet
+  Sweep<double> s64;
+  Sweep<float> s32;
+  bool verbose = false;
+  int threads = 8;
+};
+
+namespace {
+
+int bfail(chfsi_batch *b, int code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define BCHK(b, call)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return bfail(b, e_ == hipErrorOutOfMemory ? CHFSI_ERR_OOM : CHFSI_ERR_HIP,                   \
+                   std::string(#call) + ": " + hipGetErrorString(e_));                             \
+  } while (0)
+
+template <typename T>
+int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
   S.drop_graph();
-  S.members.clear();
-  for (auto &it : items)
-    if (it.active) S.members.push_back(it.idx);
-  if (S.members.empty()) return 0;
-  // descriptors
+  if (ids.empty()) return 0;
+  const bool f64 = sizeof(T) == 8;
   std::vector<BatchProblem<T>> hp;
   std::map<std::pair<int, int>, std::vector<int4>> lists;  // (np, colour) -> items
-  size_t coef_elems = 0;
-  for (size_t m = 0; m < S.members.size(); ++m) {
-    Item &it = items[S.members[m]];
-    chfsi_ctx *c = it.c;
-    const int nb = it.o->nblock;
+  for (size_t m = 0; m < ids.size(); ++m) {
+    Prob &p = B->probs[ids[m]];
+    chfsi_ctx *c = p.c;
+    const int nb = p.o.nblock;
     BatchProblem<T> P;
-    const bool f64 = sizeof(T) == 8;
-    P.buf[0] = f64 ? (T *)it.X : c->fbuf[0].as<T>();
-    P.ld[0] = f64 ? it.ld : nb;
+    P.buf[0] = f64 ? (T *)p.X : c->fbuf[0].as<T>();
+    P.ld[0] = f64 ? p.ld : nb;
     P.buf[1] = c->fbuf[1].as<T>();
     P.buf[2] = c->fbuf[2].as<T>();
     P.ld[1] = P.ld[2] = nb;
@@ -136,229 +168,299 @@ int build_sweep(Sweep<T> &S, std::vector<Item> &items, chfsi_ctx *c0) {
     P.cmap = c->cmap.as<int32_t>();
     P.minv = f64 ? (const T *)c->minv64.p : (const T *)c->minv32.p;
     P.V = f64 ? (const T *)c->V64.p : (const T *)c->V32.p;
-    P.coef = nullptr;  // set after the coefficient buffer exists
+    P.coef = nullptr;
     P.n_loc = c->mesh.n_loc;
     P.q = c->mesh.q;
     P.n_el = c->mesh.n_el;
     P.ncols = nb;
     hp.push_back(P);
-    coef_elems += (size_t)3 * S.degree;
     const int ntiles = (nb + 63) / 64;
     for (int col = 0; col < 8; ++col)
       for (int s = c->mesh.color_offset[col]; s < c->mesh.color_offset[col + 1]; ++s)
         for (int t = 0; t < ntiles; ++t)
           lists[{c->mesh.np, col}].push_back(make_int4((int)m, c->mesh.cell_order[s], t, 0));
   }
-  HIPCHK(c0, S.coef.ensure(coef_elems * sizeof(T)));
-  for (size_t m = 0; m < hp.size(); ++m) hp[m].coef = S.coef.template as<T>() + (size_t)3 * S.degree * m;
+  BCHK(B, S.coef.ensure((size_t)3 * B->degree * ids.size() * sizeof(T)));
+  for (size_t m = 0; m < hp.size(); ++m) hp[m].coef = S.coef.template as<T>() + (size_t)3 * B->degree * m;
   std::vector<int4> all;
-  S.groups.clear();
-  S.goff.clear();
-  S.gcnt.clear();
-  // launch order: colour-major, so every problem sees its colours in order
+  std::vector<std::pair<int, int>> groups;  // (np, offset)
+  std::vector<int> counts;
+  // colour-major launch order: every problem sees its colours in order 0..7
   for (int col = 0; col < 8; ++col)
     for (auto &kv : lists)
       if (kv.first.second == col) {
-        S.groups.push_back(kv.first);
-        S.goff.push_back((int)all.size());
-        S.gcnt.push_back((int)kv.second.size());
+        groups.push_back({kv.first.first, (int)all.size()});
+        counts.push_back((int)kv.second.size());
         all.insert(all.end(), kv.second.begin(), kv.second.end());
       }
-  HIPCHK(c0, S.probs.ensure(hp.size() * sizeof(BatchProblem<T>)));
-  HIPCHK(c0, S.work.ensure(all.size() * sizeof(int4)));
-  HIPCHK(c0, hipMemcpyAsync(S.probs.p, hp.data(), hp.size() * sizeof(BatchProblem<T>), hipMemcpyHostToDevice,
-                            S.stream));
-  HIPCHK(c0, hipMemcpyAsync(S.work.p, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, S.stream));
-  HIPCHK(c0, hipStreamSynchronize(S.stream));
-  // capture the sweep
+  BCHK(B, S.probs.ensure(hp.size() * sizeof(BatchProblem<T>)));
+  BCHK(B, S.work.ensure(all.size() * sizeof(int4)));
+  BCHK(B, hipMemcpyAsync(S.probs.p, hp.data(), hp.size() * sizeof(BatchProblem<T>), hipMemcpyHostToDevice, B->stream));
+  BCHK(B, hipMemcpyAsync(S.work.p, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, B->stream));
+  BCHK(B, hipStreamSynchronize(B->stream));
   std::vector<int> cur, prev, out;
-  roles(S.degree, cur, prev, out, S.final_buf);
-  HIPCHK(c0, hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
-  if (sizeof(T) == 4)
-    for (int m : S.members) {
-      Item &it = items[m];
-      copy_cols_launch<double, float>(it.X, it.ld, it.c->fbuf[0].as<float>(), it.o->nblock, it.c->mesh.n_dof,
-                                      it.o->nblock, S.stream);
+  int final_buf = 0;
+  roles(B->degree, cur, prev, out, final_buf);
+  BCHK(B, hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+  if (!f64)
+    for (int id : ids) {
+      Prob &p = B->probs[id];
+      copy_cols_launch<double, float>(p.X, p.ld, p.c->fbuf[0].as<float>(), p.o.nblock, p.c->mesh.n_dof, p.o.nblock,
+                                      B->stream);
     }
   int lerr = 0;
-  for (int k = 0; k < S.degree; ++k)
-    for (size_t g = 0; g < S.groups.size(); ++g)
-      lerr |= hx_cells_batch_launch<T>(S.groups[g].first, S.probs.template as<BatchProblem<T>>(), S.work.template as<int4>() + S.goff[g],
-                                       S.gcnt[g], k, cur[k], prev[k], out[k], S.stream);
-  for (size_t m = 0; m < S.members.size(); ++m) {
-    Item &it = items[S.members[m]];
-    const BatchProblem<T> &P = hp[m];
-    if (sizeof(T) == 4)
-      copy_cols_launch<float, double>((const float *)P.buf[S.final_buf], P.ld[S.final_buf], it.X, it.ld,
-                                      it.c->mesh.n_dof, it.o->nblock, S.stream);
-    else if (S.final_buf != 0)
-      copy_cols_launch<double, double>((const double *)P.buf[S.final_buf], P.ld[S.final_buf], it.X, it.ld,
-                                       it.c->mesh.n_dof, it.o->nblock, S.stream);
+  for (int k = 0; k < B->degree; ++k)
+    for (size_t g = 0; g < groups.size(); ++g)
+      lerr |= hx_cells_batch_launch<T>(groups[g].first, S.probs.template as<BatchProblem<T>>(),
+                                       S.work.template as<int4>() + groups[g].second, counts[g], k, cur[k], prev[k],
+                                       out[k], B->stream);
+  for (size_t m = 0; m < ids.size(); ++m) {
+    Prob &p = B->probs[ids[m]];
+    if (!f64)
+      copy_cols_launch<float, double>((const float *)hp[m].buf[final_buf], hp[m].ld[final_buf], p.X, p.ld,
+                                      p.c->mesh.n_dof, p.o.nblock, B->stream);
+    else if (final_buf != 0)
+      copy_cols_launch<double, double>((const double *)hp[m].buf[final_buf], hp[m].ld[final_buf], p.X, p.ld,
+                                       p.c->mesh.n_dof, p.o.nblock, B->stream);
   }
-  hipError_t ce = hipStreamEndCapture(S.stream, &S.graph);
-  if (ce != hipSuccess) return fail(c0, CHFSI_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-  if (lerr) return fail(c0, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
-  HIPCHK(c0, hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
+  hipError_t ce = hipStreamEndCapture(B->stream, &S.graph);
+  if (ce != hipSuccess) return bfail(B, CHFSI_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  if (lerr) return bfail(B, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
+  BCHK(B, hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
+  S.members = ids;
   return 0;
 }
 
 template <typename T>
-int run_batch(std::vector<Item> &items, int degree, int max_iter, int threads, chfsi_ctx *c0) {
-  Sweep<T> S;
-  S.degree = degree;
-  HIPCHK(c0, hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
-  struct StreamGuard {
-    hipStream_t s;
-    ~StreamGuard() {
-      if (s) (void)hipStreamDestroy(s);
-    }
-  } sg{S.stream};
-  // start: CholGS + RR of every start block
-  int st = parallel_for((int)items.size(), threads, [&](int i) {
-    Item &it = items[i];
-    if (int r = set_dev(it.c)) return r;
-    int passes = 0;
-    if (int r = orth_robust(it.c, it.X, it.ld, it.o->nblock, 0, &passes)) return r;
-    if (int r = rr_impl(it.c, it.X, it.ld, it.o->nblock, it.c->HX.as<double>(), it.o->nblock, it.evals, it.resid,
-                        nullptr))
-      return r;
-    it.res = max_wanted(it);
-    it.active = it.res > it.o->tol && it.o->max_iter > 0;
-    return 0;
-  });
-  if (st) return st;
-  std::vector<int> last_members;
-  std::vector<T> hcoef;
-  for (int pass = 0; pass < max_iter; ++pass) {
-    std::vector<int> members;
-    for (auto &it : items)
-      if (it.active) members.push_back(it.idx);
-    if (members.empty()) break;
-    if (members != last_members) {
-      if (int r = build_sweep<T>(S, items, c0)) return r;
-      last_members = members;
-    }
-    // per-problem coefficients of the normalised recursion
-    hcoef.assign((size_t)3 * degree * members.size(), T(0));
-    for (size_t m = 0; m < members.size(); ++m) {
-      Item &it = items[members[m]];
-      const int nb = it.o->nblock;
-      const double a = it.evals[nb - 1], a0 = it.evals[0], b = it.c->ub;
-      if (!(a0 < a && a < b)) return fail(c0, CHFSI_ERR_NONFINITE, "batch: Ritz values outside the filter bounds");
-      const double cc = 0.5 * (a + b), e = 0.5 * (b - a), xi0 = (a0 - cc) / e;
-      double rho = 1.0 / xi0;
-      T *tc = hcoef.data() + (size_t)3 * degree * m;
-      for (int k = 0; k < degree; ++k) {
-        double s1, s2;
-        if (k == 0) {
-          s1 = rho / e;
-          s2 = 0.0;
-        } else {
-          const double rn = 1.0 / (2.0 * xi0 - rho);
-          s1 = 2.0 * rn / e;
-          s2 = -rn * rho;
-          rho = rn;
-        }
-        tc[3 * k] = (T)s1;
-        tc[3 * k + 1] = (T)s2;
-        tc[3 * k + 2] = (T)cc;
+int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *ms_out) {
+  *ms_out = 0;
+  if (ids.empty()) return 0;
+  if (ids != S.members)
+    if (int r = build_sweep<T>(B, S, ids)) return r;
+  const int m_deg = B->degree;
+  S.hcoef.assign((size_t)3 * m_deg * ids.size(), T(0));
+  for (size_t m = 0; m < ids.size(); ++m) {
+    Prob &p = B->probs[ids[m]];
+    const int nb = p.o.nblock;
+    const double a = p.evals[nb - 1], a0 = p.evals[0], b = p.c->ub;
+    if (!(a0 < a && a < b)) return bfail(B, CHFSI_ERR_NONFINITE, "batch: Ritz values outside the filter bounds");
+    // normalised recursion: rho_1 = 1/xi0, rho_{k+1} = 1/(2 xi0 - rho_k)
+    const double cc = 0.5 * (a + b), e = 0.5 * (b - a), xi0 = (a0 - cc) / e;
+    double rho = 1.0 / xi0;
+    T *tc = S.hcoef.data() + (size_t)3 * m_deg * m;
+    for (int k = 0; k < m_deg; ++k) {
+      double s1, s2;
+      if (k == 0) {
+        s1 = rho / e;
+        s2 = 0.0;
+      } else {
+        const double rn = 1.0 / (2.0 * xi0 - rho);
+        s1 = 2.0 * rn / e;
+        s2 = -rn * rho;
+        rho = rn;
       }
-    }
-    HIPCHK(c0, hipMemcpyAsync(S.coef.p, hcoef.data(), hcoef.size() * sizeof(T), hipMemcpyHostToDevice, S.stream));
-    hipEvent_t e0, e1;
-    HIPCHK(c0, hipEventCreate(&e0));
-    HIPCHK(c0, hipEventCreate(&e1));
-    (void)hipEventRecord(e0, S.stream);
-    HIPCHK(c0, hipGraphLaunch(S.exec, S.stream));
-    (void)hipEventRecord(e1, S.stream);
-    HIPCHK(c0, hipStreamSynchronize(S.stream));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    // CholGS + RR per problem
-    st = parallel_for((int)members.size(), threads, [&](int m) {
-      Item &it = items[members[m]];
-      if (int r = set_dev(it.c)) return r;
-      int passes = 0;
-      if (int r = orth_robust(it.c, it.X, it.ld, it.o->nblock, it.o->mixed_cholgs ? 1 : 0, &passes)) return r;
-      if (int r = rr_impl(it.c, it.X, it.ld, it.o->nblock, it.c->HX.as<double>(), it.o->nblock, it.evals, it.resid,
-                          nullptr))
-        return r;
-      it.rep.iters++;
-      it.rep.t_filter += ms * 1e-3;
-      it.rep.dofvecs += it.c->mesh.n_dof * (int64_t)it.o->nblock * (degree + 1);
-      it.res = max_wanted(it);
-      it.active = it.res > it.o->tol && it.rep.iters < it.o->max_iter;
-      return 0;
-    });
-    if (st) return st;
-    if (c0->verbose) {
-      int na = 0;
-      double worst = 0;
-      for (auto &it : items) {
-        na += it.active;
-        worst = std::max(worst, it.res);
-      }
-      std::fprintf(stderr, "[chfsi] batch pass %d: %zu problems swept (%.3f ms), %d still active, max residual %.3e\n",
-                   pass, members.size(), ms, na, worst);
-      std::fflush(stderr);
+      tc[3 * k] = (T)s1;
+      tc[3 * k + 1] = (T)s2;
+      tc[3 * k + 2] = (T)cc;
     }
   }
+  BCHK(B, hipMemcpyAsync(S.coef.p, S.hcoef.data(), S.hcoef.size() * sizeof(T), hipMemcpyHostToDevice, B->stream));
+  hipEvent_t e0, e1;
+  BCHK(B, hipEventCreate(&e0));
+  BCHK(B, hipEventCreate(&e1));
+  (void)hipEventRecord(e0, B->stream);
+  hipError_t le = hipGraphLaunch(S.exec, B->stream);
+  (void)hipEventRecord(e1, B->stream);
+  hipError_t se = hipStreamSynchronize(B->stream);
+  (void)hipEventElapsedTime(ms_out, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (le != hipSuccess || se != hipSuccess)
+    return bfail(B, CHFSI_ERR_HIP, std::string("batch sweep: ") + hipGetErrorString(le != hipSuccess ? le : se));
+  return 0;
+}
+
+// CholGS + RR of problem p; updates its residual, rung and state
+int subspace_step(Prob &p, bool filtered) {
+  if (int r = set_dev(p.c)) return r;
+  int passes = 0;
+  if (int r = orth_robust(p.c, p.X, p.ld, p.o.nblock, filtered ? mixed_now(p) : 0, &passes)) return r;
+  if (int r = rr_impl(p.c, p.X, p.ld, p.o.nblock, p.c->HX.as<double>(), p.o.nblock, p.evals, p.resid, nullptr))
+    return r;
+  const double nres = max_wanted(p);
+  if (filtered) {
+    p.rep.iters++;
+    p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock;
+    if (p.rung + 1 < n_rungs(p) && (nres > 0.98 * p.res || nres < rung_tol(p))) ++p.rung;
+  } else {
+    p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock;
+  }
+  p.res = nres;
   return 0;
 }
 
 }  // namespace
 
+extern "C" int chfsi_batch_create(chfsi_batch **out, int device) {
+  if (!out) return CHFSI_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CHFSI_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return CHFSI_ERR_HIP;
+  chfsi_batch *b = new (std::nothrow) chfsi_batch();
+  if (!b) return CHFSI_ERR_OOM;
+  b->device = device;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return CHFSI_ERR_HIP;
+  }
+  const char *v = std::getenv("CHFSI_VERBOSE");
+  b->verbose = v && v[0] && v[0] != '0';
+  *out = b;
+  return 0;
+}
+
+extern "C" int chfsi_batch_destroy(chfsi_batch *b) {
+  if (!b) return CHFSI_ERR_ARG;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  b->s64.release();
+  b->s32.release();
+  (void)hipStreamDestroy(b->stream);
+  delete b;
+  return 0;
+}
+
+extern "C" const char *chfsi_batch_last_error(const chfsi_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+extern "C" int chfsi_batch_add(chfsi_batch *b, chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t ld,
+                               double *evals, double *resid) {
+  if (!b || !c || !o) return CHFSI_ERR_ARG;
+  if (c->device != b->device) return bfail(b, CHFSI_ERR_ARG, "batch: context on another device");
+  if (int r = check_block(c, X, ld, o->nblock)) return bfail(b, r, "batch: " + c->err);
+  if (o->nstates < 1 || o->nstates > o->nblock || o->degree < 1 || o->max_iter < 0 || !(o->tol > 0) || !evals ||
+      !resid || o->nblock > c->mesh.n_dof)
+    return bfail(b, CHFSI_ERR_ARG, "batch: invalid options");
+  if (b->degree == 0) b->degree = o->degree;
+  if (o->degree != b->degree) return bfail(b, CHFSI_ERR_ARG, "batch: every problem needs the session's degree");
+  for (int k = 0; k < std::max(1, std::min(o->n_ladder, 4)); ++k) {
+    const chfsi_prec pr = o->n_ladder > 0 ? o->ladder[k] : CHFSI_FP64;
+    if (pr != CHFSI_FP64 && pr != CHFSI_FP32) return bfail(b, CHFSI_ERR_ARG, "batch: ladder rungs must be FP32/FP64");
+  }
+  for (const Prob &p : b->probs)
+    if (!p.done && p.c == c) return bfail(b, CHFSI_ERR_ARG, "batch: the context is already in the session");
+  if (int r = ensure_small(c, o->nblock)) return bfail(b, r, "batch: " + c->err);
+  const size_t bytes = (size_t)c->mesh.n_dof * o->nblock * sizeof(double);  // FP64 or FP32 rungs
+  for (int k = 0; k < 3; ++k)
+    if (c->fbuf[k].ensure(bytes) != hipSuccess) return bfail(b, CHFSI_ERR_OOM, "batch: filter buffers");
+  if (c->HX.ensure(bytes) != hipSuccess) return bfail(b, CHFSI_ERR_OOM, "batch: HX buffer");
+  Prob p;
+  p.id = (int)b->probs.size();
+  p.c = c;
+  p.o = *o;
+  p.X = X;
+  p.ld = ld;
+  p.evals = evals;
+  p.resid = resid;
+  std::memset(&p.rep, 0, sizeof p.rep);
+  b->probs.push_back(p);
+  return p.id;
+}
+
+extern "C" int chfsi_batch_report(const chfsi_batch *b, int id, chfsi_report *rep) {
+  if (!b || !rep || id < 0 || id >= (int)b->probs.size()) return CHFSI_ERR_ARG;
+  *rep = b->probs[id].rep;
+  return 0;
+}
+
+extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int max_done) {
+  if (!b || !n_done || max_done < 0 || (max_done > 0 && !done_ids)) return CHFSI_ERR_ARG;
+  if (hipSetDevice(b->device) != hipSuccess) return bfail(b, CHFSI_ERR_HIP, "hipSetDevice");
+  auto finish = [&](Prob &p) {
+    p.done = true;
+    p.rep.max_resid = p.res;
+    p.rep.rung = p.rung;
+    p.rep.status = p.res <= p.o.tol ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
+    b->finished.push_back(p.id);
+  };
+  // 1. new problems: CholGS + RR of their start block
+  std::vector<int> fresh;
+  for (Prob &p : b->probs)
+    if (!p.done && !p.started) fresh.push_back(p.id);
+  int st = parallel_for((int)fresh.size(), b->threads, [&](int i) { return subspace_step(b->probs[fresh[i]], false); });
+  if (st) return bfail(b, st, "batch: start of a problem failed");
+  for (int id : fresh) {
+    Prob &p = b->probs[id];
+    p.started = true;
+    if (p.res <= p.o.tol || p.o.max_iter == 0) finish(p);
+  }
+  // 2. filter sweeps, one per precision group
+  std::vector<int> g32, g64;
+  for (Prob &p : b->probs)
+    if (!p.done) (rung_prec(p) == CHFSI_FP32 ? g32 : g64).push_back(p.id);
+  float ms32 = 0, ms64 = 0;
+  if (int r = run_sweep<float>(b, b->s32, g32, &ms32)) return r;
+  if (int r = run_sweep<double>(b, b->s64, g64, &ms64)) return r;
+  // 3. CholGS + RR of every swept problem
+  std::vector<int> swept(g32);
+  swept.insert(swept.end(), g64.begin(), g64.end());
+  st = parallel_for((int)swept.size(), b->threads, [&](int i) {
+    Prob &p = b->probs[swept[i]];
+    const bool f32 = rung_prec(p) == CHFSI_FP32;
+    p.rep.t_filter += (f32 ? ms32 : ms64) * 1e-3;
+    p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock * b->degree;
+    return subspace_step(p, true);
+  });
+  if (st) return bfail(b, st, "batch: CholGS/RR of a problem failed");
+  int remaining = 0;
+  for (int id : swept) {
+    Prob &p = b->probs[id];
+    if (p.res <= p.o.tol || p.rep.iters >= p.o.max_iter) finish(p);
+    else ++remaining;
+  }
+  if (b->verbose) {
+    double worst = 0;
+    for (int id : swept) worst = std::max(worst, b->probs[id].res);
+    std::fprintf(stderr, "[chfsi] batch pass: %zu FP32 + %zu FP64 problems swept (%.2f + %.2f ms), %d remain, max residual %.3e\n",
+                 g32.size(), g64.size(), ms32, ms64, remaining, worst);
+    std::fflush(stderr);
+  }
+  int nd = 0;
+  while (nd < max_done && !b->finished.empty()) {
+    done_ids[nd++] = b->finished.front();
+    b->finished.pop_front();
+  }
+  *n_done = nd;
+  return remaining;
+}
+
 extern "C" int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts *opts, double *const *X,
                                  const int64_t *ld, double *const *evals, double *const *resid, chfsi_report *reps) {
-  if (!ctxs || n < 1 || !opts || !X || !ld || !evals || !resid) return CHFSI_ERR_ARG;
+  if (!ctxs || n < 1 || !opts || !X || !ld || !evals || !resid || !ctxs[0]) return CHFSI_ERR_ARG;
   chfsi_ctx *c0 = ctxs[0];
-  if (!c0) return CHFSI_ERR_ARG;
-  const int degree = opts[0].degree;
-  chfsi_prec prec = opts[0].n_ladder > 0 ? opts[0].ladder[0] : CHFSI_FP64;
-  int max_iter = 0;
-  std::vector<Item> items(n);
+  chfsi_batch *b = nullptr;
+  int st = chfsi_batch_create(&b, c0->device);
+  if (st) return fail(c0, st, "batch: cannot create a session");
+  struct Guard {
+    chfsi_batch *b;
+    ~Guard() { chfsi_batch_destroy(b); }
+  } g{b};
   for (int i = 0; i < n; ++i) {
-    chfsi_ctx *c = ctxs[i];
-    const chfsi_opts *o = &opts[i];
-    if (!c) return fail(c0, CHFSI_ERR_ARG, "batch: null context");
-    if (c->device != c0->device) return fail(c0, CHFSI_ERR_ARG, "batch: contexts on different devices");
-    if (int r = check_block(c, X[i], ld[i], o->nblock)) return fail(c0, r, std::string("batch: ") + c->err);
-    if (o->nstates < 1 || o->nstates > o->nblock || o->degree != degree || degree < 1 || o->max_iter < 0 ||
-        !(o->tol > 0) || !evals[i] || !resid[i] || o->nblock > c->mesh.n_dof)
-      return fail(c0, CHFSI_ERR_ARG, "batch: invalid options (every problem needs the same degree)");
-    const chfsi_prec p = o->n_ladder > 0 ? o->ladder[0] : CHFSI_FP64;
-    if (p != prec || (p != CHFSI_FP64 && p != CHFSI_FP32))
-      return fail(c0, CHFSI_ERR_ARG, "batch: one filter precision (FP64 or FP32) for every problem");
-    for (int j = 0; j < i; ++j)
-      if (ctxs[j] == c) return fail(c0, CHFSI_ERR_ARG, "batch: a context appears twice");
-    if (int r = ensure_small(c, o->nblock)) return r;
-    const size_t bytes = (size_t)c->mesh.n_dof * o->nblock * (prec == CHFSI_FP64 ? 8 : 4);
-    for (int k = (prec == CHFSI_FP64 ? 1 : 0); k < 3; ++k) HIPCHK(c, c->fbuf[k].ensure(bytes));
-    HIPCHK(c, c->HX.ensure((size_t)c->mesh.n_dof * o->nblock * sizeof(double)));
-    Item &it = items[i];
-    it.idx = i;
-    it.c = c;
-    it.o = o;
-    it.X = X[i];
-    it.ld = ld[i];
-    it.evals = evals[i];
-    it.resid = resid[i];
-    std::memset(&it.rep, 0, sizeof it.rep);
-    max_iter = std::max(max_iter, o->max_iter);
+    if (!ctxs[i]) return fail(c0, CHFSI_ERR_ARG, "batch: null context");
+    const int id = chfsi_batch_add(b, ctxs[i], &opts[i], X[i], ld[i], evals[i], resid[i]);
+    if (id < 0) return fail(c0, id, b->err);
   }
-  if (int r = set_dev(c0)) return r;
-  const int threads = 8;
-  int st = prec == CHFSI_FP64 ? run_batch<double>(items, degree, max_iter, threads, c0)
-                              : run_batch<float>(items, degree, max_iter, threads, c0);
-  if (st) return st;
+  std::vector<int> done(n);
+  int nd = 0;
+  for (;;) {
+    const int rem = chfsi_batch_pass(b, done.data(), &nd, n);
+    if (rem < 0) return fail(c0, rem, b->err);
+    if (rem == 0) break;
+  }
   int worst = CHFSI_OK;
-  for (auto &it : items) {
-    it.rep.max_resid = it.res;
-    it.rep.status = it.res <= it.o->tol ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
-    if (it.rep.status != CHFSI_OK) worst = CHFSI_WARN_NOT_CONVERGED;
-    if (reps) reps[it.idx] = it.rep;
+  for (int i = 0; i < n; ++i) {
+    const chfsi_report &r = b->probs[i].rep;
+    if (r.status != CHFSI_OK) worst = CHFSI_WARN_NOT_CONVERGED;
+    if (reps) reps[i] = r;
   }
   return worst;
 }

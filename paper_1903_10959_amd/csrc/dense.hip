@@ -154,9 +154,10 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
 static constexpr int MT = 128, NTL = 128, KC = 16;
 static constexpr int ALD = KC + 1;   // padded LDS row of the A tile (odd -> no bank conflicts)
 
+template <bool MIXED>
 __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict__ X, int64_t ld, int64_t row0,
                                                         int64_t nrows, int n, const double *__restrict__ W,
-                                                        int upper, int mixed, double *__restrict__ C, int64_t ldc) {
+                                                        int upper, double *__restrict__ C, int64_t ldc) {
   __shared__ double As[2][MT * ALD];
   __shared__ double Ws[2][KC * NTL];
   const int nt = (n + NTL - 1) / NTL;
@@ -170,17 +171,20 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
   const int j = lane & 15, kq = lane >> 4;
   const int kend = upper ? min(n, n0 + NTL) : n;
   const int c0 = n0 + wj * 64;                   // first column of this wave
-  const int kdiag = mixed ? (c0 / 64) * 64 : 0;  // mixed: k >= kdiag is the FP64 diagonal block
+  const int kdiag = MIXED ? (c0 / 64) * 64 : 0;  // mixed: k >= kdiag is the FP64 diagonal block
 
   v4d acc[4][4];
-  v4f acc32[4][4];
+  v4f acc32[MIXED ? 4 : 1][MIXED ? 4 : 1];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      acc[a][b] = v4d{0, 0, 0, 0};
-      acc32[a][b] = v4f{0, 0, 0, 0};
-    }
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  if (MIXED) {
+#pragma unroll
+    for (int a = 0; a < (MIXED ? 4 : 1); ++a)
+#pragma unroll
+      for (int b = 0; b < (MIXED ? 4 : 1); ++b) acc32[a][b] = v4f{0, 0, 0, 0};
+  }
 
   auto stage = [&](int buf, int k0) {
     // A tile: 128 rows x 16 columns (each row 128 contiguous bytes)
@@ -213,25 +217,25 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
       for (int a = 0; a < 4; ++a) av[a] = As[buf][(wi * 64 + a * 16 + j) * ALD + kk];
 #pragma unroll
       for (int b = 0; b < 4; ++b) bv[b] = Ws[buf][kk * NTL + wj * 64 + b * 16 + j];
-      if (kbase + ks >= kdiag) {
+      if (!MIXED || kbase + ks >= kdiag) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4(av[a], bv[b], acc[a][b]);
       } else {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < (MIXED ? 4 : 1); ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc32[a][b] = mfma16x4((float)av[a], (float)bv[b], acc32[a][b]);
+          for (int b = 0; b < (MIXED ? 4 : 1); ++b) acc32[a][b] = mfma16x4((float)av[a], (float)bv[b], acc32[a][b]);
       }
     }
     __syncthreads();
   }
-  if (mixed && kdiag > 0) {
+  if (MIXED && kdiag > 0) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < (MIXED ? 4 : 1); ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += f32acc_to_f64_layout(acc32[a][b], lane);
+      for (int b = 0; b < (MIXED ? 4 : 1); ++b) acc[a][b] += f32acc_to_f64_layout(acc32[a][b], lane);
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -272,8 +276,12 @@ int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, in
   for (int64_t r = 0; r < nrows; r += chunk) {
     const int64_t rows = (nrows - r < chunk) ? nrows - r : chunk;
     const int64_t mts = (rows + MT - 1) / MT;
-    hipLaunchKernelGGL(rmul_gemm_kernel, dim3((unsigned)(mts * nt)), dim3(256), 0, s, X, ld, r, rows, n, W, upper,
-                       mixed, scratch, (int64_t)n);
+    if (mixed)
+      hipLaunchKernelGGL(rmul_gemm_kernel<true>, dim3((unsigned)(mts * nt)), dim3(256), 0, s, X, ld, r, rows, n, W,
+                         upper, scratch, (int64_t)n);
+    else
+      hipLaunchKernelGGL(rmul_gemm_kernel<false>, dim3((unsigned)(mts * nt)), dim3(256), 0, s, X, ld, r, rows, n, W,
+                         upper, scratch, (int64_t)n);
     int64_t total = rows * n;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;

@@ -116,36 +116,61 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
     }
 
     if (col_ok) {
-      // epilogue in chunks of 4 row blocks: every load of a chunk is issued
-      // before its stores, so 16 rows per lane are in flight at once
+      if (sizeof(T) == 4) {
+        // FP32: epilogue in chunks of 4 row blocks, every load of a chunk issued
+        // before its stores (16 rows per lane in flight; measured faster)
 #pragma unroll
-      for (int r0 = 0; r0 < RBP; r0 += 4) {
-        T old[4][4];
+        for (int r0 = 0; r0 < RBP; r0 += 4) {
+          T old[4][4];
 #pragma unroll
-        for (int r = r0; r < r0 + 4 && r < RBP; ++r)
+          for (int r = r0; r < r0 + 4 && r < RBP; ++r)
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq) {
-            const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
-            T v = T(0);
-            if (row < n_loc && mi_s[row] != T(0)) {
-              const int64_t d = dof_s[row];
-              if (ft_s[row]) {
-                v = vd_s[row] * X[d * ldx + col];
-                if (Xp) v += s2 * Xp[d * ldp + col];
-              } else {
-                v = Y[d * ldy + col];
+            for (int qq = 0; qq < 4; ++qq) {
+              const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
+              T v = T(0);
+              if (row < n_loc && mi_s[row] != T(0)) {
+                const int64_t d = dof_s[row];
+                if (ft_s[row]) {
+                  v = vd_s[row] * X[d * ldx + col];
+                  if (Xp) v += s2 * Xp[d * ldp + col];
+                } else {
+                  v = Y[d * ldy + col];
+                }
+              }
+              old[r - r0][qq] = v;
+            }
+#pragma unroll
+          for (int r = r0; r < r0 + 4 && r < RBP; ++r)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+              const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
+              if (row < n_loc) {
+                const T w = mi_s[row];
+                if (w != T(0)) Y[(int64_t)dof_s[row] * ldy + col] = old[r - r0][qq] + s1 * w * acc[r][qq];
               }
             }
-            old[r - r0][qq] = v;
-          }
+        }
+      } else {
+        // FP64 (compute-bound): row by row; other work-groups on the CU hide the latency
 #pragma unroll
-        for (int r = r0; r < r0 + 4 && r < RBP; ++r)
+        for (int r = 0; r < RBP; ++r)
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) {
             const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
             if (row < n_loc) {
               const T w = mi_s[row];
-              if (w != T(0)) Y[(int64_t)dof_s[row] * ldy + col] = old[r - r0][qq] + s1 * w * acc[r][qq];
+              if (w != T(0)) {
+                const int64_t d = dof_s[row];
+                T *yp = Y + d * ldy + col;
+                const T prod = s1 * w * acc[r][qq];
+                if (ft_s[row]) {
+                  T y = vd_s[row] * X[d * ldx + col] + prod;
+                  if (Xp) y += s2 * Xp[d * ldp + col];
+                  *yp = y;
+                } else {
+                  *yp += prod;
+                }
+              }
             }
           }
       }

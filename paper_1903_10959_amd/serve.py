@@ -1,4 +1,4 @@
-"""Served stream of solve requests on one GPU (host control over the C ABI).
+"""Served stream of solve requests on one GPU, with continuous batching.
 
 A request is one SCF-like sequence: a problem drawn from the batched-workload
 size distribution, solved `solves` times; solve 1 starts from a seeded block,
@@ -6,26 +6,28 @@ solve s > 1 warm-starts from solve s-1's vectors (kept on the device) with the
 potential perturbed by 1 % seeded noise (the paper reuses the previous
 wavefunctions as the starting guess, Sec. 3.3).
 
-Scheduling: requests arrive by a seeded Poisson process.  A request is
-admitted when a slot is free and its device footprint (``chfsi_footprint_bytes``
-plus its blocks) fits the HBM budget next to the requests already running;
-otherwise it waits in arrival order.  Each slot is a host thread with its own
-library contexts and HIP stream, so admitted requests run concurrently on the
-device; a slot keeps the contexts of its last meshes (mesh tables stay on the
-device).  Every number a request produces depends only on the request: alone
-or in the mix, its results are the same.
+Scheduling (one engine loop over a ``BatchSession``): requests arrive by a
+seeded Poisson process.  At every pass boundary the engine admits waiting
+requests in arrival order while their device footprint (``chfsi_footprint_bytes``
+plus the block) fits the HBM budget next to the requests already running; an
+admitted request gets a context (reused from a pool keyed by mesh, so mesh
+tables stay on the device) and its solve joins the session's shared filter
+sweeps at the next pass.  A solve leaves the session when its wanted
+residuals reach the tolerance; the request then starts its next warm solve
+or, after the last one, releases its memory.  The arithmetic of a problem
+does not depend on the other problems sharing its passes, so every result is
+the same alone and in the mix.
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
-import queue
 import threading
 import time
 
 import numpy as np
 
-from . import Context, footprint_bytes
+from . import BatchSession, Context, footprint_bytes
 
 
 @dataclasses.dataclass
@@ -34,8 +36,8 @@ class Request:
     arrival: float             # seconds after the stream starts
     problem: object            # workload.Problem
     footprint: int = 0
-    admitted: float = 0.0
-    done: float = 0.0
+    admitted: float = -1.0
+    done: float = -1.0
     solve_times: list = dataclasses.field(default_factory=list)
     iters: list = dataclasses.field(default_factory=list)
     evals: list = dataclasses.field(default_factory=list)
@@ -56,35 +58,6 @@ def make_stream(n_requests: int, rate: float, seed: int = 5, sizes=None):
     return out
 
 
-class _Slot:
-    """One concurrent lane: a stream and a small cache of contexts by mesh."""
-
-    def __init__(self, device: int, cache: int = 2):
-        import torch
-
-        self.stream = torch.cuda.Stream(device)
-        self.device = device
-        self.cache = collections.OrderedDict()
-        self.cache_size = cache
-
-    def context(self, prob):
-        key = (prob.L, prob.n_el, prob.p)
-        if key in self.cache:
-            self.cache.move_to_end(key)
-            return self.cache[key]
-        while len(self.cache) >= self.cache_size:
-            _, old = self.cache.popitem(last=False)
-            old.close()
-        c = Context(self.device, stream=self.stream).set_mesh(prob.L, prob.n_el, prob.p)
-        self.cache[key] = c
-        return c
-
-    def close(self):
-        for c in self.cache.values():
-            c.close()
-        self.cache.clear()
-
-
 _V0_CACHE = {}
 _V0_LOCK = threading.Lock()
 
@@ -102,84 +75,122 @@ def _base_potential(prob, ctx):
     return v
 
 
-def run_request(slot: _Slot, req: Request, solves: int, tol: float, degree: int, ladder, stream_seed: int,
-                t0: float):
+class _ContextPool:
+    """Idle contexts by mesh; each context has its own stream."""
+
+    def __init__(self, device: int, idle_cap: int = 16):
+        self.device = device
+        self.idle = collections.OrderedDict()   # key -> [ctx, ...]
+        self.idle_cap = idle_cap
+        self.n_idle = 0
+
+    def get(self, prob):
+        import torch
+
+        key = (prob.L, prob.n_el, prob.p)
+        lst = self.idle.get(key)
+        if lst:
+            self.n_idle -= 1
+            c = lst.pop()
+            if not lst:
+                del self.idle[key]
+            return c
+        return Context(self.device, stream=torch.cuda.Stream(self.device)).set_mesh(prob.L, prob.n_el, prob.p)
+
+    def put(self, prob, ctx):
+        key = (prob.L, prob.n_el, prob.p)
+        self.idle.setdefault(key, []).append(ctx)
+        self.idle.move_to_end(key)
+        self.n_idle += 1
+        while self.n_idle > self.idle_cap:
+            k, lst = next(iter(self.idle.items()))
+            lst.pop(0).close()
+            self.n_idle -= 1
+            if not lst:
+                del self.idle[k]
+
+    def close(self):
+        for lst in self.idle.values():
+            for c in lst:
+                c.close()
+        self.idle.clear()
+
+
+def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-6, degree: int = 20,
+          ladder=("fp32", "fp64"), stream_seed: int = 5, device: int = 0, log=None, realtime: bool = True,
+          max_active: int = 256):
+    """Run the stream; returns the requests with timings filled in.
+    realtime=False makes every request available at t = 0 (offline replay)."""
     import torch
 
     import workload
 
-    prob = req.problem
-    with torch.cuda.stream(slot.stream):
-        ctx = slot.context(prob)
-        V0 = _base_potential(prob, ctx)
-        X = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=f"cuda:{slot.device}")
-        for s in range(solves):
-            ts = time.time()
-            V = V0 if s == 0 else workload.perturbed(V0, (stream_seed, req.rid, s))
-            ctx.set_potential(V)
-            out = ctx.solve(X, prob.nstates, degree, tol, max_iter=400, ladder=ladder)
-            slot.stream.synchronize()
-            req.solve_times.append(time.time() - ts)
-            req.iters.append(out["iters"])
-            req.evals.append(out["evals"][:prob.nstates].copy())
-            req.converged = req.converged and out["converged"]
-    req.done = time.time() - t0
-
-
-def serve(requests, slots: int = 8, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-6,
-          degree: int = 20, ladder=("fp32", "fp64"), stream_seed: int = 5, device: int = 0, log=None,
-          realtime: bool = True):
-    """Run the stream; returns the requests with timings filled in.
-    realtime=False admits every request at t = 0 (offline replay)."""
     for r in requests:
         r.footprint = footprint_bytes(r.problem.n_el, r.problem.p, r.problem.nblock, 0, ladder[0]) \
             + r.problem.n_dof * r.problem.nblock * 8
         if r.footprint > hbm_budget:
             raise ValueError(f"request {r.rid} needs {r.footprint} B, above the HBM budget")
-    lanes = [_Slot(device) for _ in range(slots)]
-    free = queue.Queue()
-    for ln in lanes:
-        free.put(ln)
-    lock = threading.Lock()
-    in_use = [0.0]
-    cond = threading.Condition(lock)
-    threads = []
-    errors = []
+    order = sorted(requests, key=lambda r: r.arrival)
+    pool = _ContextPool(device)
+    sess = BatchSession(device)
+    waiting = collections.deque()
+    running = {}          # session id -> [request, ctx, X, V0, solve index, solve start]
+    in_use = 0.0
+    nxt = 0
+    n_done = 0
     t0 = time.time()
+    now = lambda: time.time() - t0
 
-    def finish(slot, req):
-        try:
-            run_request(slot, req, solves, tol, degree, ladder, stream_seed, t0)
-        except Exception as exc:  # surfaced after the run
-            errors.append((req.rid, exc))
-        finally:
-            with cond:
-                in_use[0] -= req.footprint
-                cond.notify_all()
-            free.put(slot)
-            if log:
-                log(f"request {req.rid} done at {req.done:.2f} s ({sum(req.solve_times):.2f} s of solves)")
+    def start_solve(entry, s):
+        req, ctx, X, V0 = entry[0], entry[1], entry[2], entry[3]
+        V = V0 if s == 0 else workload.perturbed(V0, (stream_seed, req.rid, s))
+        ctx.set_potential(V)
+        pid = sess.add(ctx, X, req.problem.nstates, degree, tol, max_iter=400, ladder=ladder)
+        entry[4], entry[5] = s, time.time()
+        running[pid] = entry
 
-    for req in sorted(requests, key=lambda r: r.arrival):
-        if realtime:
-            wait = req.arrival - (time.time() - t0)
-            if wait > 0:
-                time.sleep(wait)
-        slot = free.get()                     # a slot frees up
-        with cond:                            # and the memory fits
-            while in_use[0] + req.footprint > hbm_budget:
-                cond.wait()
-            in_use[0] += req.footprint
-        req.admitted = time.time() - t0
-        th = threading.Thread(target=finish, args=(slot, req))
-        th.start()
-        threads.append(th)
-    for th in threads:
-        th.join()
-    for ln in lanes:
-        ln.close()
-    if errors:
-        raise RuntimeError(f"{len(errors)} requests failed; first: {errors[0]}")
+    try:
+        while n_done < len(order):
+            t = now()
+            while nxt < len(order) and (not realtime or order[nxt].arrival <= t):
+                waiting.append(order[nxt])
+                nxt += 1
+            # admission at the pass boundary
+            while waiting and len(running) < max_active and in_use + waiting[0].footprint <= hbm_budget:
+                req = waiting.popleft()
+                in_use += req.footprint
+                req.admitted = now()
+                ctx = pool.get(req.problem)
+                X = workload.start_block_device(req.problem.n_dof, req.problem.nblock, req.problem.x0_seed,
+                                                device=f"cuda:{device}")
+                torch.cuda.synchronize(device)
+                start_solve([req, ctx, X, _base_potential(req.problem, ctx), 0, 0.0], 0)
+            if not running:
+                if waiting:
+                    raise RuntimeError("a waiting request cannot be admitted (budget)")
+                if nxt < len(order):
+                    time.sleep(max(0.0, order[nxt].arrival - now()))
+                continue
+            _, finished = sess.step()
+            for pid, res in finished:
+                entry = running.pop(pid)
+                req, ctx, X, V0, s, ts = entry
+                req.solve_times.append(time.time() - ts)
+                req.iters.append(res["iters"])
+                req.evals.append(res["evals"][:req.problem.nstates].copy())
+                req.converged = req.converged and res["converged"]
+                if s + 1 < solves:
+                    start_solve(entry, s + 1)
+                else:
+                    req.done = now()
+                    in_use -= req.footprint
+                    pool.put(req.problem, ctx)
+                    n_done += 1
+                    if log:
+                        log(f"request {req.rid} done at {req.done:.2f} s ({sum(req.solve_times):.2f} s of solves)")
+    finally:
+        sess.close()
+        pool.close()
     return requests
 
 

@@ -17,12 +17,12 @@ def test_served_results_alone_equal_results_in_the_mix():
     from paper_1903_10959_amd import serve as S
     pool = _pool()
     mix = S.make_stream(10, 1000.0, seed=11, sizes=pool)
-    S.serve(mix, slots=4, solves=3, tol=1e-6, realtime=False)
+    S.serve(mix, solves=3, tol=1e-6, realtime=False)
     for r in mix:
         assert r.converged and len(r.evals) == 3
     for r in mix[:3]:
         alone = S.Request(r.rid, 0.0, r.problem)
-        S.serve([alone], slots=1, solves=3, tol=1e-6, realtime=False)
+        S.serve([alone], solves=3, tol=1e-6, realtime=False)
         for a, b in zip(alone.evals, r.evals):
             np.testing.assert_array_equal(a, b)
         assert alone.iters == r.iters
@@ -34,7 +34,7 @@ def test_admission_respects_the_hbm_budget():
     reqs = S.make_stream(4, 1000.0, seed=12, sizes=pool)
     big = max(S.footprint_bytes(p.n_el, p.p, p.nblock, 0, "fp32") + p.n_dof * p.nblock * 8 for p in pool)
     # a budget that fits one request at a time serialises the stream
-    S.serve(reqs, slots=4, hbm_budget=big * 1.01, solves=1, tol=1e-4, realtime=False)
+    S.serve(reqs, hbm_budget=big * 1.01, solves=1, tol=1e-4, realtime=False)
     spans = sorted((r.admitted, r.done) for r in reqs)
     for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
         assert a1 >= d0 - 1e-3
