@@ -174,7 +174,9 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
     P.n_el = c->mesh.n_el;
     P.ncols = nb;
     hp.push_back(P);
-    const int ntiles = (nb + 63) / 64;
+    const int tw = hx_tile_width<T>(c->mesh.np);
+    if (tw <= 0) return bfail(B, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
+    const int ntiles = (nb + tw - 1) / tw;
     for (int col = 0; col < 8; ++col)
       for (int s = c->mesh.color_offset[col]; s < c->mesh.color_offset[col + 1]; ++s)
         for (int t = 0; t < ntiles; ++t)

@@ -19,26 +19,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
-namespace chfsi {
 
-// ---------------------------------------------------------------------------
-// Cell products of one colour.  Work-group = one cell x 64 columns; wave w owns
-// columns [n0, n0+16) with n0 = 64*tile + 16*w.  The cell's dof indices and
-// M^-1/2 values are staged in LDS, so the B operand (gathered, M^-1/2-scaled
-// X rows, 16 contiguous values per row) costs one LDS read and one global load
-// with no data-dependent branch.  A operand: K_ref (symmetric, zero padded to
-// NP) read row-wise, A[i][k] = K[k][i] contiguous in i.  Output row blocks are
-// processed RBP at a time so the accumulators stay in registers.
-// Epilogue: Y[dof, col] += s1 * minv[dof] * acc.
-// ---------------------------------------------------------------------------
-template <typename T, int NP>
-struct CellTile {
-  static constexpr int RB = NP / 16;
-  // FP64 accumulators are 8 registers per 16x16 block: at most 11 blocks live
-  static constexpr int RBP = sizeof(T) == 8 ? (RB % 11 == 0 ? 11 : (RB % 8 == 0 ? 8 : (RB % 7 == 0 ? 7 : RB)))
-                                            : RB;
-  static_assert(RB % RBP == 0, "row-block pass must divide the row blocks");
-};
+namespace chfsi {
 
 // 1 when this cell is the first (in colour order) to touch local node r
 __device__ __forceinline__ int first_touch(int r, int q, int e, int n_el) {
@@ -50,131 +32,234 @@ __device__ __forceinline__ int first_touch(int r, int q, int e, int n_el) {
   return (fx && fy && fz) ? 1 : 0;
 }
 
-// The product of one cell and one 64-column tile (called by the single-problem
-// and the batched kernels).
-template <typename T, int NP>
+// Epilogue of one 16-row x 16-column output fragment (4 rows per lane):
+// Y[dof, col] = s1 (V - shift) X + s2 Xprev + s1 minv acc on the row's first
+// touch, Y[dof, col] += s1 minv acc afterwards.  Loads and stores are split so
+// that a caller issues the loads of the next fragment before it stores this
+// one, and every load is unconditional (a row that is not written reads an
+// in-bounds address), so no branch sits between a load and its consumer.
+template <typename T>
+struct EpiFrag {
+  T v1[4], v2[4];
+};
+
+template <typename T>
+struct EpiCtx {
+  const T *X;
+  int64_t ldx;
+  const T *Xp;
+  int64_t ldp;
+  T *Y;
+  int64_t ldy;
+  const int32_t *dof_s;
+  const T *mi_s, *vd_s;
+  const int8_t *ft_s;
+  int n_loc;
+  T s1, s2;
+};
+
+template <typename T>
+__device__ __forceinline__ void epi_load(const EpiCtx<T> &c, int row0, int kq, int col, EpiFrag<T> &f) {
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int row = row0 + acc_row<T>(kq, qq);
+    const int64_t d = c.dof_s[row];
+    const bool ft = c.ft_s[row] != 0;
+    const T *p1 = ft ? c.X + d * c.ldx : c.Y + d * c.ldy;
+    const T *p2 = (ft && c.Xp) ? c.Xp + d * c.ldp : p1;
+    f.v1[qq] = p1[col];
+    f.v2[qq] = p2[col];
+  }
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ void epi_store(const EpiCtx<T> &c, int row0, int kq, int col, bool col_ok,
+                                          const EpiFrag<T> &f, const A &acc) {
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    const int row = row0 + acc_row<T>(kq, qq);
+    const T w = c.mi_s[row];
+    if (col_ok && row < c.n_loc && w != T(0)) {
+      const T prod = c.s1 * w * acc[qq];
+      T y;
+      if (c.ft_s[row]) {
+        y = c.vd_s[row] * f.v1[qq] + prod;
+        if (c.Xp) y += c.s2 * f.v2[qq];
+      } else {
+        y = f.v1[qq] + prod;
+      }
+      c.Y[(int64_t)c.dof_s[row] * c.ldy + col] = y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cell products of one colour (FP64 and FP32), both operands staged through
+// LDS.  Work-group = one cell x TW columns, NW waves in a WR x WC grid: wave (wr, wc)
+// owns row blocks [wr*RBW, (wr+1)*RBW) and column blocks [wc*CBW, (wc+1)*CBW)
+// of the 16x16 output tiles, so every A fragment read from LDS feeds CBW MFMAs
+// and every B fragment RBW MFMAs.  The contraction index runs over chunks of
+// KC local nodes: a chunk of K_ref (KC full rows, contiguous in the padded
+// matrix) and of the gathered, M^-1/2-scaled X_e (KC rows x TW columns) is
+// loaded into registers one chunk ahead, written to the other half of a
+// double-buffered LDS area after the chunk's MFMAs, and published by the one
+// barrier per chunk.  K_ref is thus read once per work-group, and each
+// gathered row once per work-group.
+// ---------------------------------------------------------------------------
+template <typename T, int NP, int NW, int WR, int CBW, int KC>
+struct LdsTile {
+  static constexpr int NT = 64 * NW;                       // threads
+  static constexpr int RB = NP / 16;
+  static constexpr int RBW = RB / WR;
+  static constexpr int WC = NW / WR;
+  static constexpr int TW = 16 * CBW * WC;                 // columns per work-group
+  static constexpr int VEC = 16 / sizeof(T);               // elements per 16-byte load
+  static constexpr int KV = KC * NP / VEC;                 // 16-byte vectors per K chunk
+  static constexpr int KPT = (KV + NT - 1) / NT;           // ... per thread
+  static constexpr int XPT = KC * TW / NT;                 // X values per thread per chunk
+  static constexpr int NCH = NP / KC;                      // chunks
+  // LDS row strides.  A 64-lane FP32 fragment read touches four rows of 16
+  // consecutive words; a stride of 16 (mod 32) words spreads them over both
+  // halves of the 32 banks (no conflicts beyond the 2-cycle minimum).  FP64
+  // reads take 4 cycles regardless, so FP64 rows stay unpadded.
+  static constexpr int pad32(int n) { return sizeof(T) == 4 ? n + (48 - n % 32) % 32 : n; }
+  static constexpr int SK = pad32(NP);
+  static constexpr int SX = pad32(TW);
+  static_assert(RB % WR == 0 && NW % WR == 0, "row blocks must split over the wave rows");
+  static_assert(KC % 4 == 0 && NP % KC == 0 && (KC * NP) % VEC == 0, "chunking");
+  static_assert((KC * TW) % NT == 0, "X chunk must split evenly over the threads");
+  static_assert((SK * sizeof(T)) % 16 == 0, "16-byte LDS stores of K rows");
+};
+
+template <typename T, int NP, int NW, int WR, int CBW, int KC, int EPD>
 __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp,
-                                          int64_t ldp, T *__restrict__ Y, int64_t ldy, const T *__restrict__ K,
-                                          const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, int e,
-                                          int tile, const T *__restrict__ minv, const T *__restrict__ V, int ncols,
-                                          T s1, T s2, T shift) {
+                                              int64_t ldp, T *__restrict__ Y, int64_t ldy,
+                                              const T *__restrict__ K, const int32_t *__restrict__ cmap,
+                                              int n_loc, int q, int n_el, int e, int tile,
+                                              const T *__restrict__ minv, const T *__restrict__ V, int ncols, T s1,
+                                              T s2, T shift) {
+  typedef LdsTile<T, NP, NW, WR, CBW, KC> C;
   typedef typename acc4<T>::type acc_t;
-  constexpr int RB = CellTile<T, NP>::RB;
-  constexpr int RBP = CellTile<T, NP>::RBP;
+  typedef T vec_t __attribute__((ext_vector_type(C::VEC)));
   __shared__ int32_t dof_s[NP];
   __shared__ T mi_s[NP];
-  __shared__ T vd_s[NP];     // s1 (V - shift) on first-touch rows
+  __shared__ T vd_s[NP];
   __shared__ int8_t ft_s[NP];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  for (int r = threadIdx.x; r < NP; r += blockDim.x) {
+  __shared__ __align__(16) T Ks[2][KC * C::SK];
+  __shared__ __align__(16) T Xs[2][KC * C::SX];
+  const int t = threadIdx.x;
+  for (int r = t; r < NP; r += C::NT) {
     int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
-    dof_s[r] = d < 0 ? 0 : d;              // clamped: row 0 is always readable
-    mi_s[r] = d < 0 ? T(0) : minv[d];      // zero weight removes Dirichlet / padding rows
+    dof_s[r] = d < 0 ? 0 : d;
+    mi_s[r] = d < 0 ? T(0) : minv[d];
     const int ft = d < 0 ? 0 : first_touch(r, q, e, n_el);
     ft_s[r] = (int8_t)ft;
     vd_s[r] = ft ? s1 * (V[d] - shift) : T(0);
   }
   __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave / C::WC, wc = wave - wr * C::WC;
   const int j = lane & 15, kq = lane >> 4;
-  const int col = tile * 64 + wave * 16 + j;
-  const bool col_ok = col < ncols;
-  const int colc = col_ok ? col : ncols - 1;   // clamped column, in bounds
-  const T cscale = col_ok ? T(1) : T(0);
+  const int col0 = tile * C::TW;
 
-#pragma unroll 1
-  for (int rb0 = 0; rb0 < RB; rb0 += RBP) {
-    acc_t acc[RBP];
-#pragma unroll
-    for (int r = 0; r < RBP; ++r) acc[r] = acc_t{0, 0, 0, 0};
-    const T *__restrict__ Kp = K + kq * NP + rb0 * 16 + j;
+  // this thread's X staging slots: chunk row xr[i], tile column xc
+  const int xc = t % C::TW;
+  const int xrow0 = t / C::TW;                       // rows xrow0 + i * (NT / TW)
+  const bool xok = col0 + xc < ncols;
+  const int xcol = xok ? col0 + xc : ncols - 1;      // clamped, in bounds
+  const T xscale = xok ? T(1) : T(0);
 
-    // two operand sets in ping-pong: the loads of step k+1 are in flight while
-    // the MFMAs of step k issue (NP/4 is even for every NP used)
-    auto load_b = [&](int k) -> T {
-      const int row = 4 * k + kq;
-      return X[(int64_t)dof_s[row] * ldx + colc] * (mi_s[row] * cscale);
-    };
-    T b0 = load_b(0), b1;
-    T a0[RBP], a1[RBP];
+  // Staging: chunk c + 1 (K_ref rows and gathered X rows) is loaded into
+  // registers while chunk c is multiplied, then written to the other LDS
+  // buffer.  The X values are scaled when stored, so no wait sits at the load.
+  vec_t kreg[C::KPT];
+  T xreg[C::XPT];
+  auto load_chunk = [&](int c) {
+    const vec_t *Kc = reinterpret_cast<const vec_t *>(K + (int64_t)c * KC * NP);
 #pragma unroll
-    for (int r = 0; r < RBP; ++r) a0[r] = Kp[r * 16];
-
-#pragma unroll 1
-    for (int k = 0; k < NP / 4; k += 2) {
-      b1 = load_b(k + 1);
-#pragma unroll
-      for (int r = 0; r < RBP; ++r) a1[r] = Kp[(int64_t)(4 * (k + 1)) * NP + r * 16];
-#pragma unroll
-      for (int r = 0; r < RBP; ++r) acc[r] = mfma16x4(a0[r], b0, acc[r]);
-      const int k2 = (k + 2 < NP / 4) ? k + 2 : k;   // last pair re-reads step k (in bounds, unused)
-      b0 = load_b(k2);
-#pragma unroll
-      for (int r = 0; r < RBP; ++r) a0[r] = Kp[(int64_t)(4 * k2) * NP + r * 16];
-#pragma unroll
-      for (int r = 0; r < RBP; ++r) acc[r] = mfma16x4(a1[r], b1, acc[r]);
+    for (int i = 0; i < C::KPT; ++i) {
+      const int v = t + C::NT * i;
+      if (v < C::KV) kreg[i] = Kc[v];
     }
-
-    if (col_ok) {
-      if (sizeof(T) == 4) {
-        // FP32: epilogue in chunks of 4 row blocks, every load of a chunk issued
-        // before its stores (16 rows per lane in flight; measured faster)
 #pragma unroll
-        for (int r0 = 0; r0 < RBP; r0 += 4) {
-          T old[4][4];
+    for (int i = 0; i < C::XPT; ++i) {
+      const int row = c * KC + xrow0 + i * (C::NT / C::TW);
+      xreg[i] = X[(int64_t)dof_s[row] * ldx + xcol];
+    }
+  };
+  auto store_chunk = [&](int buf, int c) {
+    constexpr int RV = NP / C::VEC;                 // 16-byte vectors per K row
 #pragma unroll
-          for (int r = r0; r < r0 + 4 && r < RBP; ++r)
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-              const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
-              T v = T(0);
-              if (row < n_loc && mi_s[row] != T(0)) {
-                const int64_t d = dof_s[row];
-                if (ft_s[row]) {
-                  v = vd_s[row] * X[d * ldx + col];
-                  if (Xp) v += s2 * Xp[d * ldp + col];
-                } else {
-                  v = Y[d * ldy + col];
-                }
-              }
-              old[r - r0][qq] = v;
-            }
-#pragma unroll
-          for (int r = r0; r < r0 + 4 && r < RBP; ++r)
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-              const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
-              if (row < n_loc) {
-                const T w = mi_s[row];
-                if (w != T(0)) Y[(int64_t)dof_s[row] * ldy + col] = old[r - r0][qq] + s1 * w * acc[r][qq];
-              }
-            }
+    for (int i = 0; i < C::KPT; ++i) {
+      const int v = t + C::NT * i;
+      if (v < C::KV) {
+        if constexpr (C::SK == NP) {
+          reinterpret_cast<vec_t *>(Ks[buf])[v] = kreg[i];
+        } else {
+          const int row = v / RV;
+          *reinterpret_cast<vec_t *>(&Ks[buf][row * C::SK + (v - row * RV) * C::VEC]) = kreg[i];
         }
-      } else {
-        // FP64 (compute-bound): row by row; other work-groups on the CU hide the latency
-#pragma unroll
-        for (int r = 0; r < RBP; ++r)
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) {
-            const int row = (rb0 + r) * 16 + acc_row<T>(kq, qq);
-            if (row < n_loc) {
-              const T w = mi_s[row];
-              if (w != T(0)) {
-                const int64_t d = dof_s[row];
-                T *yp = Y + d * ldy + col;
-                const T prod = s1 * w * acc[r][qq];
-                if (ft_s[row]) {
-                  T y = vd_s[row] * X[d * ldx + col] + prod;
-                  if (Xp) y += s2 * Xp[d * ldp + col];
-                  *yp = y;
-                } else {
-                  *yp += prod;
-                }
-              }
-            }
-          }
       }
     }
+#pragma unroll
+    for (int i = 0; i < C::XPT; ++i) {
+      const int rr = xrow0 + i * (C::NT / C::TW);
+      Xs[buf][rr * C::SX + xc] = xreg[i] * (mi_s[c * KC + rr] * xscale);
+    }
+  };
+
+  acc_t acc[C::RBW][CBW];
+#pragma unroll
+  for (int r = 0; r < C::RBW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = acc_t{0, 0, 0, 0};
+
+  load_chunk(0);
+  store_chunk(0, 0);
+  __syncthreads();
+  const int arow = wr * C::RBW * 16 + j;            // A fragment: K[k][arow + 16 r]
+  const int bcol = wc * CBW * 16 + j;               // B fragment: Xs[k][bcol + 16 cb]
+#pragma unroll 1
+  for (int c = 0; c < C::NCH; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < C::NCH) load_chunk(c + 1);
+    const T *Kb = Ks[buf];
+    const T *Xb = Xs[buf];
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int k = 4 * kk + kq;
+      T b[CBW];
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb) b[cb] = Xb[k * C::SX + bcol + 16 * cb];
+#pragma unroll
+      for (int r = 0; r < C::RBW; ++r) {
+        const T a = Kb[k * C::SK + arow + 16 * r];
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = mfma16x4(a, b[cb], acc[r][cb]);
+      }
+    }
+    if (c + 1 < C::NCH) store_chunk(buf ^ 1, c + 1);
+    __syncthreads();
+  }
+
+  // epilogue, software-pipelined EPD - 1 fragments ahead
+  const EpiCtx<T> ec{X, ldx, Xp, ldp, Y, ldy, dof_s, mi_s, vd_s, ft_s, n_loc, s1, s2};
+  constexpr int NF = C::RBW * CBW;
+  auto frag_col = [&](int i) { return col0 + bcol + 16 * (i % CBW); };
+  auto frag_row = [&](int i) { return (wr * C::RBW + i / CBW) * 16; };
+  auto frag_load = [&](int i, EpiFrag<T> &f) {
+    const int ci = frag_col(i);
+    epi_load(ec, frag_row(i), kq, ci < ncols ? ci : ncols - 1, f);
+  };
+  EpiFrag<T> f[EPD];
+#pragma unroll
+  for (int i = 0; i < EPD - 1; ++i)
+    if (i < NF) frag_load(i, f[i]);
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    if (i + EPD - 1 < NF) frag_load(i + EPD - 1, f[(i + EPD - 1) % EPD]);
+    const int ci = frag_col(i);
+    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i % EPD], acc[i / CBW][i % CBW]);
   }
 }
 
@@ -353,93 +438,136 @@ int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hi
   return a.split ? dispatch_bf16<true>(a, color_begin, color_end, s) : dispatch_bf16<false>(a, color_begin, color_end, s);
 }
 
+// Tile configuration per padded cell size: waves per work-group, the split
+// of the row blocks over waves, column blocks per wave, contraction chunk.
+// Four waves with 2 x 2 column blocks suit most sizes; the FP64 p = 5 tile
+// runs eight single-column-block waves (four waves per SIMD instead of two,
+// measured 1.3x faster); p = 7 splits its 32 row blocks over four waves.
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void hx_cells_kernel(const T *__restrict__ X, int64_t ldx,
-                                                       const T *__restrict__ Xp, int64_t ldp,
-                                                       T *__restrict__ Y, int64_t ldy,
-                                                       const T *__restrict__ K,
-                                                       const int32_t *__restrict__ cmap, int n_loc,
-                                                       int q, int n_el,
-                                                       const int32_t *__restrict__ cells,
-                                                       const T *__restrict__ minv, const T *__restrict__ V,
-                                                       int ncols, int ntiles, T s1, T s2, T shift) {
+struct TileCfg {
+  static constexpr bool w8 = sizeof(T) == 8 && NP == 224;
+  static constexpr int NW = w8 ? 8 : 4;
+  static constexpr int WR = NP == 16 ? 1 : (NP == 512 ? 4 : 2);
+  static constexpr int CBW = (NP == 16 || w8) ? 1 : 2;
+  static constexpr int KC = 8;
+  static constexpr int EPD = 2;
+  typedef LdsTile<T, NP, NW, WR, CBW, KC> L;
+  // eight-wave tiles must keep four waves per SIMD (two work-groups per CU)
+  static constexpr int WAVES = NW == 8 ? 4 : 1;
+};
+
+#define CHFSI_CELL_TILE(T, NP, ...)                                                                    \
+  cell_tile<T, NP, TileCfg<T, NP>::NW, TileCfg<T, NP>::WR, TileCfg<T, NP>::CBW, TileCfg<T, NP>::KC, \
+            TileCfg<T, NP>::EPD>(__VA_ARGS__)
+
+template <typename T, int NP>
+__global__ __launch_bounds__((64 * TileCfg<T, NP>::NW)) __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP>::WAVES)))
+void hx_cells_kernel(const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp, int64_t ldp, T *__restrict__ Y,
+                     int64_t ldy, const T *__restrict__ K, const int32_t *__restrict__ cmap, int n_loc, int q,
+                     int n_el, const int32_t *__restrict__ cells, const T *__restrict__ minv,
+                     const T *__restrict__ V, int ncols, int ntiles, T s1, T s2, T shift) {
   const int cell_slot = blockIdx.x / ntiles;
   const int tile = blockIdx.x - cell_slot * ntiles;
-  cell_tile<T, NP>(X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V, ncols, s1, s2,
-                   shift);
+  CHFSI_CELL_TILE(T, NP, X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V, ncols,
+                  s1, s2, shift);
 }
 
 // Batched: work item = (problem, cell, column tile); the step's buffer roles
 // (input, previous, output) are the same for every problem, its coefficients
 // come from the problem's table (s1, s2, shift per step).
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void hx_cells_batch_kernel(const BatchProblem<T> *__restrict__ probs,
-                                                             const int4 *__restrict__ work, int step, int cur,
-                                                             int prev, int out) {
+__global__ __launch_bounds__((64 * TileCfg<T, NP>::NW)) __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP>::WAVES)))
+void hx_cells_batch_kernel(const BatchProblem<T> *__restrict__ probs, const int4 *__restrict__ work, int step,
+                           int cur, int prev, int out) {
   const int4 w = work[blockIdx.x];
   const BatchProblem<T> &P = probs[w.x];
   const T *coef = P.coef + 3 * step;
-  cell_tile<T, NP>(P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
-                   P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el, w.y, w.z, P.minv, P.V, P.ncols,
-                   coef[0], coef[1], coef[2]);
+  CHFSI_CELL_TILE(T, NP, P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
+                  P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el, w.y, w.z, P.minv, P.V, P.ncols, coef[0],
+                  coef[1], coef[2]);
+}
+#undef CHFSI_CELL_TILE
+
+template <typename T, int NP>
+static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
+  constexpr int TW = TileCfg<T, NP>::L::TW;
+  const int ntiles = (a.ncols + TW - 1) / TW;
+  const int ncell = color_end - color_begin;
+  if (ncell <= 0 || ntiles <= 0) return;
+  hipLaunchKernelGGL((hx_cells_kernel<T, NP>), dim3((unsigned)(ncell * ntiles)), dim3(64 * TileCfg<T, NP>::NW), 0,
+                     s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.cmap, a.n_loc, a.q, a.n_el,
+                     a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
 }
 
 template <typename T, int NP>
 static void launch_batch(const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur, int prev,
                          int out, hipStream_t s) {
   if (nwork <= 0) return;
-  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP>), dim3((unsigned)nwork), dim3(256), 0, s, probs, work, step, cur,
-                     prev, out);
+  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP>), dim3((unsigned)nwork), dim3(64 * TileCfg<T, NP>::NW), 0, s,
+                     probs, work, step, cur, prev, out);
+}
+
+// Calls f.template run<NP>() for a supported padded cell size; -1 otherwise.
+template <typename F>
+static int with_np(int np, F &&f) {
+  switch (np) {
+    case 16: f.template run<16>(); return 0;    // p = 1
+    case 32: f.template run<32>(); return 0;    // p = 2
+    case 64: f.template run<64>(); return 0;    // p = 3
+    case 128: f.template run<128>(); return 0;  // p = 4
+    case 224: f.template run<224>(); return 0;  // p = 5
+    case 352: f.template run<352>(); return 0;  // p = 6
+    case 512: f.template run<512>(); return 0;  // p = 7
+    default: return -1;
+  }
 }
 
 template <typename T>
+struct TileWidthOp {
+  int tw = 0;
+  template <int NP> void run() { tw = TileCfg<T, NP>::L::TW; }
+};
+template <typename T>
+int hx_tile_width(int np) {
+  TileWidthOp<T> op;
+  return with_np(np, op) == 0 ? op.tw : -1;
+}
+template int hx_tile_width<double>(int);
+template int hx_tile_width<float>(int);
+
+template <typename T>
+struct LaunchCellsOp {
+  const HxArgs<T> &a;
+  int cb, ce;
+  hipStream_t s;
+  template <int NP> void run() { launch_cells<T, NP>(a, cb, ce, s); }
+};
+template <typename T>
+int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
+  LaunchCellsOp<T> op{a, color_begin, color_end, s};
+  return with_np(a.np, op);
+}
+template int hx_cells_launch<double>(const HxArgs<double> &, int, int, hipStream_t);
+template int hx_cells_launch<float>(const HxArgs<float> &, int, int, hipStream_t);
+
+template <typename T>
+struct LaunchBatchOp {
+  const BatchProblem<T> *probs;
+  const int4 *work;
+  int nwork, step, cur, prev, out;
+  hipStream_t s;
+  template <int NP> void run() { launch_batch<T, NP>(probs, work, nwork, step, cur, prev, out, s); }
+};
+template <typename T>
 int hx_cells_batch_launch(int np, const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur,
                           int prev, int out, hipStream_t s) {
-  switch (np) {
-    case 16: launch_batch<T, 16>(probs, work, nwork, step, cur, prev, out, s); break;
-    case 32: launch_batch<T, 32>(probs, work, nwork, step, cur, prev, out, s); break;
-    case 64: launch_batch<T, 64>(probs, work, nwork, step, cur, prev, out, s); break;
-    case 128: launch_batch<T, 128>(probs, work, nwork, step, cur, prev, out, s); break;
-    case 224: launch_batch<T, 224>(probs, work, nwork, step, cur, prev, out, s); break;
-    case 352: launch_batch<T, 352>(probs, work, nwork, step, cur, prev, out, s); break;
-    case 512: launch_batch<T, 512>(probs, work, nwork, step, cur, prev, out, s); break;
-    default: return -1;
-  }
-  return 0;
+  LaunchBatchOp<T> op{probs, work, nwork, step, cur, prev, out, s};
+  return with_np(np, op);
 }
 template int hx_cells_batch_launch<double>(int, const BatchProblem<double> *, const int4 *, int, int, int, int, int,
                                            hipStream_t);
 template int hx_cells_batch_launch<float>(int, const BatchProblem<float> *, const int4 *, int, int, int, int, int,
                                           hipStream_t);
-
-template <typename T, int NP>
-static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
-  int ntiles = (a.ncols + 63) / 64;
-  int ncell = color_end - color_begin;
-  if (ncell <= 0 || ntiles <= 0) return;
-  dim3 grid((unsigned)(ncell * ntiles)), block(256);
-  hipLaunchKernelGGL((hx_cells_kernel<T, NP>), grid, block, 0, s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K,
-                     a.cmap, a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2,
-                     a.shift);
-}
-
-template <typename T>
-int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
-  switch (a.np) {
-    case 16: launch_cells<T, 16>(a, color_begin, color_end, s); break;    // p = 1
-    case 32: launch_cells<T, 32>(a, color_begin, color_end, s); break;    // p = 2
-    case 64: launch_cells<T, 64>(a, color_begin, color_end, s); break;    // p = 3
-    case 128: launch_cells<T, 128>(a, color_begin, color_end, s); break;  // p = 4
-    case 224: launch_cells<T, 224>(a, color_begin, color_end, s); break;  // p = 5
-    case 352: launch_cells<T, 352>(a, color_begin, color_end, s); break;  // p = 6
-    case 512: launch_cells<T, 512>(a, color_begin, color_end, s); break;  // p = 7
-    default: return -1;
-  }
-  return 0;
-}
-
-template int hx_cells_launch<double>(const HxArgs<double> &, int, int, hipStream_t);
-template int hx_cells_launch<float>(const HxArgs<float> &, int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // Precision conversion and column-block copies (strided, DoF-major)
 // ---------------------------------------------------------------------------

@@ -27,6 +27,10 @@ struct HxArgs {
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s);
+// Columns per work-group of the cell kernel for padded cell size np (-1 if
+// np is not supported); column tiles of the batched work list use it.
+template <typename T>
+int hx_tile_width(int np);
 
 // One problem of a batched filter sweep (device-resident descriptor).
 template <typename T>
