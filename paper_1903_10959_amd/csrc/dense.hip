@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace chfsi {
 
@@ -27,70 +28,122 @@ __device__ __forceinline__ void tri_tile(int t, int &ti, int &tj) {
   tj = t - i * (i + 1) / 2;
 }
 
-template <typename T>
-__device__ __forceinline__ void gram_wave(const double *__restrict__ A, int64_t lda, const double *__restrict__ B,
-                                          int64_t ldb, int64_t r0, int64_t r1, int n, int i0, int j0, int lane,
-                                          double *__restrict__ out /* 128-wide tile row base at (i0,j0) */) {
-  typedef typename acc4<T>::type acc_t;
+// One (split, lower tile) work-group: partial G tile over rows [r0, r1).  The
+// contraction runs over chunks of 16 rows: the chunk's 128 columns of A and
+// of B are loaded into registers one chunk ahead (16-byte loads when the
+// leading dimensions are even), written to the other half of a
+// double-buffered LDS area after the chunk's MFMAs, and published by one
+// barrier per chunk.  Wave (wi, wj) owns the 64 x 64 quarter (wi, wj); on a
+// diagonal tile the strictly upper quarter is never read and is skipped.
+// mode 0: every lower tile, FP64.  Mixed overlap: mode 1 computes every
+// quarter except the 64 x 64 diagonal blocks with FP32 inputs and products,
+// mode 2 (diagonal tiles only) the diagonal blocks in FP64.
+template <int VEC, int MODE>
+__global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A, int64_t lda,
+                                                   const double *__restrict__ B, int64_t ldb, int64_t nrows, int n,
+                                                   int ntiles, int64_t rows_per_split, double *__restrict__ part) {
+  typedef double vec_t __attribute__((ext_vector_type(VEC)));
+  typedef typename std::conditional<MODE == 1, float, double>::type CT;   // product type
+  typedef typename acc4<CT>::type acc_t;
+  constexpr int KR = 16;                          // rows per chunk
+  constexpr int PT = KR * GT / (256 * VEC);       // vectors per thread per operand
+  __shared__ __align__(16) double As[2][KR][GT];
+  __shared__ __align__(16) double Bs[2][KR][GT];
+  const int ngrid = MODE == 2 ? (int)((sqrt(8.0 * ntiles + 1.0) - 1.0) * 0.5 + 0.5) : ntiles;
+  const int split = blockIdx.x / ngrid;
+  int t = blockIdx.x - split * ngrid;
+  int ti, tj;
+  if (MODE == 2) {
+    ti = tj = t;                                  // diagonal tile t
+    t = ti * (ti + 1) / 2 + ti;
+  } else {
+    tri_tile(t, ti, tj);
+  }
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wi = wave >> 1, wj = wave & 1;
   const int j = lane & 15, kq = lane >> 4;
+  const bool active = MODE == 0 ? !(ti == tj && wi < wj)      // strictly upper quarter: never read
+                    : MODE == 1 ? !(ti == tj && wi <= wj)
+                                : wi == wj;
+  const int64_t r0 = (int64_t)split * rows_per_split;
+  int64_t r1 = r0 + rows_per_split;
+  if (r1 > nrows) r1 = nrows;
+  const int ib = ti * GT, jb = tj * GT;           // tile origin
+
+  vec_t areg[PT], breg[PT];
+  // slot v -> (row v / (GT/VEC), column vector v % (GT/VEC)); out-of-range
+  // slots load a clamped in-bounds address and store zero
+  auto load_chunk = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int v = tid + 256 * i;
+      const int64_t row = min(k0 + v / (GT / VEC), r1 - 1);
+      const int cv = (v % (GT / VEC)) * VEC;
+      areg[i] = *reinterpret_cast<const vec_t *>(A + row * lda + min(ib + cv, n - VEC));
+      breg[i] = *reinterpret_cast<const vec_t *>(B + row * ldb + min(jb + cv, n - VEC));
+    }
+  };
+  auto store_chunk = [&](int buf, int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int v = tid + 256 * i;
+      const int kr = v / (GT / VEC), cv = (v % (GT / VEC)) * VEC;
+      const bool rok = k0 + kr < r1;
+      vec_t a = areg[i], b = breg[i];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        a[e] = (rok && ib + cv + e < n) ? a[e] : 0.0;
+        b[e] = (rok && jb + cv + e < n) ? b[e] : 0.0;
+      }
+      *reinterpret_cast<vec_t *>(&As[buf][kr][cv]) = a;
+      *reinterpret_cast<vec_t *>(&Bs[buf][kr][cv]) = b;
+    }
+  };
+
   acc_t acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  bool icol[4], jcol[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    icol[a] = i0 + a * 16 + j < n;
-    jcol[a] = j0 + a * 16 + j < n;
+  const int64_t nk = (r1 - r0 + KR - 1) / KR;
+  if (nk > 0) {
+    load_chunk(r0);
+    store_chunk(0, r0);
   }
-  for (int64_t k = r0; k < r1; k += 4) {
-    const int64_t row = k + kq;
-    const bool rok = row < r1;
-    T av[4], bv[4];
+  __syncthreads();
+#pragma unroll 1
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    const int buf = (int)(kc & 1);
+    if (kc + 1 < nk) load_chunk(r0 + (kc + 1) * KR);
+    if (active) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      av[a] = (rok && icol[a]) ? (T)A[row * lda + i0 + a * 16 + j] : T(0);
-      bv[a] = (rok && jcol[a]) ? (T)B[row * ldb + j0 + a * 16 + j] : T(0);
+      for (int ks = 0; ks < KR; ks += 4) {
+        const int kk = ks + kq;
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][wi * 64 + a * 16 + j];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][wj * 64 + b * 16 + j];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4((CT)av[a], (CT)bv[b], acc[a][b]);
+      }
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4(av[a], bv[b], acc[a][b]);
+    if (kc + 1 < nk) store_chunk(buf ^ 1, r0 + (kc + 1) * KR);
+    __syncthreads();
   }
+  if (!active) return;
+  double *out = part + ((int64_t)split * ntiles + t) * (GT * GT) + (wi * 64) * GT + wj * 64;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int ii = a * 16 + acc_row<T>(kq, q);
-        int jj = b * 16 + j;
-        out[ii * GT + jj] = (double)acc[a][b][q];
+        out[(a * 16 + acc_row<CT>(kq, q)) * GT + b * 16 + j] = (double)acc[a][b][q];
       }
-}
-
-__global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A, int64_t lda,
-                                                   const double *__restrict__ B, int64_t ldb, int64_t nrows, int n,
-                                                   int ntiles, int64_t rows_per_split, int mixed,
-                                                   double *__restrict__ part) {
-  const int split = blockIdx.x / ntiles;
-  const int t = blockIdx.x - split * ntiles;
-  int ti, tj;
-  tri_tile(t, ti, tj);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wj = wave & 1;
-  if (ti == tj && wi < wj) return;  // strictly upper quarter of a diagonal tile: never read
-  const int64_t r0 = (int64_t)split * rows_per_split;
-  int64_t r1 = r0 + rows_per_split;
-  if (r1 > nrows) r1 = nrows;
-  const int i0 = ti * GT + wi * 64, j0 = tj * GT + wj * 64;
-  double *out = part + ((int64_t)split * ntiles + t) * (GT * GT) + (wi * 64) * GT + wj * 64;
-  const bool diag64 = (ti == tj) && (wi == wj);
-  if (mixed && !diag64)
-    gram_wave<float>(A, lda, B, ldb, r0, r1, n, i0, j0, lane, out);
-  else
-    gram_wave<double>(A, lda, B, ldb, r0, r1, n, i0, j0, lane, out);
 }
 
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double *__restrict__ part, int nsplit, int ntiles,
@@ -134,8 +187,22 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
   int nsplit = gram_nsplit(nrows, n);
   int64_t rps = (nrows + nsplit - 1) / nsplit;
   rps = (rps + 15) / 16 * 16;
-  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)(nsplit * ntiles)), dim3(256), 0, s, A, lda, B, ldb, nrows, n,
-                     ntiles, rps, mixed, part);
+  const bool v16 = lda % 2 == 0 && ldb % 2 == 0 && n % 2 == 0 && ((uintptr_t)A % 16) == 0 &&
+                   ((uintptr_t)B % 16) == 0;
+  const int nt = (n + GT - 1) / GT;
+  const dim3 block(256), all((unsigned)(nsplit * ntiles)), diag((unsigned)(nsplit * nt));
+  if (!mixed) {
+    if (v16) hipLaunchKernelGGL((gram_kernel<2, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+    else hipLaunchKernelGGL((gram_kernel<1, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+  } else {
+    if (v16) {
+      hipLaunchKernelGGL((gram_kernel<2, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+      hipLaunchKernelGGL((gram_kernel<2, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+    } else {
+      hipLaunchKernelGGL((gram_kernel<1, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+      hipLaunchKernelGGL((gram_kernel<1, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+    }
+  }
   int64_t total = (int64_t)n * n;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
@@ -146,24 +213,32 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
 // Right multiplication X <- X W.  Rows are processed in chunks: an LDS-tiled
 // MFMA GEMM writes C = X_chunk W into a scratch chunk, a coalesced copy puts
 // it back (the paper's outer blocking over rows, which needs only a chunk of
-// extra memory).  Work-group tile 128 x 128 (4 waves x 64 x 64), K staged in
-// LDS 16 at a time, double buffered.  upper: W upper triangular, so output
-// column tile [n0, n0+128) only needs k < n0 + 128.  mixed (upper only): k in
-// the 64-wide diagonal block of a wave's columns in FP64, smaller k in FP32.
+// extra memory).  Work-group tile 128 x 128 (4 waves x 64 x 64); the
+// contraction runs over chunks of 16: the X chunk (128 rows x 16, stored
+// transposed so a fragment read is 16 consecutive words) and the W chunk
+// (16 x 128) are loaded into registers one chunk ahead (16-byte loads when
+// the leading dimensions are even), written to the other half of a
+// double-buffered LDS area after the chunk's MFMAs, and published by one
+// barrier per chunk.  upper: W upper triangular, so output column tile
+// [n0, n0+128) only needs k < n0 + 128.  mixed (upper only): k in the
+// 64-wide diagonal block of a wave's columns in FP64, smaller k in FP32.
 // ---------------------------------------------------------------------------
 static constexpr int MT = 128, NTL = 128, KC = 16;
-static constexpr int ALD = KC + 1;   // padded LDS row of the A tile (odd -> no bank conflicts)
 
-template <bool MIXED>
+template <bool MIXED, int VEC>
 __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict__ X, int64_t ld, int64_t row0,
                                                         int64_t nrows, int n, const double *__restrict__ W,
                                                         int upper, double *__restrict__ C, int64_t ldc) {
-  __shared__ double As[2][MT * ALD];
-  __shared__ double Ws[2][KC * NTL];
+  typedef double vec_t __attribute__((ext_vector_type(VEC)));
+  constexpr int APT = KC * MT / (256 * VEC);     // X vectors per thread per chunk
+  constexpr int WPT = KC * NTL / (256 * VEC);    // W vectors per thread per chunk
+  __shared__ __align__(16) double As[2][KC][MT];   // As[k][row]
+  __shared__ __align__(16) double Ws[2][KC][NTL];  // Ws[k][col]
   const int nt = (n + NTL - 1) / NTL;
   const int mt = blockIdx.x / nt;
   const int ntile = blockIdx.x - mt * nt;
   const int64_t r0 = row0 + (int64_t)mt * MT;    // first X row of this tile
+  const int64_t rlast = row0 + nrows - 1;         // last valid row
   const int n0 = ntile * NTL;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -173,70 +248,104 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
   const int c0 = n0 + wj * 64;                   // first column of this wave
   const int kdiag = MIXED ? (c0 / 64) * 64 : 0;  // mixed: k >= kdiag is the FP64 diagonal block
 
-  v4d acc[4][4];
-  v4f acc32[MIXED ? 4 : 1][MIXED ? 4 : 1];
+  // staging slots: X vector v -> (row v % MT, k-vector v / MT); W vector v ->
+  // (k-row v / (NTL/VEC), column vector v % (NTL/VEC)).  Out-of-range slots
+  // load a clamped in-bounds address and store zero.
+  vec_t areg[APT], wreg[WPT];
+  auto load_chunk = [&](int k0) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
-  if (MIXED) {
-#pragma unroll
-    for (int a = 0; a < (MIXED ? 4 : 1); ++a)
-#pragma unroll
-      for (int b = 0; b < (MIXED ? 4 : 1); ++b) acc32[a][b] = v4f{0, 0, 0, 0};
-  }
-
-  auto stage = [&](int buf, int k0) {
-    // A tile: 128 rows x 16 columns (each row 128 contiguous bytes)
-    for (int idx = tid; idx < MT * KC; idx += 256) {
-      const int r = idx / KC, c = idx - r * KC;
-      const int64_t row = r0 + r;
-      const int k = k0 + c;
-      As[buf][r * ALD + c] = (row < row0 + nrows && k < n) ? X[row * ld + k] : 0.0;
+    for (int i = 0; i < APT; ++i) {
+      const int v = tid + 256 * i;
+      const int64_t row = min(r0 + v % MT, rlast);
+      const int k = min(k0 + (v / MT) * VEC, n - VEC);
+      areg[i] = *reinterpret_cast<const vec_t *>(X + row * ld + k);
     }
-    // W tile: 16 rows x 128 columns
-    for (int idx = tid; idx < KC * NTL; idx += 256) {
-      const int r = idx / NTL, c = idx - r * NTL;
-      const int k = k0 + r, col = n0 + c;
-      Ws[buf][r * NTL + c] = (k < kend && col < n) ? W[(int64_t)k * n + col] : 0.0;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int v = tid + 256 * i;
+      const int k = min(k0 + v / (NTL / VEC), n - 1);
+      const int col = min(n0 + (v % (NTL / VEC)) * VEC, n - VEC);
+      wreg[i] = *reinterpret_cast<const vec_t *>(W + (int64_t)k * n + col);
+    }
+  };
+  auto store_chunk = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int v = tid + 256 * i;
+      const int r = v % MT, kv = (v / MT) * VEC;
+      const bool rok = r0 + r <= rlast;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) As[buf][kv + e][r] = (rok && k0 + kv + e < n) ? areg[i][e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int v = tid + 256 * i;
+      const int kr = v / (NTL / VEC), cv = (v % (NTL / VEC)) * VEC;
+      vec_t w = wreg[i];
+      const bool kok = k0 + kr < kend;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) w[e] = (kok && n0 + cv + e < n) ? w[e] : 0.0;
+      *reinterpret_cast<vec_t *>(&Ws[buf][kr][cv]) = w;
     }
   };
 
+  // one pipeline step: prefetch chunk kc + 1, multiply chunk kc, publish
+  // chunk kc + 1.  F32: FP32 inputs and products into acc32.
   const int nk = (kend + KC - 1) / KC;
-  if (nk > 0) stage(0, 0);
-  __syncthreads();
-  for (int kc = 0; kc < nk; ++kc) {
+  auto step = [&](int kc, auto f32, auto &accs) {
     const int buf = kc & 1;
-    if (kc + 1 < nk) stage(buf ^ 1, (kc + 1) * KC);
-    const int kbase = kc * KC;
+    if (kc + 1 < nk) load_chunk((kc + 1) * KC);
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 4) {
       const int kk = ks + kq;
       double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[buf][(wi * 64 + a * 16 + j) * ALD + kk];
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][wi * 64 + a * 16 + j];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Ws[buf][kk * NTL + wj * 64 + b * 16 + j];
-      if (!MIXED || kbase + ks >= kdiag) {
+      for (int b = 0; b < 4; ++b) bv[b] = Ws[buf][kk][wj * 64 + b * 16 + j];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4(av[a], bv[b], acc[a][b]);
-      } else {
-#pragma unroll
-        for (int a = 0; a < (MIXED ? 4 : 1); ++a)
-#pragma unroll
-          for (int b = 0; b < (MIXED ? 4 : 1); ++b) acc32[a][b] = mfma16x4((float)av[a], (float)bv[b], acc32[a][b]);
-      }
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (decltype(f32)::value)
+            accs[a][b] = mfma16x4((float)av[a], (float)bv[b], accs[a][b]);
+          else
+            accs[a][b] = mfma16x4(av[a], bv[b], accs[a][b]);
+        }
     }
+    if (kc + 1 < nk) store_chunk(buf ^ 1, (kc + 1) * KC);
     __syncthreads();
-  }
-  if (MIXED && kdiag > 0) {
+  };
+
+  load_chunk(0);
+  store_chunk(0, 0);
+  __syncthreads();
+  v4d acc[4][4];
+  int kc = 0;
+  if constexpr (MIXED) {
+    // chunks left of the wave's diagonal block in FP32 (kdiag is a multiple
+    // of 64, so chunks never straddle it), then the FP64 accumulators start
+    // from the converted FP32 sums
+    const int nk32 = min(kdiag / KC, nk);
+    v4f acc32[4][4];
 #pragma unroll
-    for (int a = 0; a < (MIXED ? 4 : 1); ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < (MIXED ? 4 : 1); ++b) acc[a][b] += f32acc_to_f64_layout(acc32[a][b], lane);
+      for (int b = 0; b < 4; ++b) acc32[a][b] = v4f{0, 0, 0, 0};
+#pragma unroll 1
+    for (; kc < nk32; ++kc) step(kc, std::true_type{}, acc32);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = f32acc_to_f64_layout(acc32[a][b], lane);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
   }
+#pragma unroll 1
+  for (; kc < nk; ++kc) step(kc, std::false_type{}, acc);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -271,17 +380,22 @@ int64_t rmul_chunk_rows(int n) {
 int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
                 double *scratch, hipStream_t s) {
   if (mixed && !upper) return -1;
+  if (n <= 0 || nrows <= 0) return 0;
   const int64_t chunk = rmul_chunk_rows(n);
+  // 16-byte operand loads need even leading dimensions and 16-byte aligned bases
+  const bool v16 = ld % 2 == 0 && n % 2 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)W % 16) == 0;
   const int nt = (n + NTL - 1) / NTL;
   for (int64_t r = 0; r < nrows; r += chunk) {
     const int64_t rows = (nrows - r < chunk) ? nrows - r : chunk;
     const int64_t mts = (rows + MT - 1) / MT;
-    if (mixed)
-      hipLaunchKernelGGL(rmul_gemm_kernel<true>, dim3((unsigned)(mts * nt)), dim3(256), 0, s, X, ld, r, rows, n, W,
-                         upper, scratch, (int64_t)n);
-    else
-      hipLaunchKernelGGL(rmul_gemm_kernel<false>, dim3((unsigned)(mts * nt)), dim3(256), 0, s, X, ld, r, rows, n, W,
-                         upper, scratch, (int64_t)n);
+    const dim3 grid((unsigned)(mts * nt)), block(256);
+    if (mixed) {
+      if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<true, 2>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
+      else hipLaunchKernelGGL((rmul_gemm_kernel<true, 1>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
+    } else {
+      if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<false, 2>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
+      else hipLaunchKernelGGL((rmul_gemm_kernel<false, 1>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
+    }
     int64_t total = rows * n;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
