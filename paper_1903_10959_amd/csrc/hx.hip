@@ -225,17 +225,50 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
     if (c + 1 < C::NCH) load_chunk(c + 1);
     const T *Kb = Ks[buf];
     const T *Xb = Xs[buf];
+    // Software pipeline over the chunk's (step, row-block pair) stages: the
+    // LDS reads of stage s + 1 (an A pair, and the B fragments when a new
+    // step starts) are issued before the MFMAs of stage s, and scheduling
+    // barriers keep that order, so each read has the MFMAs of one stage to
+    // land in.
+    constexpr int NPR = (C::RBW + 1) / 2;           // row-block pairs per step
+    constexpr int NST = (KC / 4) * NPR;             // stages per chunk
+    auto read_a = [&](int st, T(&a)[2]) {
+      const int kk = st / NPR, rp = st - kk * NPR;
+      const T *Ka = Kb + (4 * kk + kq) * C::SK + arow + 32 * rp;
+      a[0] = Ka[0];
+      a[1] = 2 * rp + 1 < C::RBW ? Ka[16] : T(0);
+    };
+    auto read_b = [&](int kk, T(&b)[CBW]) {
 #pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int k = 4 * kk + kq;
-      T b[CBW];
+      for (int cb = 0; cb < CBW; ++cb) b[cb] = Xb[(4 * kk + kq) * C::SX + bcol + 16 * cb];
+    };
+    T a_cur[2], a_nxt[2], b_cur[CBW], b_nxt[CBW];
+    read_b(0, b_cur);
+    read_a(0, a_cur);
 #pragma unroll
-      for (int cb = 0; cb < CBW; ++cb) b[cb] = Xb[k * C::SX + bcol + 16 * cb];
+    for (int st = 0; st < NST; ++st) {
+      const int kk = st / NPR, rp = st - kk * NPR;
+      if (st + 1 < NST) {
+        read_a(st + 1, a_nxt);
+        if ((st + 1) % NPR == 0) read_b(kk + 1, b_nxt);
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int r = 0; r < C::RBW; ++r) {
-        const T a = Kb[k * C::SK + arow + 16 * r];
+      for (int h = 0; h < 2; ++h) {
+        if (2 * rp + h < C::RBW) {
 #pragma unroll
-        for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = mfma16x4(a, b[cb], acc[r][cb]);
+          for (int cb = 0; cb < CBW; ++cb)
+            acc[2 * rp + h][cb] = mfma16x4(a_cur[h], b_cur[cb], acc[2 * rp + h][cb]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + 1 < NST) {
+        a_cur[0] = a_nxt[0];
+        a_cur[1] = a_nxt[1];
+        if ((st + 1) % NPR == 0) {
+#pragma unroll
+          for (int cb = 0; cb < CBW; ++cb) b_cur[cb] = b_nxt[cb];
+        }
       }
     }
     if (c + 1 < C::NCH) store_chunk(buf ^ 1, c + 1);
