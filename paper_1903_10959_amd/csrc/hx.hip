@@ -377,69 +377,75 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
     }
   }
   __syncthreads();
+  // waves in a 2 x 2 grid: wave (wr, wc) owns row blocks [wr*RBW, (wr+1)*RBW)
+  // and the two 16-column blocks of columns [32 wc, 32 wc + 32), so every K
+  // fragment loaded from L2 feeds two MFMAs and each wave reads half of K.
+  constexpr int RBW = RB / 2;
+  const int wr = wave >> 1, wc = wave & 1;
   const int j = lane & 15, kq = lane >> 4;
-  const int lcol = wave * 16 + j;               // column within the tile
-  const int col = col0 + lcol;
-  v4f acc[RB];
+  v4f acc[RBW][2];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) acc[r] = v4f{0, 0, 0, 0};
+  for (int r = 0; r < RBW; ++r) acc[r][0] = acc[r][1] = v4f{0, 0, 0, 0};
   typedef __attribute__((ext_vector_type(4))) int v4i;
-  for (int k = 0; k < NPB; k += 32) {
-    const int kk = k + 8 * kq;
-    v8bf bh, bl;
-    {
-      v4i t = *reinterpret_cast<const v4i *>(&xs[0][lcol * LDX + kk]);
-      bh = __builtin_bit_cast(v8bf, t);
-      if (SPLIT) {
-        v4i t2 = *reinterpret_cast<const v4i *>(&xs[NPART - 1][lcol * LDX + kk]);
-        bl = __builtin_bit_cast(v8bf, t2);
-      }
-    }
+  const __bf16 *Kh_w = Kh + (int64_t)(wr * RBW * 16 + j) * NPB + 8 * kq;   // A[i][k..k+7] = K[i][k..k+7]
+  const __bf16 *Kl_w = SPLIT ? Kl + (int64_t)(wr * RBW * 16 + j) * NPB + 8 * kq : nullptr;
+  auto load_a = [&](const __bf16 *Kp, int k, int r) {
+    return __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i *>(Kp + (int64_t)r * 16 * NPB + k));
+  };
+  // hi fragments one k-step ahead in ping-pong registers
+  v8bf ah[2][RBW];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      // A[i][k..k+7] = K[i][k..k+7] (row i = 16 r + j): one 16-byte load
-      const v4i ta = *reinterpret_cast<const v4i *>(Kh + (int64_t)(r * 16 + j) * NPB + kk);
-      const v8bf ah = __builtin_bit_cast(v8bf, ta);
-      acc[r] = mfma16x32bf(ah, bh, acc[r]);
-      if (SPLIT) {
-        const v4i tl = *reinterpret_cast<const v4i *>(Kl + (int64_t)(r * 16 + j) * NPB + kk);
-        const v8bf al = __builtin_bit_cast(v8bf, tl);
-        acc[r] = mfma16x32bf(ah, bl, acc[r]);
-        acc[r] = mfma16x32bf(al, bh, acc[r]);
+  for (int r = 0; r < RBW; ++r) ah[0][r] = load_a(Kh_w, 0, r);
+#pragma unroll 1
+  for (int k = 0; k < NPB; k += 64) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int kk = k + 32 * u;
+      if (kk >= NPB) break;                       // NPB is a multiple of 32
+      const int kn = kk + 32 < NPB ? kk + 32 : kk;
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) ah[u ^ 1][r] = load_a(Kh_w, kn, r);
+      v8bf bh[2], bl[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int lc = wc * 32 + cb * 16 + j;
+        bh[cb] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i *>(&xs[0][lc * LDX + kk + 8 * kq]));
+        if (SPLIT) bl[cb] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i *>(&xs[NPART - 1][lc * LDX + kk + 8 * kq]));
+      }
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[r][cb] = mfma16x32bf(ah[u][r], bh[cb], acc[r][cb]);
+        if (SPLIT) {
+          const v8bf al = load_a(Kl_w, kk, r);
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            acc[r][cb] = mfma16x32bf(ah[u][r], bl[cb], acc[r][cb]);
+            acc[r][cb] = mfma16x32bf(al, bh[cb], acc[r][cb]);
+          }
+        }
       }
     }
   }
-  if (col >= ncols) return;
+
+  // epilogue, software-pipelined one 16x16 fragment ahead
+  const EpiCtx<float> ec{X, ldx, Xp, ldp, Y, ldy, dof_s, mi_s, vd_s, ft_s, n_loc, s1, s2};
+  constexpr int NF = RBW * 2;
+  auto frag_col = [&](int i) { return col0 + wc * 32 + 16 * (i & 1) + j; };
+  auto frag_row = [&](int i) { return (wr * RBW + i / 2) * 16; };
+  EpiFrag<float> f[2];
+  {
+    const int c0 = frag_col(0);
+    epi_load(ec, frag_row(0), kq, c0 < ncols ? c0 : ncols - 1, f[0]);
+  }
 #pragma unroll
-  for (int r0 = 0; r0 < RB; r0 += 4) {
-    float old[4][4];
-#pragma unroll
-    for (int r = r0; r < r0 + 4 && r < RB; ++r)
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int row = r * 16 + acc_row<float>(kq, qq);
-        float v = 0.f;
-        if (row < n_loc && mi_s[row] != 0.f) {
-          const int64_t d = dof_s[row];
-          if (ft_s[row]) {
-            v = vd_s[row] * X[d * ldx + col];
-            if (Xp) v += s2 * Xp[d * ldp + col];
-          } else {
-            v = Y[d * ldy + col];
-          }
-        }
-        old[r - r0][qq] = v;
-      }
-#pragma unroll
-    for (int r = r0; r < r0 + 4 && r < RB; ++r)
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        const int row = r * 16 + acc_row<float>(kq, qq);
-        if (row < n_loc) {
-          const float w = mi_s[row];
-          if (w != 0.f) Y[(int64_t)dof_s[row] * ldy + col] = old[r - r0][qq] + s1 * w * acc[r][qq];
-        }
-      }
+  for (int i = 0; i < NF; ++i) {
+    if (i + 1 < NF) {
+      const int cn = frag_col(i + 1);
+      epi_load(ec, frag_row(i + 1), kq, cn < ncols ? cn : ncols - 1, f[(i + 1) & 1]);
+    }
+    const int ci = frag_col(i);
+    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i & 1], acc[i / 2][i & 1]);
   }
 }
 
