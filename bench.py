@@ -102,6 +102,23 @@ def batch_throughput(args):
         Xs.append(workload.start_block_device(pr.n_dof, pr.nblock, pr.x0_seed, device=dev))
         Ns.append(pr.nstates)
     torch.cuda.synchronize()
+    # autotuned cell-kernel tile per degree (FP32 filter): timed once per p on
+    # a scratch copy of one problem's block, then set on every context of that p
+    from paper_1903_10959_amd import autotune as AT
+
+    tiles = {}
+    t_tune = time.time()
+    for i, pr in enumerate(probs):
+        if pr.p not in tiles:
+            c = ctxs[i]
+            scratch = Xs[i].clone()
+            b = c.upper_bound
+            tiles[pr.p] = AT.tune_tile_variant(c, scratch, (0.5 * b, b, -50.0), prec="fp32", refresh=True)
+            del scratch
+        ctxs[i].set_tile_variant(tiles[pr.p])
+    torch.cuda.synchronize()
+    print(f"[bench] batch: tile variants per degree {tiles} (tuned in {time.time() - t_tune:.1f} s)",
+          file=sys.stderr, flush=True)
     tot_dofs = sum(pr.n_dof for pr in probs)
     print(f"[bench] batch: {len(probs)} problems, {tot_dofs} DoFs in all, setup {time.time() - t0:.1f} s",
           file=sys.stderr, flush=True)
@@ -127,7 +144,8 @@ def batch_throughput(args):
            "vs_baseline": None, "dtype": "fp32-filter/f64", "data": "synthetic",
            "config": {"workload": "batch: 64 problems, n_el in 4..12, p in 4..7, N in 16..256, L = 2.5 n_el, "
                                   f"{tot_dofs} DoFs in all, Chebyshev degree 20"},
-           "one_at_a_time_seconds": t_seq, "batch_seconds": t_batch, "speedup_vs_one_at_a_time": t_seq / t_batch}
+           "one_at_a_time_seconds": t_seq, "batch_seconds": t_batch, "speedup_vs_one_at_a_time": t_seq / t_batch,
+           "tile_variant_per_degree": {str(k): v for k, v in sorted(tiles.items())}}
     print(json.dumps(out), flush=True)
     for c in ctxs:
         c.close()

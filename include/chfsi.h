@@ -228,6 +228,16 @@ const char *chfsi_last_error(const chfsi_ctx *ctx);
 int chfsi_set_timing(chfsi_ctx *ctx, int enable);
 int chfsi_reset_timing(chfsi_ctx *ctx);
 int chfsi_last_filter_timing(chfsi_ctx *ctx, double *ms_cells, int *n_launches, int64_t *cell_vecs);
+/* Tile configuration of the cell-product kernel (the filter's work-group
+ * shape; Sec. 3.3 leaves the blocking of the cell-level products to the
+ * implementation): -1 = built-in choice (default), 0 = four waves with two
+ * 16-column blocks each, 1 = eight waves with one block each (more resident
+ * waves, fewer accumulators).  Every variant computes the same products; an
+ * autotuner times them per degree and precision and sets the faster.
+ * Applies to later filter/apply calls and to batch sweeps built after it
+ * (set it before adding the context to a batch session).  Errors:
+ * CHFSI_ERR_ARG for a null ctx or a variant outside -1..1. */
+int chfsi_set_tile_variant(chfsi_ctx *ctx, int variant);
 
 #ifdef __cplusplus
 }

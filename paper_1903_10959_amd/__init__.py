@@ -335,6 +335,12 @@ class Context:
                     dofvecs=rep.dofvecs)
 
     # ---- timing of the cell-product kernel ---------------------------------
+    def set_tile_variant(self, variant: int = -1):
+        """Cell-kernel tile configuration: -1 built-in, 0 four-wave, 1 eight-wave."""
+        self._check(self._lib.chfsi_set_tile_variant(self._h, int(variant)), "set_tile_variant")
+        self.tile_variant = int(variant)
+        return self
+
     def set_timing(self, enable: bool = True):
         self._check(self._lib.chfsi_set_timing(self._h, 1 if enable else 0), "set_timing")
 

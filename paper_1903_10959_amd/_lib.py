@@ -57,6 +57,7 @@ SIGNATURES = {
     "chfsi_status_string": (C.c_char_p, [_int]),
     "chfsi_last_error": (C.c_char_p, [_vp]),
     "chfsi_set_timing": (_int, [_vp, _int]),
+    "chfsi_set_tile_variant": (_int, [_vp, _int]),
     "chfsi_reset_timing": (_int, [_vp]),
     "chfsi_last_filter_timing": (_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
 }

@@ -1,12 +1,14 @@
-"""Autotuner for the filter's vector-block width.
+"""Autotuner for the filter: vector-block width and cell-kernel tile.
 
 The paper picks its filtering block size B^f by experiment (Sec. 3.3: too small
 wastes memory bandwidth and latency, too large costs memory and batched-GEMM
 efficiency).  Here the same trade-off is measured on the device: for a live
 problem, a short filter (a few Chebyshev steps) is timed at each candidate
 width and the fastest is cached per (architecture, degree p, block size N_b,
-precision).  Timing uses the context's HIP events on the cell-product kernel
-plus wall time around the call (the filter returns synchronised).
+precision).  The cell kernel's work-group tile (four waves with two column
+blocks each, or eight waves with one) is chosen the same way, per
+(architecture, degree p, precision).  Timing is wall time around the filter
+call, which returns synchronised.
 """
 from __future__ import annotations
 
@@ -19,6 +21,13 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chfsi_autotune.
 
 def _key(arch: str, p: int, nblock: int, prec: str) -> str:
     return f"{arch}|p{p}|nb{nblock}|{prec}"
+
+
+def _tile_key(arch: str, p: int, prec: str) -> str:
+    return f"tile|{arch}|p{p}|{prec}"
+
+
+TILE_VARIANTS = (0, 1)
 
 
 def candidates(nblock: int):
@@ -77,4 +86,38 @@ def tune_block_width(ctx, X, bounds, prec: str = "fp64", steps: int = 3, arch: s
     best = pick(timings)
     cache[key] = {"width": best, "timings_s": {str(k): v for k, v in timings.items()}}
     save_cache(cache, cache_path)
+    return best
+
+
+def tune_tile_variant(ctx, X, bounds, prec: str = "fp32", steps: int = 4, arch: str = None,
+                      cache_path: str = DEFAULT_CACHE, refresh: bool = False, timer=None, apply: bool = True):
+    """Fastest cell-kernel tile variant for ctx's degree and precision; sets it
+    on ctx when apply is true.  X (device, DoF-major) is filtered in place by
+    each trial, so pass a scratch copy.  `timer(variant) -> seconds` replaces
+    the device measurement (used by the tests)."""
+    if arch is None:
+        import torch
+
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if timer is None else "test"
+    key = _tile_key(arch, int(getattr(ctx, "p", 0)), prec)
+    cache = load_cache(cache_path)
+    if not refresh and key in cache:
+        best = int(cache[key]["variant"])
+    else:
+        timings = {}
+        for v in TILE_VARIANTS:
+            if timer is not None:
+                timings[v] = float(timer(v))
+                continue
+            a, b, a0 = bounds
+            ctx.set_tile_variant(v)
+            ctx.chebyshev_filter(X, 1, a, b, a0, prec=prec)            # warm-up
+            t0 = time.perf_counter()
+            ctx.chebyshev_filter(X, steps, a, b, a0, prec=prec)
+            timings[v] = time.perf_counter() - t0
+        best = pick(timings)
+        cache[key] = {"variant": best, "timings_s": {str(k): v for k, v in timings.items()}}
+        save_cache(cache, cache_path)
+    if apply and timer is None:
+        ctx.set_tile_variant(best)
     return best

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -153,7 +154,7 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
   if (ids.empty()) return 0;
   const bool f64 = sizeof(T) == 8;
   std::vector<BatchProblem<T>> hp;
-  std::map<std::pair<int, int>, std::vector<int4>> lists;  // (np, colour) -> items
+  std::map<std::tuple<int, int, int>, std::vector<int4>> lists;  // (np, tile variant, colour) -> items
   for (size_t m = 0; m < ids.size(); ++m) {
     Prob &p = B->probs[ids[m]];
     chfsi_ctx *c = p.c;
@@ -174,24 +175,24 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
     P.n_el = c->mesh.n_el;
     P.ncols = nb;
     hp.push_back(P);
-    const int tw = hx_tile_width<T>(c->mesh.np);
+    const int tw = hx_tile_width<T>(c->mesh.np, c->tile_variant);
     if (tw <= 0) return bfail(B, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
     const int ntiles = (nb + tw - 1) / tw;
     for (int col = 0; col < 8; ++col)
       for (int s = c->mesh.color_offset[col]; s < c->mesh.color_offset[col + 1]; ++s)
         for (int t = 0; t < ntiles; ++t)
-          lists[{c->mesh.np, col}].push_back(make_int4((int)m, c->mesh.cell_order[s], t, 0));
+          lists[{c->mesh.np, c->tile_variant, col}].push_back(make_int4((int)m, c->mesh.cell_order[s], t, 0));
   }
   BCHK(B, S.coef.ensure((size_t)3 * B->degree * ids.size() * sizeof(T)));
   for (size_t m = 0; m < hp.size(); ++m) hp[m].coef = S.coef.template as<T>() + (size_t)3 * B->degree * m;
   std::vector<int4> all;
-  std::vector<std::pair<int, int>> groups;  // (np, offset)
+  std::vector<std::tuple<int, int, int>> groups;  // (np, tile variant, offset)
   std::vector<int> counts;
   // colour-major launch order: every problem sees its colours in order 0..7
   for (int col = 0; col < 8; ++col)
     for (auto &kv : lists)
-      if (kv.first.second == col) {
-        groups.push_back({kv.first.first, (int)all.size()});
+      if (std::get<2>(kv.first) == col) {
+        groups.push_back({std::get<0>(kv.first), std::get<1>(kv.first), (int)all.size()});
         counts.push_back((int)kv.second.size());
         all.insert(all.end(), kv.second.begin(), kv.second.end());
       }
@@ -213,9 +214,10 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
   int lerr = 0;
   for (int k = 0; k < B->degree; ++k)
     for (size_t g = 0; g < groups.size(); ++g)
-      lerr |= hx_cells_batch_launch<T>(groups[g].first, S.probs.template as<BatchProblem<T>>(),
-                                       S.work.template as<int4>() + groups[g].second, counts[g], k, cur[k], prev[k],
-                                       out[k], B->stream);
+      lerr |= hx_cells_batch_launch<T>(std::get<0>(groups[g]), std::get<1>(groups[g]),
+                                       S.probs.template as<BatchProblem<T>>(),
+                                       S.work.template as<int4>() + std::get<2>(groups[g]), counts[g], k, cur[k],
+                                       prev[k], out[k], B->stream);
   for (size_t m = 0; m < ids.size(); ++m) {
     Prob &p = B->probs[ids[m]];
     if (!f64)

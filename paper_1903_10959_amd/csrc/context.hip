@@ -271,6 +271,13 @@ extern "C" int chfsi_set_timing(chfsi_ctx *c, int enable) {
   return 0;
 }
 
+extern "C" int chfsi_set_tile_variant(chfsi_ctx *c, int variant) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (variant < -1 || variant > 1) return fail(c, CHFSI_ERR_ARG, "tile variant must be -1, 0 or 1");
+  c->tile_variant = variant;
+  return 0;
+}
+
 extern "C" int chfsi_reset_timing(chfsi_ctx *c) {
   if (!c) return CHFSI_ERR_ARG;
   c->ev_used = 0;
@@ -334,6 +341,7 @@ static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64
   a.s1 = (T)s1;
   a.s2 = (T)s2;
   a.shift = (T)shift;
+  a.variant = c->tile_variant;
   for (int col = 0; col < 8; ++col) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {

@@ -49,6 +49,7 @@ struct chfsi_ctx {
   // device tables
   chfsi::DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
   int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
+  int tile_variant = -1;  // cell-kernel tile configuration (-1: built-in choice)
   // workspaces
   chfsi::DevBuf fbuf[3];      // filter recursion buffers
   chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,

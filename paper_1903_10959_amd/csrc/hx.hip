@@ -304,7 +304,12 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 // read.  SPLIT: X = hi + lo and K = hi + lo in BF16, three products
 // hi*hi + hi*lo + lo*hi accumulated in FP32.  NPB: n_loc rounded up to 32.
 // ---------------------------------------------------------------------------
-template <int NPB, bool SPLIT>
+// Epilogue depth (fragments in flight) of the BF16 kernel.
+#ifndef CHFSI_BF16_EPD
+#define CHFSI_BF16_EPD 2
+#endif
+
+template <int NPB, bool SPLIT, int EPD = CHFSI_BF16_EPD>
 __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
                                                             const float *__restrict__ Xp, int64_t ldp,
                                                             float *__restrict__ Y, int64_t ldy,
@@ -341,7 +346,10 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   // stage: 4 consecutive columns per thread per row (16-byte global loads when
   // aligned), SU rows per thread per round with every load issued first
   const bool vec_ok = ((ldx & 3) == 0) && ((col0 & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
-  constexpr int SU = 8;
+#ifndef CHFSI_BF16_SU
+#define CHFSI_BF16_SU 8
+#endif
+  constexpr int SU = CHFSI_BF16_SU;
   for (int base = threadIdx.x; base < NPB * 16; base += SU * 256) {
     float v[SU][4];
 #pragma unroll
@@ -428,24 +436,24 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
     }
   }
 
-  // epilogue, software-pipelined one 16x16 fragment ahead
+  // epilogue, software-pipelined EPD - 1 fragments ahead
   const EpiCtx<float> ec{X, ldx, Xp, ldp, Y, ldy, dof_s, mi_s, vd_s, ft_s, n_loc, s1, s2};
   constexpr int NF = RBW * 2;
   auto frag_col = [&](int i) { return col0 + wc * 32 + 16 * (i & 1) + j; };
   auto frag_row = [&](int i) { return (wr * RBW + i / 2) * 16; };
-  EpiFrag<float> f[2];
-  {
-    const int c0 = frag_col(0);
-    epi_load(ec, frag_row(0), kq, c0 < ncols ? c0 : ncols - 1, f[0]);
-  }
+  auto frag_load = [&](int i, EpiFrag<float> &f) {
+    const int ci = frag_col(i);
+    epi_load(ec, frag_row(i), kq, ci < ncols ? ci : ncols - 1, f);
+  };
+  EpiFrag<float> f[EPD];
+#pragma unroll
+  for (int i = 0; i < EPD - 1; ++i)
+    if (i < NF) frag_load(i, f[i]);
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    if (i + 1 < NF) {
-      const int cn = frag_col(i + 1);
-      epi_load(ec, frag_row(i + 1), kq, cn < ncols ? cn : ncols - 1, f[(i + 1) & 1]);
-    }
+    if (i + EPD - 1 < NF) frag_load(i + EPD - 1, f[(i + EPD - 1) % EPD]);
     const int ci = frag_col(i);
-    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i & 1], acc[i / 2][i & 1]);
+    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i % EPD], acc[i / 2][i & 1]);
   }
 }
 
@@ -477,114 +485,138 @@ int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hi
   return a.split ? dispatch_bf16<true>(a, color_begin, color_end, s) : dispatch_bf16<false>(a, color_begin, color_end, s);
 }
 
-// Tile configuration per padded cell size: waves per work-group, the split
+// Tile configurations per padded cell size: waves per work-group, the split
 // of the row blocks over waves, column blocks per wave, contraction chunk.
-// Four waves with 2 x 2 column blocks suit most sizes; the FP64 p = 5 tile
-// runs eight single-column-block waves (four waves per SIMD instead of two,
-// measured 1.3x faster); p = 7 splits its 32 row blocks over four waves.
-template <typename T, int NP>
+//  * variant 0: four waves, 2 x 2 grid, two column blocks per wave (the A
+//    fragment of every LDS read feeds two MFMAs); p = 7 splits its 32 row
+//    blocks over four waves;
+//  * variant 1: eight waves, 2 x 4 grid, one column block per wave: half the
+//    accumulators, so four waves per SIMD instead of two.  Only where the
+//    accumulators fit 128 registers (FP64 up to p = 5, FP32 up to p = 7);
+//    elsewhere variant 1 is variant 0.
+// The built-in choice (variant -1) is variant 1 for FP64 p = 5 (measured 1.3x
+// faster there) and variant 0 otherwise; the autotuner times both.
+template <typename T, int NP, int V>
 struct TileCfg {
-  static constexpr bool w8 = sizeof(T) == 8 && NP == 224;
+  static constexpr bool w8 = V == 1 && NP >= 32 && (sizeof(T) == 8 ? NP <= 224 : NP <= 512);
   static constexpr int NW = w8 ? 8 : 4;
-  static constexpr int WR = NP == 16 ? 1 : (NP == 512 ? 4 : 2);
+  static constexpr int WR = NP == 16 ? 1 : ((NP == 512 && !w8) ? 4 : 2);
   static constexpr int CBW = (NP == 16 || w8) ? 1 : 2;
   static constexpr int KC = 8;
-  static constexpr int EPD = 2;
+#ifndef CHFSI_CELL_EPD
+#define CHFSI_CELL_EPD 2
+#endif
+  static constexpr int EPD = sizeof(T) == 4 ? CHFSI_CELL_EPD : 2;
   typedef LdsTile<T, NP, NW, WR, CBW, KC> L;
   // eight-wave tiles must keep four waves per SIMD (two work-groups per CU)
   static constexpr int WAVES = NW == 8 ? 4 : 1;
 };
 
-#define CHFSI_CELL_TILE(T, NP, ...)                                                                    \
-  cell_tile<T, NP, TileCfg<T, NP>::NW, TileCfg<T, NP>::WR, TileCfg<T, NP>::CBW, TileCfg<T, NP>::KC, \
-            TileCfg<T, NP>::EPD>(__VA_ARGS__)
+template <typename T>
+static int default_variant(int np) {
+  return (sizeof(T) == 8 && np == 224) ? 1 : 0;
+}
 
-template <typename T, int NP>
-__global__ __launch_bounds__((64 * TileCfg<T, NP>::NW)) __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP>::WAVES)))
-void hx_cells_kernel(const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp, int64_t ldp, T *__restrict__ Y,
-                     int64_t ldy, const T *__restrict__ K, const int32_t *__restrict__ cmap, int n_loc, int q,
-                     int n_el, const int32_t *__restrict__ cells, const T *__restrict__ minv,
-                     const T *__restrict__ V, int ncols, int ntiles, T s1, T s2, T shift) {
+#define CHFSI_CELL_TILE(T, NP, V, ...)                                                                       \
+  cell_tile<T, NP, TileCfg<T, NP, V>::NW, TileCfg<T, NP, V>::WR, TileCfg<T, NP, V>::CBW, TileCfg<T, NP, V>::KC, \
+            TileCfg<T, NP, V>::EPD>(__VA_ARGS__)
+
+template <typename T, int NP, int V>
+__global__ __launch_bounds__((64 * TileCfg<T, NP, V>::NW))
+__attribute__((amdgpu_waves_per_eu(TileCfg<T, NP, V>::WAVES))) void hx_cells_kernel(
+    const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp, int64_t ldp, T *__restrict__ Y, int64_t ldy,
+    const T *__restrict__ K, const int32_t *__restrict__ cmap, int n_loc, int q, int n_el,
+    const int32_t *__restrict__ cells, const T *__restrict__ minv, const T *__restrict__ V_, int ncols, int ntiles,
+    T s1, T s2, T shift) {
   const int cell_slot = blockIdx.x / ntiles;
   const int tile = blockIdx.x - cell_slot * ntiles;
-  CHFSI_CELL_TILE(T, NP, X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V, ncols,
+  CHFSI_CELL_TILE(T, NP, V, X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols,
                   s1, s2, shift);
 }
 
 // Batched: work item = (problem, cell, column tile); the step's buffer roles
 // (input, previous, output) are the same for every problem, its coefficients
 // come from the problem's table (s1, s2, shift per step).
-template <typename T, int NP>
-__global__ __launch_bounds__((64 * TileCfg<T, NP>::NW)) __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP>::WAVES)))
-void hx_cells_batch_kernel(const BatchProblem<T> *__restrict__ probs, const int4 *__restrict__ work, int step,
-                           int cur, int prev, int out) {
+template <typename T, int NP, int V>
+__global__ __launch_bounds__((64 * TileCfg<T, NP, V>::NW))
+__attribute__((amdgpu_waves_per_eu(TileCfg<T, NP, V>::WAVES))) void hx_cells_batch_kernel(
+    const BatchProblem<T> *__restrict__ probs, const int4 *__restrict__ work, int step, int cur, int prev, int out) {
   const int4 w = work[blockIdx.x];
   const BatchProblem<T> &P = probs[w.x];
   const T *coef = P.coef + 3 * step;
-  CHFSI_CELL_TILE(T, NP, P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
+  CHFSI_CELL_TILE(T, NP, V, P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
                   P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el, w.y, w.z, P.minv, P.V, P.ncols, coef[0],
                   coef[1], coef[2]);
 }
 #undef CHFSI_CELL_TILE
 
-template <typename T, int NP>
+template <typename T, int NP, int V>
 static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
-  constexpr int TW = TileCfg<T, NP>::L::TW;
+  constexpr int TW = TileCfg<T, NP, V>::L::TW;
   const int ntiles = (a.ncols + TW - 1) / TW;
   const int ncell = color_end - color_begin;
   if (ncell <= 0 || ntiles <= 0) return;
-  hipLaunchKernelGGL((hx_cells_kernel<T, NP>), dim3((unsigned)(ncell * ntiles)), dim3(64 * TileCfg<T, NP>::NW), 0,
-                     s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.cmap, a.n_loc, a.q, a.n_el,
-                     a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
+  hipLaunchKernelGGL((hx_cells_kernel<T, NP, V>), dim3((unsigned)(ncell * ntiles)),
+                     dim3(64 * TileCfg<T, NP, V>::NW), 0, s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.cmap,
+                     a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
 }
 
-template <typename T, int NP>
+template <typename T, int NP, int V>
 static void launch_batch(const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur, int prev,
                          int out, hipStream_t s) {
   if (nwork <= 0) return;
-  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP>), dim3((unsigned)nwork), dim3(64 * TileCfg<T, NP>::NW), 0, s,
-                     probs, work, step, cur, prev, out);
+  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP, V>), dim3((unsigned)nwork), dim3(64 * TileCfg<T, NP, V>::NW), 0,
+                     s, probs, work, step, cur, prev, out);
 }
 
-// Calls f.template run<NP>() for a supported padded cell size; -1 otherwise.
-template <typename F>
-static int with_np(int np, F &&f) {
+// Calls f.template run<NP, V>() for a supported padded cell size and tile
+// variant (-1: the built-in choice); -1 otherwise.
+template <typename T, typename F>
+static int with_cfg(int np, int variant, F &&f) {
+  if (variant < 0) variant = default_variant<T>(np);
+  if (variant > 1) return -1;
+#define CHFSI_NP_CASE(N)                      \
+  case N:                                     \
+    if (variant == 0) f.template run<N, 0>(); \
+    else f.template run<N, 1>();              \
+    return 0;
   switch (np) {
-    case 16: f.template run<16>(); return 0;    // p = 1
-    case 32: f.template run<32>(); return 0;    // p = 2
-    case 64: f.template run<64>(); return 0;    // p = 3
-    case 128: f.template run<128>(); return 0;  // p = 4
-    case 224: f.template run<224>(); return 0;  // p = 5
-    case 352: f.template run<352>(); return 0;  // p = 6
-    case 512: f.template run<512>(); return 0;  // p = 7
+    CHFSI_NP_CASE(16)    // p = 1
+    CHFSI_NP_CASE(32)    // p = 2
+    CHFSI_NP_CASE(64)    // p = 3
+    CHFSI_NP_CASE(128)   // p = 4
+    CHFSI_NP_CASE(224)   // p = 5
+    CHFSI_NP_CASE(352)   // p = 6
+    CHFSI_NP_CASE(512)   // p = 7
     default: return -1;
   }
+#undef CHFSI_NP_CASE
 }
 
 template <typename T>
 struct TileWidthOp {
   int tw = 0;
-  template <int NP> void run() { tw = TileCfg<T, NP>::L::TW; }
+  template <int NP, int V> void run() { tw = TileCfg<T, NP, V>::L::TW; }
 };
 template <typename T>
-int hx_tile_width(int np) {
+int hx_tile_width(int np, int variant) {
   TileWidthOp<T> op;
-  return with_np(np, op) == 0 ? op.tw : -1;
+  return with_cfg<T>(np, variant, op) == 0 ? op.tw : -1;
 }
-template int hx_tile_width<double>(int);
-template int hx_tile_width<float>(int);
+template int hx_tile_width<double>(int, int);
+template int hx_tile_width<float>(int, int);
 
 template <typename T>
 struct LaunchCellsOp {
   const HxArgs<T> &a;
   int cb, ce;
   hipStream_t s;
-  template <int NP> void run() { launch_cells<T, NP>(a, cb, ce, s); }
+  template <int NP, int V> void run() { launch_cells<T, NP, V>(a, cb, ce, s); }
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
   LaunchCellsOp<T> op{a, color_begin, color_end, s};
-  return with_np(a.np, op);
+  return with_cfg<T>(a.np, a.variant, op);
 }
 template int hx_cells_launch<double>(const HxArgs<double> &, int, int, hipStream_t);
 template int hx_cells_launch<float>(const HxArgs<float> &, int, int, hipStream_t);
@@ -595,17 +627,17 @@ struct LaunchBatchOp {
   const int4 *work;
   int nwork, step, cur, prev, out;
   hipStream_t s;
-  template <int NP> void run() { launch_batch<T, NP>(probs, work, nwork, step, cur, prev, out, s); }
+  template <int NP, int V> void run() { launch_batch<T, NP, V>(probs, work, nwork, step, cur, prev, out, s); }
 };
 template <typename T>
-int hx_cells_batch_launch(int np, const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur,
-                          int prev, int out, hipStream_t s) {
+int hx_cells_batch_launch(int np, int variant, const BatchProblem<T> *probs, const int4 *work, int nwork, int step,
+                          int cur, int prev, int out, hipStream_t s) {
   LaunchBatchOp<T> op{probs, work, nwork, step, cur, prev, out, s};
-  return with_np(np, op);
+  return with_cfg<T>(np, variant, op);
 }
-template int hx_cells_batch_launch<double>(int, const BatchProblem<double> *, const int4 *, int, int, int, int, int,
-                                           hipStream_t);
-template int hx_cells_batch_launch<float>(int, const BatchProblem<float> *, const int4 *, int, int, int, int, int,
+template int hx_cells_batch_launch<double>(int, int, const BatchProblem<double> *, const int4 *, int, int, int, int,
+                                           int, hipStream_t);
+template int hx_cells_batch_launch<float>(int, int, const BatchProblem<float> *, const int4 *, int, int, int, int, int,
                                           hipStream_t);
 // ---------------------------------------------------------------------------
 // Precision conversion and column-block copies (strided, DoF-major)

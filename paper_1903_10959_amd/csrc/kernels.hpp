@@ -24,13 +24,14 @@ struct HxArgs {
   const T *V;          // potential [n_dof]
   int ncols;
   T s1, s2, shift;
+  int variant;         // tile configuration: -1 built-in choice, 0 four-wave, 1 eight-wave
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s);
 // Columns per work-group of the cell kernel for padded cell size np (-1 if
 // np is not supported); column tiles of the batched work list use it.
 template <typename T>
-int hx_tile_width(int np);
+int hx_tile_width(int np, int variant);
 
 // One problem of a batched filter sweep (device-resident descriptor).
 template <typename T>
@@ -47,8 +48,8 @@ struct BatchProblem {
 // items (int4: x = problem, y = cell, z = tile) whose problems share the padded
 // cell size np.
 template <typename T>
-int hx_cells_batch_launch(int np, const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur,
-                          int prev, int out, hipStream_t s);
+int hx_cells_batch_launch(int np, int variant, const BatchProblem<T> *probs, const int4 *work, int nwork, int step,
+                          int cur, int prev, int out, hipStream_t s);
 // BF16 cell products: FP32 X/Y/minv, K_ref as BF16 hi (and lo when split),
 // padded to npb = round_up(n_loc, 32).
 struct HxBf16Args {

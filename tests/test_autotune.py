@@ -33,3 +33,22 @@ def test_tuner_picks_fastest_and_caches(tmp_path):
 
 def test_ties_prefer_the_smaller_width():
     assert AT.pick({128: 1.0, 256: 1.0, 64: 2.0}) == 128
+
+
+def test_tile_variant_tuner_picks_fastest_and_caches(tmp_path):
+    path = str(tmp_path / "cache.json")
+    calls = []
+
+    def timer(v):
+        calls.append(v)
+        return {0: 2.0, 1: 1.5}[v]
+
+    assert AT.tune_tile_variant(_Ctx(), None, None, "fp32", cache_path=path, timer=timer, arch="gfx950") == 1
+    assert calls == [0, 1]
+    assert AT.tune_tile_variant(_Ctx(), None, None, "fp32", cache_path=path, timer=timer, arch="gfx950") == 1
+    assert calls == [0, 1]                      # cached
+    assert "tile|gfx950|p6|fp32" in AT.load_cache(path)
+
+
+def test_tile_variant_ties_prefer_variant_zero():
+    assert AT.pick({0: 1.0, 1: 1.0}) == 0

@@ -37,6 +37,32 @@ def test_apply_fp64_matches_oracle(n_el, p, ncols, ld):
     c.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n_el,p,ncols", [(4, 4, 70), (3, 5, 65), (2, 6, 33), (2, 7, 20), (5, 3, 64), (3, 2, 40)])
+def test_apply_tile_variants_match_oracle(variant, n_el, p, ncols):
+    """Both cell-kernel tile configurations give the oracle's product (FP64 to
+    rounding, FP32 at single-precision level)."""
+    L = 2.5 * n_el
+    wells = workload.draw_wells(4, L, 41 + p, (1.0, 3.0), (0.3, 0.6))
+    c, V = make_ctx(L, n_el, p, wells=wells)
+    c.set_tile_variant(variant)
+    X = workload.start_block(c.n_dof, ncols, 3000 + p)
+    Yo = oracle_apply(L, n_el, p, V)(X)
+    e64 = _rel(to_host(c.apply(to_gpu(X))), Yo)
+    e32 = _rel(to_host(c.apply(to_gpu(X), prec="fp32")), Yo)
+    assert e64 < 1e-13, e64
+    assert e32 < 2e-6, e32
+    c.close()
+
+
+def test_tile_variant_rejects_unknown():
+    prob = workload.PROBLEMS["small"]
+    c, _ = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    with pytest.raises(Exception):
+        c.set_tile_variant(2)
+    c.close()
+
+
 def test_apply_fp32_close_to_oracle():
     prob = workload.PROBLEMS["small"]
     c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
