@@ -131,6 +131,9 @@ struct chfsi_batch {
   Sweep<float> s32;
   bool verbose = false;
   int threads = 8;
+  // shared Jacobi eigensolve of the projected Hamiltonians
+  chfsi::DevBuf jac_table, jac_norms;
+  std::vector<double> jac_host;
 };
 
 namespace {
@@ -285,21 +288,47 @@ int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *m
 }
 
 // CholGS + RR of problem p; updates its residual, rung and state
-int subspace_step(Prob &p, bool filtered) {
-  if (int r = set_dev(p.c)) return r;
-  int passes = 0;
-  if (int r = orth_robust(p.c, p.X, p.ld, p.o.nblock, filtered ? mixed_now(p) : 0, &passes)) return r;
-  if (int r = rr_impl(p.c, p.X, p.ld, p.o.nblock, p.c->HX.as<double>(), p.o.nblock, p.evals, p.resid, nullptr))
-    return r;
-  const double nres = max_wanted(p);
-  if (filtered) {
-    p.rep.iters++;
-    p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock;
-    if (p.rung + 1 < n_rungs(p) && (nres > 0.98 * p.res || nres < rung_tol(p))) ++p.rung;
-  } else {
-    p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock;
-  }
-  p.res = nres;
+// CholGS + Rayleigh-Ritz of many problems: CholGS and the projection per
+// problem on its own stream (host threads), one batched Jacobi eigensolve of
+// all projected Hamiltonians on the batch stream, then the rotations and
+// residuals per problem.
+int subspace_steps(chfsi_batch *B, const std::vector<int> &ids, bool filtered) {
+  if (ids.empty()) return 0;
+  int st = parallel_for((int)ids.size(), B->threads, [&](int i) {
+    Prob &p = B->probs[ids[i]];
+    if (int r = set_dev(p.c)) return r;
+    int passes = 0;
+    if (int r = orth_robust(p.c, p.X, p.ld, p.o.nblock, filtered ? mixed_now(p) : 0, &passes)) return r;
+    if (int r = rr_project(p.c, p.X, p.ld, p.o.nblock, p.c->HX.as<double>(), p.o.nblock)) return r;
+    return hipStreamSynchronize(p.c->stream) == hipSuccess ? 0 : (int)CHFSI_ERR_HIP;
+  });
+  if (st) return bfail(B, st, "batch: CholGS or projection of a problem failed");
+  std::vector<JacobiJob> jobs;
+  for (int id : ids) jobs.push_back(rr_eigen_job(B->probs[id].c, B->probs[id].o.nblock));
+  BCHK(B, B->jac_table.ensure(jacobi_table_bytes((int)jobs.size())));
+  BCHK(B, B->jac_norms.ensure(2 * jobs.size() * sizeof(double)));
+  B->jac_host.resize(2 * jobs.size());
+  if (jacobi_eigh_batch(jobs.data(), (int)jobs.size(), 1e-14, 40, B->jac_table.p, B->jac_norms.as<double>(),
+                        B->jac_host.data(), B->stream, nullptr) != 0)
+    return bfail(B, CHFSI_ERR_HIP, "batch: Jacobi eigensolve failed");
+  BCHK(B, hipStreamSynchronize(B->stream));
+  st = parallel_for((int)ids.size(), B->threads, [&](int i) {
+    Prob &p = B->probs[ids[i]];
+    if (int r = set_dev(p.c)) return r;
+    if (int r = rr_finish(p.c, p.X, p.ld, p.o.nblock, p.c->HX.as<double>(), p.o.nblock, p.evals, p.resid))
+      return r;
+    const double nres = max_wanted(p);
+    if (filtered) {
+      p.rep.iters++;
+      p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock;
+      if (p.rung + 1 < n_rungs(p) && (nres > 0.98 * p.res || nres < rung_tol(p))) ++p.rung;
+    } else {
+      p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock;
+    }
+    p.res = nres;
+    return 0;
+  });
+  if (st) return bfail(B, st, "batch: Rayleigh-Ritz of a problem failed");
   return 0;
 }
 
@@ -329,6 +358,8 @@ extern "C" int chfsi_batch_destroy(chfsi_batch *b) {
   (void)hipStreamSynchronize(b->stream);
   b->s64.release();
   b->s32.release();
+  b->jac_table.release();
+  b->jac_norms.release();
   (void)hipStreamDestroy(b->stream);
   delete b;
   return 0;
@@ -390,8 +421,7 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   std::vector<int> fresh;
   for (Prob &p : b->probs)
     if (!p.done && !p.started) fresh.push_back(p.id);
-  int st = parallel_for((int)fresh.size(), b->threads, [&](int i) { return subspace_step(b->probs[fresh[i]], false); });
-  if (st) return bfail(b, st, "batch: start of a problem failed");
+  if (int st = subspace_steps(b, fresh, false)) return st;
   for (int id : fresh) {
     Prob &p = b->probs[id];
     p.started = true;
@@ -407,14 +437,13 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   // 3. CholGS + RR of every swept problem
   std::vector<int> swept(g32);
   swept.insert(swept.end(), g64.begin(), g64.end());
-  st = parallel_for((int)swept.size(), b->threads, [&](int i) {
-    Prob &p = b->probs[swept[i]];
+  for (int id : swept) {
+    Prob &p = b->probs[id];
     const bool f32 = rung_prec(p) == CHFSI_FP32;
     p.rep.t_filter += (f32 ? ms32 : ms64) * 1e-3;
     p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock * b->degree;
-    return subspace_step(p, true);
-  });
-  if (st) return bfail(b, st, "batch: CholGS/RR of a problem failed");
+  }
+  if (int st = subspace_steps(b, swept, true)) return st;
   int remaining = 0;
   for (int id : swept) {
     Prob &p = b->probs[id];

@@ -595,16 +595,26 @@ int chfsi::orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, i
 // ---------------------------------------------------------------------------
 // rayleighRitz
 // ---------------------------------------------------------------------------
-int chfsi::rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
-                   double *resid, int *sweeps) {
+// Part 1: HX = Htilde X and the projected Hamiltonian G = X^T HX (into Smat).
+int chfsi::rr_project(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh) {
   const int64_t nd = c->mesh.n_dof;
   if (int r = cheb_step_t<double>(c, X, ld, nullptr, 0, HX, ldh, ncols, 1.0, 0.0, 0.0)) return r;
-  double *G = c->Smat.as<double>();
-  gram_launch(X, ld, HX, ldh, nd, ncols, c->gram_part.as<double>(), G, 0, c->stream);
-  double *Q = c->Wmat.as<double>();
-  if (jacobi_eigh(G, ncols, c->jac_work.as<double>(), c->evals_d.as<double>(), Q, 1e-14, 40,
-                  c->host_scratch.data(), c->stream, sweeps) != 0)
-    return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
+  gram_launch(X, ld, HX, ldh, nd, ncols, c->gram_part.as<double>(), c->Smat.as<double>(), 0, c->stream);
+  return 0;
+}
+
+// The eigensolve of part 2 as a job of the (batched) Jacobi driver: G in
+// Smat, eigenvectors into Wmat, eigenvalues into evals_d.
+chfsi::JacobiJob chfsi::rr_eigen_job(chfsi_ctx *c, int ncols) {
+  return JacobiJob{c->Smat.as<double>(), ncols, c->jac_work.as<double>(), c->evals_d.as<double>(),
+                   c->Wmat.as<double>()};
+}
+
+// Part 3: X <- X Q, HX <- HX Q, residual norms; evals and resid to the host.
+int chfsi::rr_finish(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
+                     double *resid) {
+  const int64_t nd = c->mesh.n_dof;
+  const double *Q = c->Wmat.as<double>();
   if (rmul_launch(X, ld, nd, ncols, Q, 0, 0, c->rscratch.as<double>(), c->stream) != 0 ||
       rmul_launch(HX, ldh, nd, ncols, Q, 0, 0, c->rscratch.as<double>(), c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
@@ -615,6 +625,16 @@ int chfsi::rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, i
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipGetLastError());
   return 0;
+}
+
+int chfsi::rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
+                   double *resid, int *sweeps) {
+  if (int r = rr_project(c, X, ld, ncols, HX, ldh)) return r;
+  const JacobiJob job = rr_eigen_job(c, ncols);
+  if (jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, 40, c->host_scratch.data(), c->stream, sweeps) !=
+      0)
+    return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
+  return rr_finish(c, X, ld, ncols, HX, ldh, evals, resid);
 }
 
 extern "C" int chfsi_rayleigh_ritz(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *evals, double *resid,

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/chfsi.h"
+#include "kernels.hpp"
 #include "mesh.hpp"
 
 namespace chfsi {
@@ -73,6 +74,11 @@ int ensure_small(chfsi_ctx *c, int n);
 // the solve's CholGS (CholeskyQR2 / shifted Cholesky QR when needed)
 int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes);
 // Rayleigh-Ritz with HX in a caller buffer; evals/resid on the host
+// Rayleigh-Ritz in three parts (a batch shares the middle one across problems)
+int rr_project(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh);
+JacobiJob rr_eigen_job(chfsi_ctx *c, int ncols);
+int rr_finish(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
+              double *resid);
 int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals, double *resid,
             int *sweeps);
 

@@ -110,6 +110,19 @@ void trtri_t_launch(const double *L, const double *dinv, int n, double *Z, doubl
 // A: n x n symmetric (row-major, full), destroyed; work: see jacobi_work_elems.
 // On exit: evals ascending (device, n), Q (n x n row-major, columns = vectors).
 size_t jacobi_work_elems(int n);
+// Many independent eigenproblems at once: every round launch covers all
+// problems still iterating, one host synchronisation per sweep checks them
+// all.  Job k: A (destroyed), work (jacobi_work_elems(n)), evals/Q as above.
+// table: device scratch of jacobi_table_bytes(njobs); norms: device
+// [2 njobs]; host_norms: host [2 njobs].
+struct JacobiJob {
+  double *A;
+  int n;
+  double *work, *evals, *Q;
+};
+size_t jacobi_table_bytes(int njobs);
+int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_sweeps, void *table, double *norms,
+                      double *host_norms, hipStream_t s, int *sweeps_done);
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
                 double *host_scratch, hipStream_t s, int *sweeps_done);
 // Zero the strictly upper triangle, helpers.

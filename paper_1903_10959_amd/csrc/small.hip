@@ -9,7 +9,10 @@
 //    step ii).  Cyclic Jacobi in round-robin (parallel) order: each round
 //    rotates n/2 disjoint (p,q) planes at once; the 2x2 block of every pair
 //    of planes is updated by one thread from the previous round's matrix
-//    (double buffered), so a round is one launch with no atomics.
+//    (double buffered), so a round is one launch with no atomics.  Many
+//    independent eigenproblems share each round's launch (the batched
+//    workload's projected Hamiltonians), with one convergence check per
+//    sweep for all of them.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -278,69 +281,97 @@ __device__ __forceinline__ void jrot(const double *A, int n, int p, int q, doubl
   s = t * c;
 }
 
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const double *__restrict__ A, double *__restrict__ An,
-                                                           const double *__restrict__ V, double *__restrict__ Vn,
-                                                           int n, int np, int r) {
-  const int P = np / 2;
+// One problem of a batched Jacobi round: matrices A (n x n) and V, each
+// double buffered (A[b] / V[b]), the buffer holding the matrix at the start
+// of the sweep (par0), and the range of blocks of the round launch that
+// update it.
+struct JacProb {
+  double *A[2], *V[2];
+  int n, np, par0;
+  int64_t first_block, nblocks;
+};
+
+// Round r of a sweep for every problem in the table.  Each problem does
+// exactly one sweep (rounds 0 .. np-2) per batched sweep and idles in later
+// rounds, so its sequence of operations is the one of a solve on its own.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+  // problem of this block: last entry with first_block <= blockIdx.x
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].first_block <= (int64_t)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const JacProb &J = probs[lo];
+  const int n = J.n, np = J.np, P = np / 2;
+  if (r >= np - 1) return;                       // this problem's sweep is complete
+  const int par = (J.par0 + r) & 1;
+  const double *__restrict__ A = J.A[par];
+  double *__restrict__ An = J.A[par ^ 1];
+  const double *__restrict__ V = J.V[par];
+  double *__restrict__ Vn = J.V[par ^ 1];
   const int64_t nA = (int64_t)P * P;
   const int64_t total = nA + (int64_t)n * P;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    if (t < nA) {
-      const int I = (int)(t / P), J = (int)(t % P);
-      const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
-      const int pJ = rr_index(J, r, np), qJ = rr_index(np - 1 - J, r, np);
-      double cI, sI, tI, cJ, sJ, tJ;
-      jrot(A, n, pI, qI, cI, sI, tI);
-      jrot(A, n, pJ, qJ, cJ, sJ, tJ);
-      if (I == J) {
-        if (pI >= n || qI >= n) {
-          if (pI < n) An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI];
-          if (qI < n) An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI];
-          continue;
-        }
-        const double apq = A[(int64_t)pI * n + qI];
-        An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI] - tI * apq;
-        An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI] + tI * apq;
-        An[(int64_t)pI * n + qI] = 0.0;
-        An[(int64_t)qI * n + pI] = 0.0;
-        continue;
+  const int64_t t = ((int64_t)blockIdx.x - J.first_block) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  if (t < nA) {
+    const int I = (int)(t / P), Jc = (int)(t % P);
+    const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
+    const int pJ = rr_index(Jc, r, np), qJ = rr_index(np - 1 - Jc, r, np);
+    double cI, sI, tI, cJ, sJ, tJ;
+    jrot(A, n, pI, qI, cI, sI, tI);
+    jrot(A, n, pJ, qJ, cJ, sJ, tJ);
+    if (I == Jc) {
+      if (pI >= n || qI >= n) {
+        if (pI < n) An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI];
+        if (qI < n) An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI];
+        return;
       }
-      const bool pIo = pI < n, qIo = qI < n, pJo = pJ < n, qJo = qJ < n;
-      const double b00 = (pIo && pJo) ? A[(int64_t)pI * n + pJ] : 0.0;
-      const double b01 = (pIo && qJo) ? A[(int64_t)pI * n + qJ] : 0.0;
-      const double b10 = (qIo && pJo) ? A[(int64_t)qI * n + pJ] : 0.0;
-      const double b11 = (qIo && qJo) ? A[(int64_t)qI * n + qJ] : 0.0;
-      // rows: R_I^T B
-      const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
-      const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
-      // columns: (R_I^T B) R_J
-      if (pIo && pJo) An[(int64_t)pI * n + pJ] = cJ * r00 - sJ * r01;
-      if (pIo && qJo) An[(int64_t)pI * n + qJ] = sJ * r00 + cJ * r01;
-      if (qIo && pJo) An[(int64_t)qI * n + pJ] = cJ * r10 - sJ * r11;
-      if (qIo && qJo) An[(int64_t)qI * n + qJ] = sJ * r10 + cJ * r11;
-    } else {
-      const int64_t u = t - nA;
-      const int row = (int)(u / P), I = (int)(u % P);
-      const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
-      double c, s, tt;
-      jrot(A, n, pI, qI, c, s, tt);
-      const double vp = pI < n ? V[(int64_t)row * n + pI] : 0.0;
-      const double vq = qI < n ? V[(int64_t)row * n + qI] : 0.0;
-      if (pI < n) Vn[(int64_t)row * n + pI] = c * vp - s * vq;
-      if (qI < n) Vn[(int64_t)row * n + qI] = s * vp + c * vq;
+      const double apq = A[(int64_t)pI * n + qI];
+      An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI] - tI * apq;
+      An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI] + tI * apq;
+      An[(int64_t)pI * n + qI] = 0.0;
+      An[(int64_t)qI * n + pI] = 0.0;
+      return;
     }
+    const bool pIo = pI < n, qIo = qI < n, pJo = pJ < n, qJo = qJ < n;
+    const double b00 = (pIo && pJo) ? A[(int64_t)pI * n + pJ] : 0.0;
+    const double b01 = (pIo && qJo) ? A[(int64_t)pI * n + qJ] : 0.0;
+    const double b10 = (qIo && pJo) ? A[(int64_t)qI * n + pJ] : 0.0;
+    const double b11 = (qIo && qJo) ? A[(int64_t)qI * n + qJ] : 0.0;
+    // rows: R_I^T B
+    const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
+    const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
+    // columns: (R_I^T B) R_J
+    if (pIo && pJo) An[(int64_t)pI * n + pJ] = cJ * r00 - sJ * r01;
+    if (pIo && qJo) An[(int64_t)pI * n + qJ] = sJ * r00 + cJ * r01;
+    if (qIo && pJo) An[(int64_t)qI * n + pJ] = cJ * r10 - sJ * r11;
+    if (qIo && qJo) An[(int64_t)qI * n + qJ] = sJ * r10 + cJ * r11;
+  } else {
+    const int64_t u = t - nA;
+    const int row = (int)(u / P), I = (int)(u % P);
+    const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
+    double c, s, tt;
+    jrot(A, n, pI, qI, c, s, tt);
+    const double vp = pI < n ? V[(int64_t)row * n + pI] : 0.0;
+    const double vq = qI < n ? V[(int64_t)row * n + qI] : 0.0;
+    if (pI < n) Vn[(int64_t)row * n + pI] = c * vp - s * vq;
+    if (qI < n) Vn[(int64_t)row * n + qI] = s * vp + c * vq;
   }
 }
 
-// out[0] = sum of squares off the diagonal, out[1] = on the diagonal
-__global__ __launch_bounds__(1024) void offnorm_kernel(const double *A, int n, double *out) {
+// out[2k] = sum of squares off the diagonal of problem k's current matrix,
+// out[2k+1] = on the diagonal (one work-group per problem)
+__global__ __launch_bounds__(1024) void offnorm_kernel(const JacProb *__restrict__ probs, double *__restrict__ out) {
   __shared__ double so[1024], sd[1024];
+  const JacProb &J = probs[blockIdx.x];
+  const double *A = J.A[J.par0];
+  const int n = J.n;
   double o = 0, d = 0;
   const int64_t total = (int64_t)n * n;
   for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int i = (int)(idx / n), jj = (int)(idx % n);
-    double v = A[idx];
+    const int i = (int)(idx / n), jj = (int)(idx % n);
+    const double v = A[idx];
     if (i == jj) d += v * v;
     else o += v * v;
   }
@@ -355,8 +386,8 @@ __global__ __launch_bounds__(1024) void offnorm_kernel(const double *A, int n, d
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = so[0];
-    out[1] = sd[0];
+    out[2 * blockIdx.x] = so[0];
+    out[2 * blockIdx.x + 1] = sd[0];
   }
 }
 
@@ -382,39 +413,95 @@ __global__ __launch_bounds__(256) void jacobi_sort_kernel(const double *A, const
   for (int row = 0; row < n; ++row) Q[(int64_t)row * n + rank] = V[(int64_t)row * n + i];
 }
 
-size_t jacobi_work_elems(int n) { return (size_t)3 * n * n + 8; }
+size_t jacobi_work_elems(int n) { return (size_t)3 * n * n + 16; }
+size_t jacobi_table_bytes(int njobs) { return (size_t)(njobs > 0 ? njobs : 1) * sizeof(JacProb); }
+
+int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_sweeps, void *table, double *norms,
+                      double *host_norms, hipStream_t s, int *sweeps_done) {
+  if (njobs <= 0) return 0;
+  std::vector<JacProb> all(njobs);
+  std::vector<int> active(njobs, 1);
+  std::vector<double> prev_off(njobs, -1.0);
+  for (int k = 0; k < njobs; ++k) {
+    const JacobiJob &jb = jobs[k];
+    const int n = jb.n;
+    JacProb &J = all[k];
+    J.A[0] = jb.A;
+    J.A[1] = jb.work;
+    J.V[0] = jb.work + (size_t)n * n;
+    J.V[1] = jb.work + (size_t)2 * n * n;
+    J.n = n;
+    J.np = n + (n & 1);
+    J.par0 = 0;
+    J.first_block = J.nblocks = 0;
+    hipLaunchKernelGGL(eye_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, J.V[0], n);
+    if (n <= 1) active[k] = 0;
+  }
+  JacProb *dtab = static_cast<JacProb *>(table);
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    // convergence of every active problem, one host synchronisation
+    std::vector<JacProb> act;
+    std::vector<int> ids;
+    for (int k = 0; k < njobs; ++k)
+      if (active[k]) {
+        act.push_back(all[k]);
+        ids.push_back(k);
+      }
+    if (act.empty()) break;
+    if (hipMemcpyAsync(dtab, act.data(), act.size() * sizeof(JacProb), hipMemcpyHostToDevice, s) != hipSuccess)
+      return -1;
+    hipLaunchKernelGGL(offnorm_kernel, dim3((unsigned)act.size()), dim3(1024), 0, s, dtab, norms);
+    if (hipMemcpyAsync(host_norms, norms, 2 * act.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    std::vector<JacProb> run;
+    int rmax = 0;
+    int64_t blocks = 0;
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int k = ids[a];
+      const double off = host_norms[2 * a], tot = host_norms[2 * a] + host_norms[2 * a + 1];
+      bool done = off <= tol * tol * tot;
+      if (prev_off[k] >= 0 && off >= prev_off[k] && off <= 1e-20 * tot) done = true;  // stagnated at rounding
+      prev_off[k] = off;
+      if (done) {
+        active[k] = 0;
+        continue;
+      }
+      JacProb &J = all[k];
+      const int P = J.np / 2;
+      J.first_block = blocks;
+      J.nblocks = ((int64_t)P * P + (int64_t)J.n * P + 255) / 256;
+      blocks += J.nblocks;
+      rmax = std::max(rmax, J.np - 1);
+      run.push_back(J);
+      J.par0 ^= (J.np - 1) & 1;                   // buffer holding the matrix after this sweep
+    }
+    if (run.empty()) break;
+    if (hipMemcpyAsync(dtab, run.data(), run.size() * sizeof(JacProb), hipMemcpyHostToDevice, s) != hipSuccess)
+      return -1;
+    for (int r = 0; r < rmax; ++r)
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dtab, (int)run.size(), r);
+    // the table is rewritten next sweep: this sweep's launches must have read it
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  }
+  for (int k = 0; k < njobs; ++k) {
+    const JacProb &J = all[k];
+    hipLaunchKernelGGL(jacobi_sort_kernel, dim3((J.n + 255) / 256), dim3(256), 0, s, J.A[J.par0], J.V[J.par0], J.n,
+                       jobs[k].evals, jobs[k].Q);
+  }
+  if (sweeps_done) *sweeps_done = sweep;
+  return 0;
+}
 
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
                 double *host_scratch, hipStream_t s, int *sweeps_done) {
-  const int np = n + (n & 1);
-  double *A1 = work;
-  double *V0 = work + (size_t)n * n;
-  double *V1 = work + (size_t)2 * n * n;
-  double *nrm = work + (size_t)3 * n * n;
-  double *a_cur = A, *a_nxt = A1, *v_cur = V0, *v_nxt = V1;
-  hipLaunchKernelGGL(eye_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, v_cur, n);
-  const int P = np / 2;
-  const int64_t total = (int64_t)P * P + (int64_t)n * P;
-  const unsigned grid = grid_for(total);
-  int sweep = 0;
-  double prev_off = -1;
-  for (; sweep < max_sweeps && n > 1; ++sweep) {
-    hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(1024), 0, s, a_cur, n, nrm);
-    if (hipMemcpyAsync(host_scratch, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-    if (hipStreamSynchronize(s) != hipSuccess) return -1;
-    const double off = host_scratch[0], tot = host_scratch[0] + host_scratch[1];
-    if (off <= tol * tol * tot) break;
-    if (prev_off >= 0 && off >= prev_off && off <= 1e-20 * tot) break;  // stagnated at rounding level
-    prev_off = off;
-    for (int r = 0; r < np - 1; ++r) {
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3(grid), dim3(256), 0, s, a_cur, a_nxt, v_cur, v_nxt, n, np, r);
-      std::swap(a_cur, a_nxt);
-      std::swap(v_cur, v_nxt);
-    }
-  }
-  if (sweeps_done) *sweeps_done = sweep;
-  hipLaunchKernelGGL(jacobi_sort_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a_cur, v_cur, n, evals, Q);
-  return 0;
+  // one problem through the batched driver: the table (one entry) and the two
+  // norms live at the end of the work array
+  static_assert(sizeof(JacProb) <= 8 * sizeof(double), "one table entry fits the work tail");
+  const JacobiJob job{A, n, work, evals, Q};
+  double *tail = work + (size_t)3 * n * n;
+  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + 8, host_scratch, s, sweeps_done);
 }
 
 __global__ void fill_kernel(double *X, int64_t n, double v) {
