@@ -161,8 +161,9 @@ def served_stream(args):
 
     reqs = S.make_stream(args.requests, args.rate, seed=5)
     t0 = time.time()
+    lt = [float(v) for v in args.ladder_tol.split(",")] if args.ladder_tol else None
     S.serve(reqs, hbm_budget=args.hbm_budget, solves=5, tol=args.tol, degree=20, ladder=("fp32", "fp64"),
-            log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+            ladder_tol=lt, log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     wall = time.time() - t0
     st = S.latency_stats(reqs, wall)
@@ -173,7 +174,8 @@ def served_stream(args):
            "config": {"workload": f"served: {args.requests} requests, Poisson rate {args.rate}/s, sizes of the "
                                   f"batched workload, 5 solves each to residual {args.tol} Ha, continuous batching, "
                                   f"HBM budget {args.hbm_budget / 1e9:.0f} GB"},
-           "latency": st, "throughput_dofvecs_per_s": dofvecs / wall, "wall_s": wall}
+           "latency": st, "throughput_dofvecs_per_s": dofvecs / wall, "wall_s": wall,
+           "ladder_tol": lt}
     print(json.dumps(out), flush=True)
 
 
@@ -245,6 +247,8 @@ def main():
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate per second")
     ap.add_argument("--hbm-budget", type=float, default=160e9, help="serve: device bytes for admitted requests")
+    ap.add_argument("--ladder-tol", default="",
+                    help="serve: residual (Ha) ending each precision rung, comma separated (default 4 u b per rung)")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run a plain elementwise copy (y = x * 1) of this many bytes, three times: "
                          "the reference for scaling HBM byte counters")

@@ -74,9 +74,9 @@ class BatchSession:
         self._done = (C.c_int * 4096)()
 
     def add(self, ctx, X, nstates: int, degree: int, tol: float, max_iter: int = 200, ladder=("fp32", "fp64"),
-            mixed_cholgs: bool = False) -> int:
+            mixed_cholgs: bool = False, ladder_tol=None) -> int:
         px, ld, nb = Context._block(X)
-        o = _opts(nstates, nb, degree, tol, max_iter, 0, ladder, None, mixed_cholgs)
+        o = _opts(nstates, nb, degree, tol, max_iter, 0, ladder, ladder_tol, mixed_cholgs)
         ev, rs = np.empty(nb), np.empty(nb)
         pid = self._lib.chfsi_batch_add(self._h, ctx._h, C.byref(o), px, ld, ev.ctypes.data_as(C.c_void_p),
                                        rs.ctypes.data_as(C.c_void_p))

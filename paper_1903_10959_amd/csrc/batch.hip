@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -134,6 +135,7 @@ struct chfsi_batch {
   // shared Jacobi eigensolve of the projected Hamiltonians
   chfsi::DevBuf jac_table, jac_norms;
   std::vector<double> jac_host;
+  double build_ms = 0;           // host time spent (re)building sweep graphs in the current pass
 };
 
 namespace {
@@ -242,8 +244,11 @@ template <typename T>
 int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *ms_out) {
   *ms_out = 0;
   if (ids.empty()) return 0;
-  if (ids != S.members)
+  if (ids != S.members) {
+    const auto t0 = std::chrono::steady_clock::now();
     if (int r = build_sweep<T>(B, S, ids)) return r;
+    B->build_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
   const int m_deg = B->degree;
   S.hcoef.assign((size_t)3 * m_deg * ids.size(), T(0));
   for (size_t m = 0; m < ids.size(); ++m) {
@@ -432,6 +437,8 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   for (Prob &p : b->probs)
     if (!p.done) (rung_prec(p) == CHFSI_FP32 ? g32 : g64).push_back(p.id);
   float ms32 = 0, ms64 = 0;
+  b->build_ms = 0;
+  const auto t_sw = std::chrono::steady_clock::now();
   if (int r = run_sweep<float>(b, b->s32, g32, &ms32)) return r;
   if (int r = run_sweep<double>(b, b->s64, g64, &ms64)) return r;
   // 3. CholGS + RR of every swept problem
@@ -443,7 +450,9 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
     p.rep.t_filter += (f32 ? ms32 : ms64) * 1e-3;
     p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock * b->degree;
   }
+  const auto t_ss = std::chrono::steady_clock::now();
   if (int st = subspace_steps(b, swept, true)) return st;
+  const auto t_end = std::chrono::steady_clock::now();
   int remaining = 0;
   for (int id : swept) {
     Prob &p = b->probs[id];
@@ -453,8 +462,12 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   if (b->verbose) {
     double worst = 0;
     for (int id : swept) worst = std::max(worst, b->probs[id].res);
-    std::fprintf(stderr, "[chfsi] batch pass: %zu FP32 + %zu FP64 problems swept (%.2f + %.2f ms), %d remain, max residual %.3e\n",
-                 g32.size(), g64.size(), ms32, ms64, remaining, worst);
+    std::fprintf(stderr,
+                 "[chfsi] batch pass: %zu FP32 + %zu FP64 problems swept (%.2f + %.2f ms on the device, %.2f ms wall "
+                 "incl. %.2f ms graph builds), CholGS/RR %.2f ms, %d remain, max residual %.3e\n",
+                 g32.size(), g64.size(), ms32, ms64,
+                 std::chrono::duration<double, std::milli>(t_ss - t_sw).count(), b->build_ms,
+                 std::chrono::duration<double, std::milli>(t_end - t_ss).count(), remaining, worst);
     std::fflush(stderr);
   }
   int nd = 0;

@@ -118,7 +118,7 @@ class _ContextPool:
 
 def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-6, degree: int = 20,
           ladder=("fp32", "fp64"), stream_seed: int = 5, device: int = 0, log=None, realtime: bool = True,
-          max_active: int = 256):
+          max_active: int = 256, ladder_tol=None):
     """Run the stream; returns the requests with timings filled in.
     realtime=False makes every request available at t = 0 (offline replay)."""
     import torch
@@ -145,7 +145,7 @@ def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-
         req, ctx, X, V0 = entry[0], entry[1], entry[2], entry[3]
         V = V0 if s == 0 else workload.perturbed(V0, (stream_seed, req.rid, s))
         ctx.set_potential(V)
-        pid = sess.add(ctx, X, req.problem.nstates, degree, tol, max_iter=400, ladder=ladder)
+        pid = sess.add(ctx, X, req.problem.nstates, degree, tol, max_iter=400, ladder=ladder, ladder_tol=ladder_tol)
         entry[4], entry[5] = s, time.time()
         running[pid] = entry
 
