@@ -196,8 +196,9 @@ def time_to_solution(args, prob, bw):
     V = workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords())
     ctx.set_potential(V)
     runs = {}
+    ladder = tuple(args.ladder.split(","))
     variants = [("fp64", dict(ladder=("fp64",), mixed_cholgs=False)),
-                ("mixed", dict(ladder=("bf16", "fp32", "fp64"), mixed_cholgs=True))]
+                ("mixed", dict(ladder=ladder, mixed_cholgs=True))]
     for name, kw in variants:
         X = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=dev)
         torch.cuda.synchronize()
@@ -220,7 +221,7 @@ def time_to_solution(args, prob, bw):
         "value": runs["fp64"]["seconds"] / runs["mixed"]["seconds"],
         "unit": "speedup (FP64 time / mixed time)",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "data": "synthetic",
-        "dtype": "f64 vs fp32-filter/mixed-CholGS",
+        "dtype": "f64 vs " + "->".join(ladder) + " filter ladder/mixed-CholGS",
         "config": {"workload": workload.fmt_problem(prob), "tol_Ha": args.tol, "filter_block": bw},
         "fp64": runs["fp64"], "mixed": runs["mixed"],
         "max_abs_eval_diff_mixed_vs_fp64": float(np.max(np.abs(e64 - emx))),
@@ -247,6 +248,7 @@ def main():
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate per second")
     ap.add_argument("--hbm-budget", type=float, default=160e9, help="serve: device bytes for admitted requests")
+    ap.add_argument("--ladder", default="bf16,fp32,fp64", help="tts: filter precisions of the mixed path's ladder")
     ap.add_argument("--ladder-tol", default="",
                     help="serve: residual (Ha) ending each precision rung, comma separated (default 4 u b per rung)")
     ap.add_argument("--calib-bytes", type=int, default=0,

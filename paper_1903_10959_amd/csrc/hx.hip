@@ -304,12 +304,8 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 // read.  SPLIT: X = hi + lo and K = hi + lo in BF16, three products
 // hi*hi + hi*lo + lo*hi accumulated in FP32.  NPB: n_loc rounded up to 32.
 // ---------------------------------------------------------------------------
-// Epilogue depth (fragments in flight) of the BF16 kernel.
-#ifndef CHFSI_BF16_EPD
-#define CHFSI_BF16_EPD 2
-#endif
-
-template <int NPB, bool SPLIT, int EPD = CHFSI_BF16_EPD>
+// EPD: epilogue fragments in flight (3 measured no faster than 2).
+template <int NPB, bool SPLIT, int EPD = 2>
 __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
                                                             const float *__restrict__ Xp, int64_t ldp,
                                                             float *__restrict__ Y, int64_t ldy,
@@ -346,10 +342,7 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   // stage: 4 consecutive columns per thread per row (16-byte global loads when
   // aligned), SU rows per thread per round with every load issued first
   const bool vec_ok = ((ldx & 3) == 0) && ((col0 & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
-#ifndef CHFSI_BF16_SU
-#define CHFSI_BF16_SU 8
-#endif
-  constexpr int SU = CHFSI_BF16_SU;
+  constexpr int SU = 8;   // (all 22 rows at once measured no faster)
   for (int base = threadIdx.x; base < NPB * 16; base += SU * 256) {
     float v[SU][4];
 #pragma unroll
@@ -503,10 +496,7 @@ struct TileCfg {
   static constexpr int WR = NP == 16 ? 1 : ((NP == 512 && !w8) ? 4 : 2);
   static constexpr int CBW = (NP == 16 || w8) ? 1 : 2;
   static constexpr int KC = 8;
-#ifndef CHFSI_CELL_EPD
-#define CHFSI_CELL_EPD 2
-#endif
-  static constexpr int EPD = sizeof(T) == 4 ? CHFSI_CELL_EPD : 2;
+  static constexpr int EPD = 2;   // epilogue fragments in flight (3 measured no faster)
   typedef LdsTile<T, NP, NW, WR, CBW, KC> L;
   // eight-wave tiles must keep four waves per SIMD (two work-groups per CU)
   static constexpr int WAVES = NW == 8 ? 4 : 1;
