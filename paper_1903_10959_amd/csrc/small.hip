@@ -6,13 +6,13 @@
 //  * trtri_t: W = L^-T (Alg. 3 step 3; the paper uses pXtrtri), block row by
 //    block row from the diagonal-block inverses.
 //  * jacobi: symmetric eigensolver for the projected Hamiltonian (Sec. 3.5
-//    step ii).  Cyclic Jacobi in round-robin (parallel) order: each round
-//    rotates n/2 disjoint (p,q) planes at once; the 2x2 block of every pair
-//    of planes is updated by one thread from the previous round's matrix
-//    (double buffered), so a round is one launch with no atomics.  Many
-//    independent eigenproblems share each round's launch (the batched
-//    workload's projected Hamiltonians), with one convergence check per
-//    sweep for all of them.
+//    step ii).  Block-cyclic Jacobi: blocks of 32 indices paired in
+//    round-robin (parallel) order; each pair's 64 x 64 submatrix gets a sweep
+//    of plane rotations in LDS, and the accumulated 64 x 64 rotations are
+//    applied to the whole matrix and to the eigenvectors as small dense
+//    products.  Many independent eigenproblems share each launch (the
+//    batched workload's projected Hamiltonians), with one convergence check
+//    per sweep for all of them.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -281,83 +281,209 @@ __device__ __forceinline__ void jrot(const double *A, int n, int p, int q, doubl
   s = t * c;
 }
 
-// One problem of a batched Jacobi round: matrices A (n x n) and V, each
-// double buffered (A[b] / V[b]), the buffer holding the matrix at the start
-// of the sweep (par0), and the range of blocks of the round launch that
-// update it.
+// Block-cyclic Jacobi.  The indices are grouped in blocks of JB = 32; a
+// block round pairs the blocks in round-robin order (as the scalar method
+// pairs indices), and for every pair (I, J) of blocks
+//   1. one work-group takes the 64 x 64 submatrix S = A[I u J, I u J] into
+//      LDS and runs one cyclic sweep of plane rotations over its 64 indices,
+//      accumulating them in R (64 x 64, orthogonal);
+//   2. A <- R^T A R tile by tile (every pair of pairs: one 64 x 64 triple
+//      product), into the other buffer;
+//   3. V <- V R in place, panel by panel.
+// A block sweep (nbp - 1 block rounds) applies every plane rotation of a
+// scalar sweep, and more, in 3 (nbp - 1) launches instead of n - 1.
+static constexpr int JB = 32, J2 = 64;
+
+// One problem of a batched block-Jacobi round: A (n x n) double buffered
+// (A[b]), V updated in place, R the current round's pair rotations
+// (npairs x 64 x 64), the buffer holding A at the start of the sweep (par0),
+// and the first work-group of this problem in each of the three launches.
 struct JacProb {
-  double *A[2], *V[2];
-  int n, np, par0;
-  int64_t first_block, nblocks;
+  double *A[2], *V, *R;
+  int n, nbp, par0;
+  int64_t first_inner, first_tile, first_panel;
 };
 
-// Round r of a sweep for every problem in the table.  Each problem does
-// exactly one sweep (rounds 0 .. np-2) per batched sweep and idles in later
-// rounds, so its sequence of operations is the one of a solve on its own.
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
-  // problem of this block: last entry with first_block <= blockIdx.x
+__device__ __forceinline__ int jac_find(const JacProb *__restrict__ probs, int nprob, int which) {
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (probs[mid].first_block <= (int64_t)blockIdx.x) lo = mid;
+    const int64_t f = which == 0 ? probs[mid].first_inner : which == 1 ? probs[mid].first_tile : probs[mid].first_panel;
+    if (f <= (int64_t)blockIdx.x) lo = mid;
     else hi = mid - 1;
   }
-  const JacProb &J = probs[lo];
-  const int n = J.n, np = J.np, P = np / 2;
-  if (r >= np - 1) return;                       // this problem's sweep is complete
-  const int par = (J.par0 + r) & 1;
-  const double *__restrict__ A = J.A[par];
-  double *__restrict__ An = J.A[par ^ 1];
-  const double *__restrict__ V = J.V[par];
-  double *__restrict__ Vn = J.V[par ^ 1];
-  const int64_t nA = (int64_t)P * P;
-  const int64_t total = nA + (int64_t)n * P;
-  const int64_t t = ((int64_t)blockIdx.x - J.first_block) * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  if (t < nA) {
-    const int I = (int)(t / P), Jc = (int)(t % P);
-    const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
-    const int pJ = rr_index(Jc, r, np), qJ = rr_index(np - 1 - Jc, r, np);
-    double cI, sI, tI, cJ, sJ, tJ;
-    jrot(A, n, pI, qI, cI, sI, tI);
-    jrot(A, n, pJ, qJ, cJ, sJ, tJ);
-    if (I == Jc) {
-      if (pI >= n || qI >= n) {
-        if (pI < n) An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI];
-        if (qI < n) An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI];
-        return;
-      }
-      const double apq = A[(int64_t)pI * n + qI];
-      An[(int64_t)pI * n + pI] = A[(int64_t)pI * n + pI] - tI * apq;
-      An[(int64_t)qI * n + qI] = A[(int64_t)qI * n + qI] + tI * apq;
-      An[(int64_t)pI * n + qI] = 0.0;
-      An[(int64_t)qI * n + pI] = 0.0;
-      return;
-    }
-    const bool pIo = pI < n, qIo = qI < n, pJo = pJ < n, qJo = qJ < n;
-    const double b00 = (pIo && pJo) ? A[(int64_t)pI * n + pJ] : 0.0;
-    const double b01 = (pIo && qJo) ? A[(int64_t)pI * n + qJ] : 0.0;
-    const double b10 = (qIo && pJo) ? A[(int64_t)qI * n + pJ] : 0.0;
-    const double b11 = (qIo && qJo) ? A[(int64_t)qI * n + qJ] : 0.0;
-    // rows: R_I^T B
-    const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
-    const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
-    // columns: (R_I^T B) R_J
-    if (pIo && pJo) An[(int64_t)pI * n + pJ] = cJ * r00 - sJ * r01;
-    if (pIo && qJo) An[(int64_t)pI * n + qJ] = sJ * r00 + cJ * r01;
-    if (qIo && pJo) An[(int64_t)qI * n + pJ] = cJ * r10 - sJ * r11;
-    if (qIo && qJo) An[(int64_t)qI * n + qJ] = sJ * r10 + cJ * r11;
-  } else {
-    const int64_t u = t - nA;
-    const int row = (int)(u / P), I = (int)(u % P);
-    const int pI = rr_index(I, r, np), qI = rr_index(np - 1 - I, r, np);
-    double c, s, tt;
-    jrot(A, n, pI, qI, c, s, tt);
-    const double vp = pI < n ? V[(int64_t)row * n + pI] : 0.0;
-    const double vq = qI < n ? V[(int64_t)row * n + qI] : 0.0;
-    if (pI < n) Vn[(int64_t)row * n + pI] = c * vp - s * vq;
-    if (qI < n) Vn[(int64_t)row * n + qI] = s * vp + c * vq;
+  return lo;
+}
+
+// global index of local index i (0..63) of block pair (I, J); >= n: padding
+__device__ __forceinline__ int jac_gidx(int i, int I, int J) { return i < JB ? I * JB + i : J * JB + (i - JB); }
+
+// 1. one sweep of the 64-index pair submatrix in LDS; R out
+__global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+  __shared__ double S[J2][J2 + 1];
+  __shared__ double Rs[J2][J2 + 1];
+  __shared__ double cs[J2 / 2], sn[J2 / 2], tn[J2 / 2];
+  const JacProb &P = probs[jac_find(probs, nprob, 0)];
+  if (r >= P.nbp - 1) return;                      // this problem's sweep is complete
+  const int k = (int)(blockIdx.x - P.first_inner);
+  const int n = P.n;
+  const int I = rr_index(k, r, P.nbp), J = rr_index(P.nbp - 1 - k, r, P.nbp);
+  const double *A = P.A[(P.par0 + r) & 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < J2 * J2; e += 1024) {
+    const int i = e / J2, j = e % J2;
+    const int gi = jac_gidx(i, I, J), gj = jac_gidx(j, I, J);
+    S[i][j] = (gi < n && gj < n) ? A[(int64_t)gi * n + gj] : 0.0;
+    Rs[i][j] = i == j ? 1.0 : 0.0;
   }
+  __syncthreads();
+  for (int ir = 0; ir < J2 - 1; ++ir) {
+    if (t < J2 / 2) {
+      const int p = rr_index(t, ir, J2), q = rr_index(J2 - 1 - t, ir, J2);
+      double c = 1.0, s = 0.0, tt = 0.0;
+      const double apq = S[p][q];
+      if (fabs(apq) >= 1e-300) {
+        const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
+        tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + tt * tt);
+        s = tt * c;
+      }
+      cs[t] = c;
+      sn[t] = s;
+      tn[t] = tt;
+    }
+    __syncthreads();
+    {
+      // 2x2 block (pair a rows, pair b columns), one per thread, in place
+      const int a = t / (J2 / 2), b = t % (J2 / 2);
+      const int pa = rr_index(a, ir, J2), qa = rr_index(J2 - 1 - a, ir, J2);
+      const int pb = rr_index(b, ir, J2), qb = rr_index(J2 - 1 - b, ir, J2);
+      if (a == b) {
+        const double apq = S[pa][qa];
+        S[pa][pa] -= tn[a] * apq;
+        S[qa][qa] += tn[a] * apq;
+        S[pa][qa] = 0.0;
+        S[qa][pa] = 0.0;
+      } else {
+        const double ca = cs[a], sa = sn[a], cb = cs[b], sb = sn[b];
+        const double b00 = S[pa][pb], b01 = S[pa][qb], b10 = S[qa][pb], b11 = S[qa][qb];
+        const double r00 = ca * b00 - sa * b10, r01 = ca * b01 - sa * b11;
+        const double r10 = sa * b00 + ca * b10, r11 = sa * b01 + ca * b11;
+        S[pa][pb] = cb * r00 - sb * r01;
+        S[pa][qb] = sb * r00 + cb * r01;
+        S[qa][pb] = cb * r10 - sb * r11;
+        S[qa][qb] = sb * r10 + cb * r11;
+      }
+      // R <- R J: rows 2 per thread, pair b
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = 2 * a + h;
+        const double rp = Rs[row][pb], rq = Rs[row][qb];
+        Rs[row][pb] = cs[b] * rp - sn[b] * rq;
+        Rs[row][qb] = sn[b] * rp + cs[b] * rq;
+      }
+    }
+    __syncthreads();
+  }
+  double *Rg = P.R + (int64_t)k * J2 * J2;
+  for (int e = t; e < J2 * J2; e += 1024) Rg[e] = Rs[e / J2][e % J2];
+}
+
+// C = op(X) Y for 64 x 64 LDS operands, 16 outputs (4 x 4) per thread of 256;
+// TRANS: X used transposed
+template <bool TRANS>
+__device__ __forceinline__ void jac_mm64(const double (*X)[J2 + 1], const double (*Y)[J2 + 1], double (&c)[4][4],
+                                         int i0, int j0) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[u][v] = 0.0;
+#pragma unroll 4
+  for (int kk = 0; kk < J2; ++kk) {
+    double x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = TRANS ? X[kk][i0 + 16 * u] : X[i0 + 16 * u][kk];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[v] = Y[kk][j0 + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[u][v] += x[u] * y[v];
+  }
+}
+
+// 2. A_next[P1 rows, P2 cols] = R_P1^T A[P1, P2] R_P2 for every pair of pairs
+__global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+  __shared__ double T[J2][J2 + 1], R1[J2][J2 + 1], R2[J2][J2 + 1];
+  const JacProb &P = probs[jac_find(probs, nprob, 1)];
+  if (r >= P.nbp - 1) return;
+  const int np2 = P.nbp / 2;
+  const int tile = (int)(blockIdx.x - P.first_tile);
+  const int k1 = tile / np2, k2 = tile % np2;
+  const int n = P.n;
+  const int I1 = rr_index(k1, r, P.nbp), J1 = rr_index(P.nbp - 1 - k1, r, P.nbp);
+  const int I2 = rr_index(k2, r, P.nbp), J2b = rr_index(P.nbp - 1 - k2, r, P.nbp);
+  const double *A = P.A[(P.par0 + r) & 1];
+  double *An = P.A[(P.par0 + r + 1) & 1];
+  const double *Rg1 = P.R + (int64_t)k1 * J2 * J2, *Rg2 = P.R + (int64_t)k2 * J2 * J2;
+  const int t = threadIdx.x;
+  for (int e = t; e < J2 * J2; e += 256) {
+    const int i = e / J2, j = e % J2;
+    const int gi = jac_gidx(i, I1, J1), gj = jac_gidx(j, I2, J2b);
+    T[i][j] = (gi < n && gj < n) ? A[(int64_t)gi * n + gj] : 0.0;
+    R1[i][j] = Rg1[e];
+    R2[i][j] = Rg2[e];
+  }
+  __syncthreads();
+  const int i0 = t / 16, j0 = t % 16;
+  double c[4][4];
+  jac_mm64<false>(T, R2, c, i0, j0);               // U = T R2
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[i0 + 16 * u][j0 + 16 * v] = c[u][v];
+  __syncthreads();
+  jac_mm64<true>(R1, T, c, i0, j0);                // R1^T U
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = jac_gidx(i0 + 16 * u, I1, J1), gj = jac_gidx(j0 + 16 * v, I2, J2b);
+      if (gi < n && gj < n) An[(int64_t)gi * n + gj] = c[u][v];
+    }
+}
+
+// 3. V[panel rows, P cols] <- V[panel rows, P cols] R_P, in place
+__global__ __launch_bounds__(256) void jacobi_apply_v_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+  __shared__ double T[J2][J2 + 1], Rl[J2][J2 + 1];
+  const JacProb &P = probs[jac_find(probs, nprob, 2)];
+  if (r >= P.nbp - 1) return;
+  const int np2 = P.nbp / 2;
+  const int w = (int)(blockIdx.x - P.first_panel);
+  const int panel = w / np2, k = w % np2;
+  const int n = P.n;
+  const int I = rr_index(k, r, P.nbp), J = rr_index(P.nbp - 1 - k, r, P.nbp);
+  const double *Rg = P.R + (int64_t)k * J2 * J2;
+  const int t = threadIdx.x;
+  const int row0 = panel * J2;
+  for (int e = t; e < J2 * J2; e += 256) {
+    const int i = e / J2, j = e % J2;
+    const int gr = row0 + i, gj = jac_gidx(j, I, J);
+    T[i][j] = (gr < n && gj < n) ? P.V[(int64_t)gr * n + gj] : 0.0;
+    Rl[i][j] = Rg[e];
+  }
+  __syncthreads();
+  const int i0 = t / 16, j0 = t % 16;
+  double c[4][4];
+  jac_mm64<false>(T, Rl, c, i0, j0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gr = row0 + i0 + 16 * u, gj = jac_gidx(j0 + 16 * v, I, J);
+      if (gr < n && gj < n) P.V[(int64_t)gr * n + gj] = c[u][v];
+    }
 }
 
 // out[2k] = sum of squares off the diagonal of problem k's current matrix,
@@ -413,7 +539,17 @@ __global__ __launch_bounds__(256) void jacobi_sort_kernel(const double *A, const
   for (int row = 0; row < n; ++row) Q[(int64_t)row * n + rank] = V[(int64_t)row * n + i];
 }
 
-size_t jacobi_work_elems(int n) { return (size_t)3 * n * n + 16; }
+static int jac_nbp(int n) {
+  const int nblk = (n + JB - 1) / JB;
+  return nblk + (nblk & 1);
+}
+
+// work: A's second buffer (n^2), V (n^2), the pair rotations
+// (nbp/2 x 64 x 64), a tail of 16 for the single-problem table and norms
+static constexpr int JTAIL = 16;
+size_t jacobi_work_elems(int n) {
+  return (size_t)2 * n * n + (size_t)(jac_nbp(n) / 2) * J2 * J2 + JTAIL;
+}
 size_t jacobi_table_bytes(int njobs) { return (size_t)(njobs > 0 ? njobs : 1) * sizeof(JacProb); }
 
 int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_sweeps, void *table, double *norms,
@@ -428,13 +564,13 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
     JacProb &J = all[k];
     J.A[0] = jb.A;
     J.A[1] = jb.work;
-    J.V[0] = jb.work + (size_t)n * n;
-    J.V[1] = jb.work + (size_t)2 * n * n;
+    J.V = jb.work + (size_t)n * n;
+    J.R = jb.work + (size_t)2 * n * n;
     J.n = n;
-    J.np = n + (n & 1);
+    J.nbp = jac_nbp(n);
     J.par0 = 0;
-    J.first_block = J.nblocks = 0;
-    hipLaunchKernelGGL(eye_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, J.V[0], n);
+    J.first_inner = J.first_tile = J.first_panel = 0;
+    hipLaunchKernelGGL(eye_kernel, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, J.V, n);
     if (n <= 1) active[k] = 0;
   }
   JacProb *dtab = static_cast<JacProb *>(table);
@@ -457,7 +593,7 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
     if (hipStreamSynchronize(s) != hipSuccess) return -1;
     std::vector<JacProb> run;
     int rmax = 0;
-    int64_t blocks = 0;
+    int64_t n_inner = 0, n_tile = 0, n_panel = 0;
     for (size_t a = 0; a < act.size(); ++a) {
       const int k = ids[a];
       const double off = host_norms[2 * a], tot = host_norms[2 * a] + host_norms[2 * a + 1];
@@ -469,25 +605,32 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
         continue;
       }
       JacProb &J = all[k];
-      const int P = J.np / 2;
-      J.first_block = blocks;
-      J.nblocks = ((int64_t)P * P + (int64_t)J.n * P + 255) / 256;
-      blocks += J.nblocks;
-      rmax = std::max(rmax, J.np - 1);
+      const int np2 = J.nbp / 2;
+      J.first_inner = n_inner;
+      J.first_tile = n_tile;
+      J.first_panel = n_panel;
+      n_inner += np2;
+      n_tile += (int64_t)np2 * np2;
+      n_panel += (int64_t)((J.n + J2 - 1) / J2) * np2;
+      rmax = std::max(rmax, J.nbp - 1);
       run.push_back(J);
-      J.par0 ^= (J.np - 1) & 1;                   // buffer holding the matrix after this sweep
+      J.par0 ^= (J.nbp - 1) & 1;                  // buffer holding A after this sweep
     }
     if (run.empty()) break;
     if (hipMemcpyAsync(dtab, run.data(), run.size() * sizeof(JacProb), hipMemcpyHostToDevice, s) != hipSuccess)
       return -1;
-    for (int r = 0; r < rmax; ++r)
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dtab, (int)run.size(), r);
+    const int nr = (int)run.size();
+    for (int r = 0; r < rmax; ++r) {
+      hipLaunchKernelGGL(jacobi_inner_kernel, dim3((unsigned)n_inner), dim3(1024), 0, s, dtab, nr, r);
+      hipLaunchKernelGGL(jacobi_apply_a_kernel, dim3((unsigned)n_tile), dim3(256), 0, s, dtab, nr, r);
+      hipLaunchKernelGGL(jacobi_apply_v_kernel, dim3((unsigned)n_panel), dim3(256), 0, s, dtab, nr, r);
+    }
     // the table is rewritten next sweep: this sweep's launches must have read it
     if (hipStreamSynchronize(s) != hipSuccess) return -1;
   }
   for (int k = 0; k < njobs; ++k) {
     const JacProb &J = all[k];
-    hipLaunchKernelGGL(jacobi_sort_kernel, dim3((J.n + 255) / 256), dim3(256), 0, s, J.A[J.par0], J.V[J.par0], J.n,
+    hipLaunchKernelGGL(jacobi_sort_kernel, dim3((J.n + 255) / 256), dim3(256), 0, s, J.A[J.par0], J.V, J.n,
                        jobs[k].evals, jobs[k].Q);
   }
   if (sweeps_done) *sweeps_done = sweep;
@@ -497,11 +640,11 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
                 double *host_scratch, hipStream_t s, int *sweeps_done) {
   // one problem through the batched driver: the table (one entry) and the two
-  // norms live at the end of the work array
-  static_assert(sizeof(JacProb) <= 8 * sizeof(double), "one table entry fits the work tail");
+  // norms live in the tail of the work array
+  static_assert(sizeof(JacProb) <= (JTAIL - 2) * sizeof(double), "one table entry fits the work tail");
   const JacobiJob job{A, n, work, evals, Q};
-  double *tail = work + (size_t)3 * n * n;
-  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + 8, host_scratch, s, sweeps_done);
+  double *tail = work + jacobi_work_elems(n) - JTAIL;
+  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + (JTAIL - 2), host_scratch, s, sweeps_done);
 }
 
 __global__ void fill_kernel(double *X, int64_t n, double v) {
