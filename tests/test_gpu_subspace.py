@@ -74,7 +74,7 @@ def test_rayleigh_ritz_exact_on_rotated_eigenvectors():
     c.close()
 
 
-@pytest.mark.parametrize("ncols", [24, 97, 200])
+@pytest.mark.parametrize("ncols", [1, 2, 3, 24, 31, 32, 33, 63, 64, 65, 97, 129, 200])
 def test_rayleigh_ritz_matches_oracle(ncols):
     prob = workload.PROBLEMS["small"]
     c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
