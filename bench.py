@@ -230,6 +230,53 @@ def time_to_solution(args, prob, bw):
     ctx.close()
 
 
+def rr_split_compare(args, prob):
+    """Rayleigh-Ritz cost: the full procedure (all pairs, full rotation) against
+    spectrum splitting with the mixed-precision projection (Alg. 4:
+    N_fr = 15 % of N largest pairs, partial rotation), on the same block."""
+    import numpy as np
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
+    ctx.set_potential(workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords()))
+    X0 = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=dev)
+    ctx.orthonormalize(X0)
+    ctx.rayleigh_ritz(X0)          # a Ritz basis, as at the end of a ChFSI pass
+    n_fr = max(1, int(round(0.15 * prob.nstates)))
+    nb = prob.nblock
+    times = {"full": [], "split_mixed": [], "split_fp64": []}
+    out = {}
+    for rep in range(args.steps + 1):
+        for name in times:
+            X = X0.clone()
+            torch.cuda.synchronize()
+            t0 = time.time()
+            if name == "full":
+                ev, rs = ctx.rayleigh_ritz(X)
+                out[name] = ev[nb - n_fr:]
+            else:
+                ev, rs = ctx.rayleigh_ritz_split(X, n_fr, mixed=(name == "split_mixed"))
+                out[name] = ev
+            torch.cuda.synchronize()
+            if rep > 0:
+                times[name].append(time.time() - t0)
+            del X
+    ms = {k: 1e3 * float(np.median(v)) for k, v in times.items()}
+    res = {"metric": "Rayleigh-Ritz wall time: full vs spectrum splitting with mixed-precision projection",
+           "value": ms["full"] / ms["split_mixed"], "unit": "speedup (full / split-mixed)", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "data": "synthetic", "dtype": "f64 / f32-outside-fr-fr",
+           "config": {"workload": workload.fmt_problem(prob), "n_fr": n_fr, "N_b": nb},
+           "ms": ms, "steps": args.steps,
+           "max_abs_fr_eval_diff_mixed_vs_full": float(np.max(np.abs(out["split_mixed"] - out["full"]))),
+           "max_abs_fr_eval_diff_fp64_split_vs_full": float(np.max(np.abs(out["split_fp64"] - out["full"])))}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,8 +288,9 @@ def main():
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=16)
-    ap.add_argument("--mode", default="step", choices=["step", "tts"],
-                    help="step: throughput of whole ChFSI iterations (default); tts: time to solution")
+    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr"],
+                    help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
+                         "rr: Rayleigh-Ritz full vs spectrum splitting")
     ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
@@ -286,6 +334,8 @@ def main():
           file=sys.stderr, flush=True)
     if args.mode == "tts":
         return time_to_solution(args, prob, bw)
+    if args.mode == "rr":
+        return rr_split_compare(args, prob)
     ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
     V = workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords())
     ctx.set_potential(V)

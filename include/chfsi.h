@@ -132,6 +132,22 @@ int chfsi_orthonormalize(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int m
 int chfsi_rayleigh_ritz(chfsi_ctx *ctx, double *X, int64_t ld, int ncols,
                         double *evals, double *resid, double *HX_out);
 
+/* ---- rayleighRitz with spectrum splitting (Sec. 3.5, Alg. 4, and the
+ * mixed-precision projected Hamiltonian of Sec. 3.5, eq.
+ * partialDiagMixedPrec1) ---------------------------------------------------
+ * For orthonormal X [n_dof x ld] with ncols = N_oc + N_fr columns:
+ * HX = Htilde X; Hhat = X^T HX (lower triangle).  mixed = 1: the fr-fr block
+ * (rows and columns >= N_oc, its start rounded down to a multiple of 64) in
+ * FP64, every other block with FP32 inputs and products; mixed = 0: all FP64.
+ * Hhat Q = Q D (FP64 Jacobi; all pairs are computed, the N_fr largest used);
+ * X[:, N_oc:] <- X Q_fr, the partial rotation; the first N_oc columns are left
+ * as they are (the paper keeps the fully occupied part unrotated).
+ * evals_fr, resid_fr: host [n_fr], ascending Ritz values of the N_fr largest
+ * pairs and ||Htilde x_i - d_i x_i||_2 of the rotated columns.  Errors:
+ * CHFSI_ERR_ARG for n_fr outside 1..ncols or null host arrays. */
+int chfsi_rayleigh_ritz_split(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int n_fr, int mixed,
+                              double *evals_fr, double *resid_fr);
+
 /* ---- solve (Alg. 2 step 7 with the adaptive repeat of Sec. 3.3) ----------
  * X: device [n_dof x ld], ld >= nblock, holds the start (or warm-start) block
  * on entry and the Ritz vectors (tilde space, orthonormal) on exit.

@@ -319,6 +319,17 @@ class Context:
                                                   rs.ctypes.data_as(C.c_void_p), ph), "rayleigh_ritz")
         return ev, rs
 
+    def rayleigh_ritz_split(self, X, n_fr: int, mixed: bool = True):
+        """Spectrum-splitting Rayleigh-Ritz: Ritz values and residuals of the n_fr
+        largest pairs; rotates only the trailing n_fr columns of X."""
+        px, ld, n = self._block(X)
+        ev = np.empty(int(n_fr))
+        rs = np.empty(int(n_fr))
+        self._check(self._lib.chfsi_rayleigh_ritz_split(self._h, px, ld, n, int(n_fr), 1 if mixed else 0,
+                                                        ev.ctypes.data_as(C.c_void_p), rs.ctypes.data_as(C.c_void_p)),
+                    "rayleigh_ritz_split")
+        return ev, rs
+
     # ---- solve -----------------------------------------------------------
     def solve(self, X, nstates: int, degree: int, tol: float, max_iter: int = 200, block_width: int = 0,
               ladder=("fp64",), ladder_tol=None, mixed_cholgs: bool = False):

@@ -654,6 +654,48 @@ extern "C" int chfsi_rayleigh_ritz(chfsi_ctx *c, double *X, int64_t ld, int ncol
 }
 
 // ---------------------------------------------------------------------------
+// rayleighRitz with spectrum splitting (Alg. 4) and the mixed-precision
+// projected Hamiltonian
+// ---------------------------------------------------------------------------
+extern "C" int chfsi_rayleigh_ritz_split(chfsi_ctx *c, double *X, int64_t ld, int ncols, int n_fr, int mixed,
+                                         double *evals_fr, double *resid_fr) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (n_fr < 1 || n_fr > ncols) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: n_fr must be in 1..ncols");
+  if (!evals_fr || !resid_fr) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: evals/resid must be host arrays");
+  if (int r = ensure_small(c, ncols)) return r;
+  const int64_t nd = c->mesh.n_dof;
+  HIPCHK(c, c->HX.ensure((size_t)nd * ncols * sizeof(double)));
+  double *HX = c->HX.as<double>();
+  const int64_t ldh = ncols;
+  const int n_oc = ncols - n_fr;
+  // step 1: Hhat = X^T Htilde X; mixed: the fr-fr block in FP64, the rest FP32
+  if (int r = cheb_step_t<double>(c, X, ld, nullptr, 0, HX, ldh, ncols, 1.0, 0.0, 0.0)) return r;
+  double *G = c->Smat.as<double>();
+  if (mixed)
+    gram_split_launch(X, ld, HX, ldh, nd, ncols, c->gram_part.as<double>(), G, n_oc, c->stream);
+  else
+    gram_launch(X, ld, HX, ldh, nd, ncols, c->gram_part.as<double>(), G, 0, c->stream);
+  // step 2: eigenpairs of Hhat (all of them; the N_fr largest are used)
+  const JacobiJob job = rr_eigen_job(c, ncols);
+  if (jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, 40, c->host_scratch.data(), c->stream,
+                  nullptr) != 0)
+    return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
+  // step 3: partial rotation of the trailing N_fr columns (and of HX, for
+  // their residuals); the first N_oc columns stay as they are
+  const double *Qfr = job.Q + n_oc;
+  if (rmul_cols_launch(X, ld, nd, ncols, Qfr, ncols, n_fr, n_oc, 0, 0, c->rscratch.as<double>(), c->stream) != 0 ||
+      rmul_cols_launch(HX, ldh, nd, ncols, Qfr, ncols, n_fr, n_oc, 0, 0, c->rscratch.as<double>(), c->stream) != 0)
+    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: block too wide for the row-panel kernel");
+  resid_launch(X + n_oc, ld, HX + n_oc, ldh, job.evals + n_oc, nd, n_fr, c->resid_part.as<double>(),
+               c->resid_d.as<double>(), c->stream);
+  HIPCHK(c, hipMemcpyAsync(evals_fr, job.evals + n_oc, n_fr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(resid_fr, c->resid_d.p, n_fr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // solve
 // ---------------------------------------------------------------------------
 static double elapsed_s(hipEvent_t a, hipEvent_t b) {

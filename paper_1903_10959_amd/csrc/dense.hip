@@ -37,13 +37,17 @@ __device__ __forceinline__ void tri_tile(int t, int &ti, int &tj) {
 // diagonal tile the strictly upper quarter is never read and is skipped.
 // mode 0: every lower tile, FP64.  Mixed overlap: mode 1 computes every
 // quarter except the 64 x 64 diagonal blocks with FP32 inputs and products,
-// mode 2 (diagonal tiles only) the diagonal blocks in FP64.
+// mode 2 (diagonal tiles only) the diagonal blocks in FP64.  Split projected
+// Hamiltonian: mode 3 computes every quarter outside the trailing block
+// (rows and columns >= fr0, fr0 a multiple of 64) with FP32 inputs and
+// products, mode 4 the quarters inside it in FP64.
 template <int VEC, int MODE>
 __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A, int64_t lda,
                                                    const double *__restrict__ B, int64_t ldb, int64_t nrows, int n,
-                                                   int ntiles, int64_t rows_per_split, double *__restrict__ part) {
+                                                   int ntiles, int64_t rows_per_split, int fr0,
+                                                   double *__restrict__ part) {
   typedef double vec_t __attribute__((ext_vector_type(VEC)));
-  typedef typename std::conditional<MODE == 1, float, double>::type CT;   // product type
+  typedef typename std::conditional<MODE == 1 || MODE == 3, float, double>::type CT;   // product type
   typedef typename acc4<CT>::type acc_t;
   constexpr int KR = 16;                          // rows per chunk
   constexpr int PT = KR * GT / (256 * VEC);       // vectors per thread per operand
@@ -63,9 +67,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
   const int wave = tid >> 6, lane = tid & 63;
   const int wi = wave >> 1, wj = wave & 1;
   const int j = lane & 15, kq = lane >> 4;
-  const bool active = MODE == 0 ? !(ti == tj && wi < wj)      // strictly upper quarter: never read
-                    : MODE == 1 ? !(ti == tj && wi <= wj)
-                                : wi == wj;
+  auto quarter_active = [&](int qi, int qj) {
+    const bool lower = !(ti == tj && qi < qj);     // strictly upper quarter: never read
+    const bool in_fr = ti * GT + qi * 64 >= fr0 && tj * GT + qj * 64 >= fr0;
+    return MODE == 0 ? lower : MODE == 1 ? !(ti == tj && qi <= qj) : MODE == 2 ? qi == qj
+         : MODE == 3 ? lower && !in_fr : lower && in_fr;
+  };
+  if (!(quarter_active(0, 0) || quarter_active(1, 0) || quarter_active(0, 1) || quarter_active(1, 1)))
+    return;                                        // whole work-group idle in this mode
+  const bool active = quarter_active(wi, wj);
   const int64_t r0 = (int64_t)split * rows_per_split;
   int64_t r1 = r0 + rows_per_split;
   if (r1 > nrows) r1 = nrows;
@@ -192,16 +202,39 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
   const int nt = (n + GT - 1) / GT;
   const dim3 block(256), all((unsigned)(nsplit * ntiles)), diag((unsigned)(nsplit * nt));
   if (!mixed) {
-    if (v16) hipLaunchKernelGGL((gram_kernel<2, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
-    else hipLaunchKernelGGL((gram_kernel<1, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+    if (v16) hipLaunchKernelGGL((gram_kernel<2, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
+    else hipLaunchKernelGGL((gram_kernel<1, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
   } else {
     if (v16) {
-      hipLaunchKernelGGL((gram_kernel<2, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
-      hipLaunchKernelGGL((gram_kernel<2, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+      hipLaunchKernelGGL((gram_kernel<2, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
+      hipLaunchKernelGGL((gram_kernel<2, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
     } else {
-      hipLaunchKernelGGL((gram_kernel<1, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
-      hipLaunchKernelGGL((gram_kernel<1, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, part);
+      hipLaunchKernelGGL((gram_kernel<1, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
+      hipLaunchKernelGGL((gram_kernel<1, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
     }
+  }
+  int64_t total = (int64_t)n * n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, ntiles, n, G);
+}
+
+void gram_split_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
+                       double *G, int fr0, hipStream_t s) {
+  int ntiles = gram_ntiles(n);
+  int nsplit = gram_nsplit(nrows, n);
+  int64_t rps = (nrows + nsplit - 1) / nsplit;
+  rps = (rps + 15) / 16 * 16;
+  fr0 = fr0 / 64 * 64;
+  const bool v16 = lda % 2 == 0 && ldb % 2 == 0 && n % 2 == 0 && ((uintptr_t)A % 16) == 0 &&
+                   ((uintptr_t)B % 16) == 0;
+  const dim3 block(256), all((unsigned)(nsplit * ntiles));
+  if (v16) {
+    hipLaunchKernelGGL((gram_kernel<2, 3>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
+    hipLaunchKernelGGL((gram_kernel<2, 4>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
+  } else {
+    hipLaunchKernelGGL((gram_kernel<1, 3>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
+    hipLaunchKernelGGL((gram_kernel<1, 4>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
   }
   int64_t total = (int64_t)n * n;
   int64_t blocks = (total + 255) / 256;
@@ -225,16 +258,18 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
 // ---------------------------------------------------------------------------
 static constexpr int MT = 128, NTL = 128, KC = 16;
 
+// C[r, 0:nout] = X[row0 + r, 0:n] W[0:n, 0:nout] (W row stride ldw)
 template <bool MIXED, int VEC>
 __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict__ X, int64_t ld, int64_t row0,
                                                         int64_t nrows, int n, const double *__restrict__ W,
-                                                        int upper, double *__restrict__ C, int64_t ldc) {
+                                                        int64_t ldw, int nout, int upper, double *__restrict__ C,
+                                                        int64_t ldc) {
   typedef double vec_t __attribute__((ext_vector_type(VEC)));
   constexpr int APT = KC * MT / (256 * VEC);     // X vectors per thread per chunk
   constexpr int WPT = KC * NTL / (256 * VEC);    // W vectors per thread per chunk
   __shared__ __align__(16) double As[2][KC][MT];   // As[k][row]
   __shared__ __align__(16) double Ws[2][KC][NTL];  // Ws[k][col]
-  const int nt = (n + NTL - 1) / NTL;
+  const int nt = (nout + NTL - 1) / NTL;
   const int mt = blockIdx.x / nt;
   const int ntile = blockIdx.x - mt * nt;
   const int64_t r0 = row0 + (int64_t)mt * MT;    // first X row of this tile
@@ -264,8 +299,8 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
     for (int i = 0; i < WPT; ++i) {
       const int v = tid + 256 * i;
       const int k = min(k0 + v / (NTL / VEC), n - 1);
-      const int col = min(n0 + (v % (NTL / VEC)) * VEC, n - VEC);
-      wreg[i] = *reinterpret_cast<const vec_t *>(W + (int64_t)k * n + col);
+      const int col = min(n0 + (v % (NTL / VEC)) * VEC, nout - VEC);
+      wreg[i] = *reinterpret_cast<const vec_t *>(W + (int64_t)k * ldw + col);
     }
   };
   auto store_chunk = [&](int buf, int k0) {
@@ -284,7 +319,7 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
       vec_t w = wreg[i];
       const bool kok = k0 + kr < kend;
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) w[e] = (kok && n0 + cv + e < n) ? w[e] : 0.0;
+      for (int e = 0; e < VEC; ++e) w[e] = (kok && n0 + cv + e < nout) ? w[e] : 0.0;
       *reinterpret_cast<vec_t *>(&Ws[buf][kr][cv]) = w;
     }
   };
@@ -354,18 +389,19 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
       for (int q = 0; q < 4; ++q) {
         const int64_t rr = (int64_t)mt * MT + wi * 64 + a * 16 + acc_row<double>(kq, q);  // chunk-local row
         const int col = c0 + b * 16 + j;
-        if (rr < nrows && col < n) C[rr * ldc + col] = acc[a][b][q];
+        if (rr < nrows && col < nout) C[rr * ldc + col] = acc[a][b][q];
       }
 }
 
 __global__ __launch_bounds__(256) void copy_back_kernel(const double *__restrict__ C, int64_t ldc, double *X,
-                                                        int64_t ld, int64_t row0, int64_t nrows, int n) {
+                                                        int64_t ld, int64_t row0, int64_t nrows, int n,
+                                                        int col0) {
   const int64_t total = nrows * (int64_t)n;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = t / n;
     const int c = (int)(t - r * n);
-    X[(row0 + r) * ld + c] = C[r * ldc + c];
+    X[(row0 + r) * ld + col0 + c] = C[r * ldc + c];
   }
 }
 
@@ -377,32 +413,40 @@ int64_t rmul_chunk_rows(int n) {
   return rows;
 }
 
-int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
-                double *scratch, hipStream_t s) {
+int rmul_cols_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int64_t ldw, int nout,
+                     int out_col0, int upper, int mixed, double *scratch, hipStream_t s) {
   if (mixed && !upper) return -1;
-  if (n <= 0 || nrows <= 0) return 0;
+  if (upper && (nout != n || ldw != n)) return -1;
+  if (n <= 0 || nout <= 0 || nrows <= 0) return 0;
   const int64_t chunk = rmul_chunk_rows(n);
   // 16-byte operand loads need even leading dimensions and 16-byte aligned bases
-  const bool v16 = ld % 2 == 0 && n % 2 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)W % 16) == 0;
-  const int nt = (n + NTL - 1) / NTL;
+  const bool v16 = ld % 2 == 0 && n % 2 == 0 && ldw % 2 == 0 && nout % 2 == 0 && ((uintptr_t)X % 16) == 0 &&
+                   ((uintptr_t)W % 16) == 0;
+  const int nt = (nout + NTL - 1) / NTL;
   for (int64_t r = 0; r < nrows; r += chunk) {
     const int64_t rows = (nrows - r < chunk) ? nrows - r : chunk;
     const int64_t mts = (rows + MT - 1) / MT;
     const dim3 grid((unsigned)(mts * nt)), block(256);
+    const int64_t ldc = nout;
     if (mixed) {
-      if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<true, 2>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
-      else hipLaunchKernelGGL((rmul_gemm_kernel<true, 1>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
+      if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<true, 2>), grid, block, 0, s, X, ld, r, rows, n, W, ldw, nout, upper, scratch, ldc);
+      else hipLaunchKernelGGL((rmul_gemm_kernel<true, 1>), grid, block, 0, s, X, ld, r, rows, n, W, ldw, nout, upper, scratch, ldc);
     } else {
-      if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<false, 2>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
-      else hipLaunchKernelGGL((rmul_gemm_kernel<false, 1>), grid, block, 0, s, X, ld, r, rows, n, W, upper, scratch, (int64_t)n);
+      if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<false, 2>), grid, block, 0, s, X, ld, r, rows, n, W, ldw, nout, upper, scratch, ldc);
+      else hipLaunchKernelGGL((rmul_gemm_kernel<false, 1>), grid, block, 0, s, X, ld, r, rows, n, W, ldw, nout, upper, scratch, ldc);
     }
-    int64_t total = rows * n;
+    int64_t total = rows * nout;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(copy_back_kernel, dim3((unsigned)blocks), dim3(256), 0, s, scratch, (int64_t)n, X, ld, r,
-                       rows, n);
+    hipLaunchKernelGGL(copy_back_kernel, dim3((unsigned)blocks), dim3(256), 0, s, scratch, ldc, X, ld, r, rows, nout,
+                       out_col0);
   }
   return 0;
+}
+
+int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
+                double *scratch, hipStream_t s) {
+  return rmul_cols_launch(X, ld, nrows, n, W, n, n, 0, upper, mixed, scratch, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -170,3 +170,52 @@ def test_solve_precision_ladder_reaches_fp64_accuracy(ladder, mixed):
     err = np.abs(out["evals"][:N] - ev[:N]) / np.maximum(np.abs(ev[:N]), 1.0)
     assert np.max(err) < (1e-10 if not mixed else 1e-8), err
     c.close()
+
+
+@pytest.mark.parametrize("ncols,n_fr", [(24, 4), (97, 15), (200, 30), (200, 200), (65, 1)])
+def test_rayleigh_ritz_split_fp64_equals_full(ncols, n_fr):
+    """Spectrum splitting with an all-FP64 projection: the N_fr largest Ritz
+    pairs of the full Rayleigh-Ritz; the first N_oc columns untouched."""
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = och.cholgs(workload.start_block(c.n_dof, ncols, 500 + ncols))
+    ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
+    Xr, HXr, D, res = och.rayleigh_ritz(ap, X)
+    n_oc = ncols - n_fr
+    Xg = to_gpu(X)
+    ev, rs = c.rayleigh_ritz_split(Xg, n_fr, mixed=False)
+    scale = max(1.0, np.max(np.abs(D)))
+    np.testing.assert_allclose(ev, D[n_oc:], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(rs, res[n_oc:], rtol=1e-6, atol=1e-11 * scale)
+    G = to_host(Xg)
+    assert np.array_equal(G[:, :n_oc], X[:, :n_oc])
+    sgn = np.sign(np.sum(G[:, n_oc:] * Xr[:, n_oc:], axis=0))
+    assert np.max(np.abs(G[:, n_oc:] * sgn[None, :] - Xr[:, n_oc:])) < 1e-8
+    c.close()
+
+
+def test_rayleigh_ritz_split_mixed_precision_accuracy():
+    """Mixed projection (FP32 outside the fr-fr block): on a random block the
+    N_fr largest Ritz values carry FP32-level error; near convergence (the
+    regime the paper's argument is made for) the coupling blocks vanish and
+    the error drops far below it."""
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
+    ncols, n_fr = 130, 20
+    n_oc = ncols - n_fr
+    X = och.cholgs(workload.start_block(c.n_dof, ncols, 77))
+    _, _, D, _ = och.rayleigh_ritz(ap, X)
+    ev, _ = c.rayleigh_ritz_split(to_gpu(X), n_fr, mixed=True)
+    scale = np.max(np.abs(D))
+    err_random = np.max(np.abs(ev - D[n_oc:]))
+    assert err_random < 1e-5 * scale, err_random
+    # near-converged block: exact eigenvectors plus a 1e-4 perturbation
+    H = fem.htilde_csr(prob.L, prob.n_el, prob.p, V)
+    w, U = och.eig_dense(H)
+    Xn = och.cholgs(U[:, :ncols] + 1e-4 * workload.start_block(c.n_dof, ncols, 78))
+    _, _, Dn, _ = och.rayleigh_ritz(ap, Xn)
+    evn, _ = c.rayleigh_ritz_split(to_gpu(Xn), n_fr, mixed=True)
+    err_conv = np.max(np.abs(evn - Dn[n_oc:]))
+    assert err_conv < 1e-8 * scale and err_conv < err_random / 10, (err_conv, err_random)
+    c.close()
