@@ -245,7 +245,12 @@ def rr_split_compare(args, prob):
     ctx.set_potential(workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords()))
     X0 = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=dev)
     ctx.orthonormalize(X0)
-    ctx.rayleigh_ritz(X0)          # a Ritz basis, as at the end of a ChFSI pass
+    ev0, _ = ctx.rayleigh_ritz(X0)
+    # the block Rayleigh-Ritz sees inside a ChFSI pass: filtered, then
+    # orthonormalised (not yet a Ritz basis of its own span)
+    ctx.chebyshev_filter(X0, prob.degree, float(ev0[-1]), ctx.upper_bound, float(ev0[0]),
+                         block_width=prob.block_width)
+    ctx.orthonormalize(X0)
     n_fr = max(1, int(round(0.15 * prob.nstates)))
     nb = prob.nblock
     times = {"full": [], "split_mixed": [], "split_fp64": []}

@@ -254,6 +254,13 @@ int chfsi_last_filter_timing(chfsi_ctx *ctx, double *ms_cells, int *n_launches, 
  * (set it before adding the context to a batch session).  Errors:
  * CHFSI_ERR_ARG for a null ctx or a variant outside -1..1. */
 int chfsi_set_tile_variant(chfsi_ctx *ctx, int variant);
+/* How rayleighRitz (both forms) obtains Htilde times the rotated columns for
+ * the residuals (Sec. 3.5 step iii leaves this open): 0 = cost model
+ * (default): rotate HX with X when that GEMM is cheaper than the cell
+ * products, else apply Htilde again; 1 = always rotate HX; 2 = always apply
+ * Htilde again.  Both give the same vectors up to rounding; HX_out receives
+ * whichever.  Errors: CHFSI_ERR_ARG for a null ctx or a mode outside 0..2. */
+int chfsi_set_rr_residual(chfsi_ctx *ctx, int mode);
 
 #ifdef __cplusplus
 }

@@ -352,6 +352,11 @@ class Context:
         self.tile_variant = int(variant)
         return self
 
+    def set_rr_residual(self, mode: int = 0):
+        """Ritz residuals: 0 cost model, 1 rotate HX with X, 2 apply Htilde again."""
+        self._check(self._lib.chfsi_set_rr_residual(self._h, int(mode)), "set_rr_residual")
+        return self
+
     def set_timing(self, enable: bool = True):
         self._check(self._lib.chfsi_set_timing(self._h, 1 if enable else 0), "set_timing")
 

@@ -59,6 +59,7 @@ SIGNATURES = {
     "chfsi_rayleigh_ritz_split": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp, _vp]),
     "chfsi_set_timing": (_int, [_vp, _int]),
     "chfsi_set_tile_variant": (_int, [_vp, _int]),
+    "chfsi_set_rr_residual": (_int, [_vp, _int]),
     "chfsi_reset_timing": (_int, [_vp]),
     "chfsi_last_filter_timing": (_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
 }

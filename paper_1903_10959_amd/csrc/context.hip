@@ -278,6 +278,13 @@ extern "C" int chfsi_set_tile_variant(chfsi_ctx *c, int variant) {
   return 0;
 }
 
+extern "C" int chfsi_set_rr_residual(chfsi_ctx *c, int mode) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (mode < 0 || mode > 2) return fail(c, CHFSI_ERR_ARG, "rr residual mode must be 0, 1 or 2");
+  c->rr_residual = mode;
+  return 0;
+}
+
 extern "C" int chfsi_reset_timing(chfsi_ctx *c) {
   if (!c) return CHFSI_ERR_ARG;
   c->ev_used = 0;
@@ -523,7 +530,7 @@ int chfsi::ensure_small(chfsi_ctx *c, int n) {
   HIPCHK(c, c->flag.ensure(4 * sizeof(int)));
   HIPCHK(c, c->diag0.ensure((size_t)n * sizeof(double)));
   HIPCHK(c, c->minratio.ensure((size_t)nb * sizeof(double)));
-  HIPCHK(c, c->rscratch.ensure((size_t)rmul_chunk_rows(n) * n * sizeof(double)));
+  HIPCHK(c, c->rscratch.ensure(rmul_scratch_elems(c->mesh.n_dof, n) * sizeof(double)));
   if ((int)c->host_scratch.size() < nb + 16) c->host_scratch.resize(nb + 16);
   HIPCHK(c, c->gram_part.ensure(gram_part_elems(c->mesh.n_dof, n) * sizeof(double)));
   HIPCHK(c, c->resid_part.ensure((size_t)resid_nchunk(c->mesh.n_dof) * n * sizeof(double)));
@@ -556,7 +563,7 @@ static int cholgs_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed
     return fail(c, CHFSI_ERR_NOT_SPD, msg);
   }
   trtri_t_launch(S, c->dinv.as<double>(), ncols, c->Zmat.as<double>(), c->Wmat.as<double>(), c->stream);
-  if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->rscratch.as<double>(), c->stream) != 0)
+  if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->rscratch.as<double>(), c->rscratch.bytes / sizeof(double), c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "orthonormalize: block too wide for the row-panel kernel");
   HIPCHK(c, hipGetLastError());
   return 0;
@@ -610,14 +617,41 @@ chfsi::JacobiJob chfsi::rr_eigen_job(chfsi_ctx *c, int ncols) {
                    c->Wmat.as<double>()};
 }
 
-// Part 3: X <- X Q, HX <- HX Q, residual norms; evals and resid to the host.
+// The residuals of k rotated columns need Htilde applied to them: either HX is
+// rotated with X (2 n_dof ncols flops per column, a plain GEMM) or Htilde is
+// applied again (the cell products, 2 n_cells np^2 flops per column, which run
+// at a lower fraction of peak than the GEMM: weighted 1.4).  Both give Htilde
+// times the rotated columns; the cheaper is taken unless the mode forces one.
+static bool rr_reapply(const chfsi_ctx *c, int ncols) {
+  if (c->rr_residual != 0) return c->rr_residual == 2;
+  const MeshTables &M = c->mesh;
+  const double cells = (double)M.n_el * M.n_el * M.n_el;
+  return 1.4 * cells * M.np * M.np < (double)M.n_dof * ncols;
+}
+
+// Rotates the columns [col0, col0 + nout) of X (and of HX) by W (ncols x nout,
+// row stride ncols); HX then holds Htilde X on those columns, by rotation or by
+// a fresh application.
+static int rr_rotate(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, const double *W,
+                     int nout, int col0) {
+  const int64_t nd = c->mesh.n_dof;
+  double *scr = c->rscratch.as<double>();
+  const size_t se = c->rscratch.bytes / sizeof(double);
+  if (rmul_cols_launch(X, ld, nd, ncols, W, ncols, nout, col0, 0, 0, scr, se, c->stream) != 0)
+    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
+  if (rr_reapply(c, ncols))
+    return cheb_step_t<double>(c, X + col0, ld, nullptr, 0, HX + col0, ldh, nout, 1.0, 0.0, 0.0);
+  if (rmul_cols_launch(HX, ldh, nd, ncols, W, ncols, nout, col0, 0, 0, scr, se, c->stream) != 0)
+    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
+  return 0;
+}
+
+// Part 3: X <- X Q, HX = Htilde X (rr_rotate), residual norms; evals and
+// resid to the host.
 int chfsi::rr_finish(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
                      double *resid) {
   const int64_t nd = c->mesh.n_dof;
-  const double *Q = c->Wmat.as<double>();
-  if (rmul_launch(X, ld, nd, ncols, Q, 0, 0, c->rscratch.as<double>(), c->stream) != 0 ||
-      rmul_launch(HX, ldh, nd, ncols, Q, 0, 0, c->rscratch.as<double>(), c->stream) != 0)
-    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
+  if (int r = rr_rotate(c, X, ld, ncols, HX, ldh, c->Wmat.as<double>(), ncols, 0)) return r;
   resid_launch(X, ld, HX, ldh, c->evals_d.as<double>(), nd, ncols, c->resid_part.as<double>(),
                c->resid_d.as<double>(), c->stream);
   HIPCHK(c, hipMemcpyAsync(evals, c->evals_d.p, ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -680,12 +714,9 @@ extern "C" int chfsi_rayleigh_ritz_split(chfsi_ctx *c, double *X, int64_t ld, in
   if (jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, 40, c->host_scratch.data(), c->stream,
                   nullptr) != 0)
     return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
-  // step 3: partial rotation of the trailing N_fr columns (and of HX, for
-  // their residuals); the first N_oc columns stay as they are
-  const double *Qfr = job.Q + n_oc;
-  if (rmul_cols_launch(X, ld, nd, ncols, Qfr, ncols, n_fr, n_oc, 0, 0, c->rscratch.as<double>(), c->stream) != 0 ||
-      rmul_cols_launch(HX, ldh, nd, ncols, Qfr, ncols, n_fr, n_oc, 0, 0, c->rscratch.as<double>(), c->stream) != 0)
-    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: block too wide for the row-panel kernel");
+  // step 3: partial rotation of the trailing N_fr columns (and Htilde on
+  // them, for their residuals); the first N_oc columns stay as they are
+  if (int r = rr_rotate(c, X, ld, ncols, HX, ldh, job.Q + n_oc, n_fr, n_oc)) return r;
   resid_launch(X + n_oc, ld, HX + n_oc, ldh, job.evals + n_oc, nd, n_fr, c->resid_part.as<double>(),
                c->resid_d.as<double>(), c->stream);
   HIPCHK(c, hipMemcpyAsync(evals_fr, job.evals + n_oc, n_fr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -812,8 +843,8 @@ extern "C" size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_w
   b += nd * nblock * 8;                                            // HX
   const size_t nn = (size_t)nblock * nblock;
   b += 4 * nn * 8 + jacobi_work_elems(nblock) * 8;                 // S, Z, W, jacobi
-  b += gram_part_elems((int64_t)nd, nblock) * 8;
-  b += (size_t)rmul_chunk_rows(nblock) * nblock * 8;
+  b += gram_part_elems_slots((int64_t)nd, nblock, 512) * 8;       // 256 CUs x 2 resident gram work-groups
+  b += rmul_scratch_elems((int64_t)nd, nblock) * 8;
   b += (size_t)resid_nchunk((int64_t)nd) * nblock * 8;
   return b;
 }

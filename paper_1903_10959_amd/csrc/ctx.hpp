@@ -51,6 +51,7 @@ struct chfsi_ctx {
   chfsi::DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
   int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
   int tile_variant = -1;  // cell-kernel tile configuration (-1: built-in choice)
+  int rr_residual = 0;    // Ritz residuals: 0 cost model, 1 rotate HX, 2 apply Htilde again
   // workspaces
   chfsi::DevBuf fbuf[3];      // filter recursion buffers
   chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,

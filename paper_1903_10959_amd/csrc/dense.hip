@@ -6,9 +6,17 @@
 //    the 64x64 diagonal blocks, FP32 inputs/products on the rest.
 //  * rmul: X <- X W in place by row panels (Sec. 3.4 step 4, X L^-T; Sec. 3.5
 //    subspace rotation X Q).  The paper's outer blocking over rows (B^d) keeps
-//    only a panel of the output in extra memory; here a panel of R rows is
-//    staged in LDS and overwritten in place.
+//    only a panel of the output in extra memory: here a chunk of rows is
+//    multiplied into a scratch panel and copied back.
 //  * resid: column norms ||HX_j - lam_j X_j||.
+//
+// Launch shapes are sized from the device's resident work-group count (CUs x
+// work-groups per CU at the kernel's occupancy), so that a grid ends just
+// under a whole number of rounds: a grid of 4.04 rounds takes as long as one
+// of 5.  Work-groups are dispatched to the 8 XCDs round-robin; the block index
+// is remapped so that work-groups sharing operand rows (the tiles of one gram
+// split, the column tiles of one rmul row tile) run on one XCD and share its
+// L2.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,6 +26,25 @@
 namespace chfsi {
 
 static constexpr int GT = 128;  // gram output tile (4 waves x 64x64)
+
+// Resident work-groups of `kern` (256 threads) on the current device.
+template <typename K>
+static int resident_slots(K kern) {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0);
+  return (cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+}
+
+// Physical block index -> logical index such that the logical indices on one
+// XCD (physical b = 8 i + x) are contiguous: XCD x holds [x*per + min(x, rem),
+// ... + per + (x < rem)).
+__device__ __forceinline__ int xcd_grouped_block() {
+  const int g = (int)gridDim.x, b = (int)blockIdx.x;
+  const int per = g >> 3, rem = g & 7, x = b & 7;
+  return x * per + min(x, rem) + (b >> 3);
+}
 
 // lower-triangle tile enumeration t -> (ti, tj), ti >= tj
 __device__ __forceinline__ void tri_tile(int t, int &ti, int &tj) {
@@ -35,33 +62,43 @@ __device__ __forceinline__ void tri_tile(int t, int &ti, int &tj) {
 // double-buffered LDS area after the chunk's MFMAs, and published by one
 // barrier per chunk.  Wave (wi, wj) owns the 64 x 64 quarter (wi, wj); on a
 // diagonal tile the strictly upper quarter is never read and is skipped.
+// FP32 modes stage the chunk in LDS already rounded to FP32 (half the LDS
+// bytes, so more resident work-groups).
 // mode 0: every lower tile, FP64.  Mixed overlap: mode 1 computes every
 // quarter except the 64 x 64 diagonal blocks with FP32 inputs and products,
 // mode 2 (diagonal tiles only) the diagonal blocks in FP64.  Split projected
 // Hamiltonian: mode 3 computes every quarter outside the trailing block
 // (rows and columns >= fr0, fr0 a multiple of 64) with FP32 inputs and
 // products, mode 4 the quarters inside it in FP64.
+// Grid: nsplit x ngrid work-groups.  Modes 0, 1, 3: ngrid = ntl = all lower
+// tiles.  Mode 2: ngrid = the diagonal tiles, part indexed by the full
+// triangle (ntl tiles).  Mode 4: ngrid = ntl = the lower tiles of the trailing
+// sub-triangle starting at tile row/column tf, part indexed within it.
 template <int VEC, int MODE>
 __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A, int64_t lda,
                                                    const double *__restrict__ B, int64_t ldb, int64_t nrows, int n,
-                                                   int ntiles, int64_t rows_per_split, int fr0,
+                                                   int ngrid, int ntl, int tf, int64_t rows_per_split, int fr0,
                                                    double *__restrict__ part) {
   typedef double vec_t __attribute__((ext_vector_type(VEC)));
   typedef typename std::conditional<MODE == 1 || MODE == 3, float, double>::type CT;   // product type
   typedef typename acc4<CT>::type acc_t;
+  typedef CT lds_vec_t __attribute__((ext_vector_type(VEC)));
   constexpr int KR = 16;                          // rows per chunk
   constexpr int PT = KR * GT / (256 * VEC);       // vectors per thread per operand
-  __shared__ __align__(16) double As[2][KR][GT];
-  __shared__ __align__(16) double Bs[2][KR][GT];
-  const int ngrid = MODE == 2 ? (int)((sqrt(8.0 * ntiles + 1.0) - 1.0) * 0.5 + 0.5) : ntiles;
-  const int split = blockIdx.x / ngrid;
-  int t = blockIdx.x - split * ngrid;
+  // staged in the product type: FP32 modes round once, at the LDS store
+  __shared__ __align__(16) CT As[2][KR][GT];
+  __shared__ __align__(16) CT Bs[2][KR][GT];
+  const int lid = xcd_grouped_block();
+  const int split = lid / ngrid;
+  int t = lid - split * ngrid;                    // part tile index
   int ti, tj;
   if (MODE == 2) {
     ti = tj = t;                                  // diagonal tile t
     t = ti * (ti + 1) / 2 + ti;
   } else {
     tri_tile(t, ti, tj);
+    ti += tf;
+    tj += tf;
   }
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -100,14 +137,14 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
       const int v = tid + 256 * i;
       const int kr = v / (GT / VEC), cv = (v % (GT / VEC)) * VEC;
       const bool rok = k0 + kr < r1;
-      vec_t a = areg[i], b = breg[i];
+      lds_vec_t a, b;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        a[e] = (rok && ib + cv + e < n) ? a[e] : 0.0;
-        b[e] = (rok && jb + cv + e < n) ? b[e] : 0.0;
+        a[e] = (rok && ib + cv + e < n) ? (CT)areg[i][e] : (CT)0;
+        b[e] = (rok && jb + cv + e < n) ? (CT)breg[i][e] : (CT)0;
       }
-      *reinterpret_cast<vec_t *>(&As[buf][kr][cv]) = a;
-      *reinterpret_cast<vec_t *>(&Bs[buf][kr][cv]) = b;
+      *reinterpret_cast<lds_vec_t *>(&As[buf][kr][cv]) = a;
+      *reinterpret_cast<lds_vec_t *>(&Bs[buf][kr][cv]) = b;
     }
   };
 
@@ -130,7 +167,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
 #pragma unroll
       for (int ks = 0; ks < KR; ks += 4) {
         const int kk = ks + kq;
-        double av[4], bv[4];
+        CT av[4], bv[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][wi * 64 + a * 16 + j];
 #pragma unroll
@@ -138,14 +175,14 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4((CT)av[a], (CT)bv[b], acc[a][b]);
+          for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x4(av[a], bv[b], acc[a][b]);
       }
     }
     if (kc + 1 < nk) store_chunk(buf ^ 1, r0 + (kc + 1) * KR);
     __syncthreads();
   }
   if (!active) return;
-  double *out = part + ((int64_t)split * ntiles + t) * (GT * GT) + (wi * 64) * GT + wj * 64;
+  double *out = part + ((int64_t)split * ntl + t) * (GT * GT) + (wi * 64) * GT + wj * 64;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -156,18 +193,24 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
       }
 }
 
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double *__restrict__ part, int nsplit, int ntiles,
-                                                          int n, double *__restrict__ G) {
-  const int64_t total = (int64_t)n * n;
+// G[i, j] = sum over splits of the partial tiles, for i >= j in the region
+// [r0, n) x [r0, n) (tiles numbered within the sub-triangle from tile row tf),
+// mirrored to the upper triangle.  skip0 >= 0: leave out the entries with both
+// i and j >= skip0 (written by another reduction).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double *__restrict__ part, int nsplit, int ntl,
+                                                          int n, int tf, int r0, int skip0,
+                                                          double *__restrict__ G) {
+  const int m = n - r0;
+  const int64_t total = (int64_t)m * m;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx / n), jj = (int)(idx - (int64_t)i * n);
-    if (jj > i) continue;
-    int ti = i / GT, tj = jj / GT;
-    int t = ti * (ti + 1) / 2 + tj;
-    const double *p = part + (int64_t)t * (GT * GT) + (i - ti * GT) * GT + (jj - tj * GT);
+    const int i = r0 + (int)(idx / m), jj = r0 + (int)(idx - idx / m * m);
+    if (jj > i || (skip0 >= 0 && jj >= skip0)) continue;
+    const int ti = i / GT - tf, tj = jj / GT - tf;
+    const int t = ti * (ti + 1) / 2 + tj;
+    const double *p = part + (int64_t)t * (GT * GT) + (i % GT) * GT + (jj % GT);
     double s = 0;
-    for (int sp = 0; sp < nsplit; ++sp) s += p[(int64_t)sp * ntiles * (GT * GT)];
+    for (int sp = 0; sp < nsplit; ++sp) s += p[(int64_t)sp * ntl * (GT * GT)];
     G[(int64_t)i * n + jj] = s;
     G[(int64_t)jj * n + i] = s;
   }
@@ -178,68 +221,102 @@ static int gram_ntiles(int n) {
   return nt * (nt + 1) / 2;
 }
 
-int gram_nsplit(int64_t nrows, int n) {
-  int ntiles = gram_ntiles(n);
-  int64_t want = (2048 + ntiles - 1) / ntiles;           // about 8 work-groups per CU
-  int64_t maxs = (nrows + 255) / 256;                    // at least 256 rows per split
+// Row splits for a launch of ntl tiles: the largest count whose grid fits in
+// four rounds of `slots` resident work-groups, with at least 256 rows per split.
+static int gram_nsplit_tiles(int64_t nrows, int ntl, int slots) {
+  int64_t want = 4 * (int64_t)slots / ntl;
+  const int64_t maxs = (nrows + 255) / 256;
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
   return (int)want;
 }
 
-size_t gram_part_elems(int64_t nrows, int n) {
-  return (size_t)gram_nsplit(nrows, n) * gram_ntiles(n) * GT * GT;
+static int gram_slots() { return resident_slots(gram_kernel<2, 0>); }
+
+int gram_nsplit(int64_t nrows, int n) { return gram_nsplit_tiles(nrows, gram_ntiles(n), gram_slots()); }
+
+// Enough for a launch over the full triangle or over any trailing sub-triangle.
+size_t gram_part_elems_slots(int64_t nrows, int n, int slots) {
+  const int nt = (n + GT - 1) / GT;
+  size_t best = 0;
+  for (int m = 1; m <= nt; ++m) {
+    const int ntl = m * (m + 1) / 2;
+    const size_t e = (size_t)gram_nsplit_tiles(nrows, ntl, slots) * ntl;
+    if (e > best) best = e;
+  }
+  return best * GT * GT;
+}
+
+size_t gram_part_elems(int64_t nrows, int n) { return gram_part_elems_slots(nrows, n, gram_slots()); }
+
+static int64_t gram_rows_per_split(int64_t nrows, int nsplit) {
+  int64_t rps = (nrows + nsplit - 1) / nsplit;
+  return (rps + 15) / 16 * 16;
+}
+
+static void gram_reduce(const double *part, int nsplit, int ntl, int n, int tf, int r0, int skip0, double *G,
+                        hipStream_t s) {
+  const int64_t m = n - r0;
+  int64_t blocks = (m * m + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) return;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, ntl, n, tf, r0,
+                     skip0, G);
+}
+
+static bool gram_v16(const double *A, int64_t lda, const double *B, int64_t ldb, int n) {
+  return lda % 2 == 0 && ldb % 2 == 0 && n % 2 == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0;
+}
+
+template <int MODE>
+static void gram_mode(bool v16, dim3 grid, const double *A, int64_t lda, const double *B, int64_t ldb,
+                      int64_t nrows, int n, int ngrid, int ntl, int tf, int64_t rps, int fr0, double *part,
+                      hipStream_t s) {
+  if (v16)
+    hipLaunchKernelGGL((gram_kernel<2, MODE>), grid, dim3(256), 0, s, A, lda, B, ldb, nrows, n, ngrid, ntl, tf, rps,
+                       fr0, part);
+  else
+    hipLaunchKernelGGL((gram_kernel<1, MODE>), grid, dim3(256), 0, s, A, lda, B, ldb, nrows, n, ngrid, ntl, tf, rps,
+                       fr0, part);
 }
 
 void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                  double *G, int mixed, hipStream_t s) {
-  int ntiles = gram_ntiles(n);
-  int nsplit = gram_nsplit(nrows, n);
-  int64_t rps = (nrows + nsplit - 1) / nsplit;
-  rps = (rps + 15) / 16 * 16;
-  const bool v16 = lda % 2 == 0 && ldb % 2 == 0 && n % 2 == 0 && ((uintptr_t)A % 16) == 0 &&
-                   ((uintptr_t)B % 16) == 0;
+  const int ntiles = gram_ntiles(n);
+  const int nsplit = gram_nsplit_tiles(nrows, ntiles, gram_slots());
+  const int64_t rps = gram_rows_per_split(nrows, nsplit);
+  const bool v16 = gram_v16(A, lda, B, ldb, n);
   const int nt = (n + GT - 1) / GT;
-  const dim3 block(256), all((unsigned)(nsplit * ntiles)), diag((unsigned)(nsplit * nt));
+  const dim3 all((unsigned)(nsplit * ntiles)), diag((unsigned)(nsplit * nt));
   if (!mixed) {
-    if (v16) hipLaunchKernelGGL((gram_kernel<2, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
-    else hipLaunchKernelGGL((gram_kernel<1, 0>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
+    gram_mode<0>(v16, all, A, lda, B, ldb, nrows, n, ntiles, ntiles, 0, rps, 0, part, s);
   } else {
-    if (v16) {
-      hipLaunchKernelGGL((gram_kernel<2, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
-      hipLaunchKernelGGL((gram_kernel<2, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
-    } else {
-      hipLaunchKernelGGL((gram_kernel<1, 1>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
-      hipLaunchKernelGGL((gram_kernel<1, 2>), diag, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, 0, part);
-    }
+    gram_mode<1>(v16, all, A, lda, B, ldb, nrows, n, ntiles, ntiles, 0, rps, 0, part, s);
+    gram_mode<2>(v16, diag, A, lda, B, ldb, nrows, n, nt, ntiles, 0, rps, 0, part, s);
   }
-  int64_t total = (int64_t)n * n;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, ntiles, n, G);
+  gram_reduce(part, nsplit, ntiles, n, 0, 0, -1, G, s);
 }
 
 void gram_split_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                        double *G, int fr0, hipStream_t s) {
-  int ntiles = gram_ntiles(n);
-  int nsplit = gram_nsplit(nrows, n);
-  int64_t rps = (nrows + nsplit - 1) / nsplit;
-  rps = (rps + 15) / 16 * 16;
   fr0 = fr0 / 64 * 64;
-  const bool v16 = lda % 2 == 0 && ldb % 2 == 0 && n % 2 == 0 && ((uintptr_t)A % 16) == 0 &&
-                   ((uintptr_t)B % 16) == 0;
-  const dim3 block(256), all((unsigned)(nsplit * ntiles));
-  if (v16) {
-    hipLaunchKernelGGL((gram_kernel<2, 3>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
-    hipLaunchKernelGGL((gram_kernel<2, 4>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
-  } else {
-    hipLaunchKernelGGL((gram_kernel<1, 3>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
-    hipLaunchKernelGGL((gram_kernel<1, 4>), all, block, 0, s, A, lda, B, ldb, nrows, n, ntiles, rps, fr0, part);
-  }
-  int64_t total = (int64_t)n * n;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, nsplit, ntiles, n, G);
+  const bool v16 = gram_v16(A, lda, B, ldb, n);
+  // the trailing block in FP64, on a grid over its own sub-triangle of tiles
+  // (so that the few tiles it touches get every row split), reduced first
+  const int nt = (n + GT - 1) / GT, tf = fr0 / GT, m = nt - tf;
+  const int ntl4 = m * (m + 1) / 2;
+  const int slots = gram_slots();
+  const int nsplit4 = gram_nsplit_tiles(nrows, ntl4, slots);
+  gram_mode<4>(v16, dim3((unsigned)(nsplit4 * ntl4)), A, lda, B, ldb, nrows, n, ntl4, ntl4, tf,
+               gram_rows_per_split(nrows, nsplit4), fr0, part, s);
+  gram_reduce(part, nsplit4, ntl4, n, tf, fr0, -1, G, s);
+  if (fr0 == 0) return;
+  // everything else with FP32 inputs and products; part is reused in order
+  const int ntiles = gram_ntiles(n);
+  const int nsplit = gram_nsplit_tiles(nrows, ntiles, slots);
+  gram_mode<3>(v16, dim3((unsigned)(nsplit * ntiles)), A, lda, B, ldb, nrows, n, ntiles, ntiles, 0,
+               gram_rows_per_split(nrows, nsplit), fr0, part, s);
+  gram_reduce(part, nsplit, ntiles, n, 0, 0, fr0, G, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,8 +347,9 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
   __shared__ __align__(16) double As[2][KC][MT];   // As[k][row]
   __shared__ __align__(16) double Ws[2][KC][NTL];  // Ws[k][col]
   const int nt = (nout + NTL - 1) / NTL;
-  const int mt = blockIdx.x / nt;
-  const int ntile = blockIdx.x - mt * nt;
+  const int lid = xcd_grouped_block();
+  const int mt = lid / nt;
+  const int ntile = lid - mt * nt;
   const int64_t r0 = row0 + (int64_t)mt * MT;    // first X row of this tile
   const int64_t rlast = row0 + nrows - 1;         // last valid row
   const int n0 = ntile * NTL;
@@ -405,24 +483,38 @@ __global__ __launch_bounds__(256) void copy_back_kernel(const double *__restrict
   }
 }
 
-int64_t rmul_chunk_rows(int n) {
-  // about 256 MiB of scratch, a multiple of the 128-row tile
-  int64_t rows = ((int64_t)1 << 25) / (n > 0 ? n : 1);
-  rows = rows / MT * MT;
-  if (rows < MT) rows = MT;
-  return rows;
+size_t rmul_scratch_elems(int64_t nrows, int n) {
+  // at most 1 GiB, and no more than the whole product needs
+  const int64_t cap = (int64_t)1 << 27;
+  const int64_t all = (nrows + MT - 1) / MT * MT * (int64_t)(n > 0 ? n : 1);
+  int64_t e = all < cap ? all : cap;
+  if (e < (int64_t)MT * n) e = (int64_t)MT * n;
+  return (size_t)e;
 }
 
 int rmul_cols_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int64_t ldw, int nout,
-                     int out_col0, int upper, int mixed, double *scratch, hipStream_t s) {
+                     int out_col0, int upper, int mixed, double *scratch, size_t scratch_elems, hipStream_t s) {
   if (mixed && !upper) return -1;
   if (upper && (nout != n || ldw != n)) return -1;
   if (n <= 0 || nout <= 0 || nrows <= 0) return 0;
-  const int64_t chunk = rmul_chunk_rows(n);
+  if (scratch_elems < (size_t)MT * nout) return -1;
+  const int nt = (nout + NTL - 1) / NTL;
+  // row tiles per launch: as many as the scratch panel holds, rounded down to
+  // whole rounds of resident work-groups when there is more than one round
+  const int64_t mts_all = (nrows + MT - 1) / MT;
+  int64_t mts_chunk = (int64_t)(scratch_elems / nout) / MT;
+  if (mts_chunk < mts_all) {
+    const int64_t slots = mixed ? resident_slots(rmul_gemm_kernel<true, 2>) : resident_slots(rmul_gemm_kernel<false, 2>);
+    const int64_t rounds = mts_chunk * nt / slots;
+    if (rounds >= 1) mts_chunk = rounds * slots / nt;
+  } else {
+    mts_chunk = mts_all;
+  }
+  if (mts_chunk < 1) mts_chunk = 1;
+  const int64_t chunk = mts_chunk * MT;
   // 16-byte operand loads need even leading dimensions and 16-byte aligned bases
   const bool v16 = ld % 2 == 0 && n % 2 == 0 && ldw % 2 == 0 && nout % 2 == 0 && ((uintptr_t)X % 16) == 0 &&
                    ((uintptr_t)W % 16) == 0;
-  const int nt = (nout + NTL - 1) / NTL;
   for (int64_t r = 0; r < nrows; r += chunk) {
     const int64_t rows = (nrows - r < chunk) ? nrows - r : chunk;
     const int64_t mts = (rows + MT - 1) / MT;
@@ -445,8 +537,8 @@ int rmul_cols_launch(double *X, int64_t ld, int64_t nrows, int n, const double *
 }
 
 int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
-                double *scratch, hipStream_t s) {
-  return rmul_cols_launch(X, ld, nrows, n, W, n, n, 0, upper, mixed, scratch, s);
+                double *scratch, size_t scratch_elems, hipStream_t s) {
+  return rmul_cols_launch(X, ld, nrows, n, W, n, n, 0, upper, mixed, scratch, scratch_elems, s);
 }
 
 // ---------------------------------------------------------------------------

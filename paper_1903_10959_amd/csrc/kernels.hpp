@@ -80,8 +80,12 @@ void nonfinite_launch(const T *X, int64_t ld, int64_t nrows, int ncols, int *fla
 // partial tiles go to `part` ([nsplit x ntiles x 128 x 128]) and are summed in
 // a fixed order into G (n x n, row-major, lower triangle mirrored to upper).
 // mixed: 64x64 diagonal blocks in FP64, the rest with FP32 inputs/products.
+// nsplit is sized from the device's resident work-groups; gram_part_elems is
+// the partial buffer for any gram launch on the current device, and
+// gram_part_elems_slots the same for a given resident count (no device query).
 int gram_nsplit(int64_t nrows, int n);
 size_t gram_part_elems(int64_t nrows, int n);
+size_t gram_part_elems_slots(int64_t nrows, int n, int slots);
 void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                  double *G, int mixed, hipStream_t s);
 // As gram_launch, with the trailing block (rows and columns >= fr0, rounded
@@ -90,17 +94,18 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
 void gram_split_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                        double *G, int fr0, hipStream_t s);
 // X[r, 0:n] <- X[r, 0:n] W for all rows, chunk by chunk through `scratch`
-// (rmul_chunk_rows(n) x n doubles).  W: n x n row-major.  upper: W upper
-// triangular (zero blocks skipped).  mixed (requires upper): the 64-wide
-// diagonal blocks of W in FP64, the rest with FP32 inputs and products.
-int64_t rmul_chunk_rows(int n);
+// (scratch_elems doubles, at least 128 x n; rmul_scratch_elems gives the size
+// used by the library).  W: n x n row-major.  upper: W upper triangular (zero
+// blocks skipped).  mixed (requires upper): the 64-wide diagonal blocks of W in
+// FP64, the rest with FP32 inputs and products.  Returns -1 on bad arguments.
+size_t rmul_scratch_elems(int64_t nrows, int n);
 int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int upper, int mixed,
-                double *scratch, hipStream_t s);
+                double *scratch, size_t scratch_elems, hipStream_t s);
 // X[r, out_col0 : out_col0+nout] <- X[r, 0:n] W[0:n, 0:nout] (W row stride ldw),
 // for all rows, chunk by chunk through `scratch` (as above); a partial
 // rotation when nout < n.  upper/mixed as above (upper requires nout = ldw = n).
 int rmul_cols_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int64_t ldw, int nout,
-                     int out_col0, int upper, int mixed, double *scratch, hipStream_t s);
+                     int out_col0, int upper, int mixed, double *scratch, size_t scratch_elems, hipStream_t s);
 // resid[j] = || HX[:,j] - lam[j] X[:,j] ||_2 ; part: [nchunk x n]
 int resid_nchunk(int64_t nrows);
 void resid_launch(const double *X, int64_t ldx, const double *HX, int64_t ldh, const double *lam, int64_t nrows,

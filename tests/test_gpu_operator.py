@@ -60,6 +60,8 @@ def test_tile_variant_rejects_unknown():
     c, _ = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
     with pytest.raises(Exception):
         c.set_tile_variant(2)
+    with pytest.raises(Exception):
+        c.set_rr_residual(3)
     c.close()
 
 

@@ -74,18 +74,26 @@ def test_rayleigh_ritz_exact_on_rotated_eigenvectors():
     c.close()
 
 
-@pytest.mark.parametrize("ncols", [1, 2, 3, 24, 31, 32, 33, 63, 64, 65, 97, 129, 200])
-def test_rayleigh_ritz_matches_oracle(ncols):
+RR_COLS = [1, 2, 3, 24, 31, 32, 33, 63, 64, 65, 97, 129, 200]
+
+
+@pytest.mark.parametrize("ncols,mode", [(n, 0) for n in RR_COLS] + [(n, m) for n in (1, 33, 129) for m in (1, 2)])
+def test_rayleigh_ritz_matches_oracle(ncols, mode):
+    """mode: how Htilde of the rotated columns is formed (0 cost model,
+    1 rotating HX, 2 applying Htilde again); HX_out checked against the oracle."""
     prob = workload.PROBLEMS["small"]
     c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    c.set_rr_residual(mode)
     X = och.cholgs(workload.start_block(c.n_dof, ncols, 300 + ncols))
     ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
     Xr, HXr, D, res = och.rayleigh_ritz(ap, X)
     Xg = to_gpu(X)
-    ev, rs = c.rayleigh_ritz(Xg)
+    HX = to_gpu(np.zeros_like(X))
+    ev, rs = c.rayleigh_ritz(Xg, HX_out=HX)
     scale = max(1.0, np.max(np.abs(D)))
     np.testing.assert_allclose(ev, D, rtol=0, atol=1e-12 * scale)
     np.testing.assert_allclose(rs, res, rtol=1e-6, atol=1e-11 * scale)
+    assert np.max(np.abs(to_host(HX) - ap(to_host(Xg)))) < 1e-11 * scale
     # Ritz vectors up to sign (the projected spectrum of a random block is simple)
     G = to_host(Xg)
     sgn = np.sign(np.sum(G * Xr, axis=0))
@@ -134,10 +142,10 @@ def test_solve_box_closed_form_at_large_p6_shape_subset():
 
 
 def test_cholgs_and_rr_at_568_columns_across_row_chunks():
-    """568 columns (the large_p6 block) on 59,319 DoFs: more rows than one
-    row chunk of the rotation kernel, so the chunked path and its ragged last
-    chunk are both exercised."""
-    L, n_el, p = 20.0, 8, 5
+    """568 columns (the large_p6 block) on 262,144 DoFs: 1.49e8 elements, more
+    than the rotation kernel's 2^27-element scratch panel holds, so the chunked
+    path and its ragged last chunk are both exercised."""
+    L, n_el, p = 26.0, 13, 5
     wells = workload.draw_wells(8, L, 21, (1.0, 3.0), (0.5, 1.5))
     c, V = make_ctx(L, n_el, p, wells=wells)
     X = workload.start_block(c.n_dof, 568, 31)
@@ -172,12 +180,14 @@ def test_solve_precision_ladder_reaches_fp64_accuracy(ladder, mixed):
     c.close()
 
 
-@pytest.mark.parametrize("ncols,n_fr", [(24, 4), (97, 15), (200, 30), (200, 200), (65, 1)])
-def test_rayleigh_ritz_split_fp64_equals_full(ncols, n_fr):
+@pytest.mark.parametrize("ncols,n_fr,mode", [(24, 4, 0), (97, 15, 0), (200, 30, 0), (200, 200, 0), (65, 1, 0),
+                                             (97, 15, 1), (97, 15, 2), (200, 30, 1), (200, 30, 2)])
+def test_rayleigh_ritz_split_fp64_equals_full(ncols, n_fr, mode):
     """Spectrum splitting with an all-FP64 projection: the N_fr largest Ritz
     pairs of the full Rayleigh-Ritz; the first N_oc columns untouched."""
     prob = workload.PROBLEMS["small"]
     c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    c.set_rr_residual(mode)
     X = och.cholgs(workload.start_block(c.n_dof, ncols, 500 + ncols))
     ap = oracle_apply(prob.L, prob.n_el, prob.p, V)
     Xr, HXr, D, res = och.rayleigh_ritz(ap, X)
