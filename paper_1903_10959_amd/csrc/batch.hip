@@ -311,8 +311,8 @@ int subspace_steps(chfsi_batch *B, const std::vector<int> &ids, bool filtered) {
   std::vector<JacobiJob> jobs;
   for (int id : ids) jobs.push_back(rr_eigen_job(B->probs[id].c, B->probs[id].o.nblock));
   BCHK(B, B->jac_table.ensure(jacobi_table_bytes((int)jobs.size())));
-  BCHK(B, B->jac_norms.ensure(2 * jobs.size() * sizeof(double)));
-  B->jac_host.resize(2 * jobs.size());
+  BCHK(B, B->jac_norms.ensure(jacobi_norms_elems((int)jobs.size()) * sizeof(double)));
+  B->jac_host.resize(jacobi_norms_elems((int)jobs.size()));
   if (jacobi_eigh_batch(jobs.data(), (int)jobs.size(), 1e-14, 40, B->jac_table.p, B->jac_norms.as<double>(),
                         B->jac_host.data(), B->stream, nullptr) != 0)
     return bfail(B, CHFSI_ERR_HIP, "batch: Jacobi eigensolve failed");

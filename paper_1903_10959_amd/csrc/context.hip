@@ -531,7 +531,8 @@ int chfsi::ensure_small(chfsi_ctx *c, int n) {
   HIPCHK(c, c->diag0.ensure((size_t)n * sizeof(double)));
   HIPCHK(c, c->minratio.ensure((size_t)nb * sizeof(double)));
   HIPCHK(c, c->rscratch.ensure(rmul_scratch_elems(c->mesh.n_dof, n) * sizeof(double)));
-  if ((int)c->host_scratch.size() < nb + 16) c->host_scratch.resize(nb + 16);
+  const size_t hs = std::max((size_t)nb + 16, jacobi_norms_elems(1));
+  if (c->host_scratch.size() < hs) c->host_scratch.resize(hs);
   HIPCHK(c, c->gram_part.ensure(gram_part_elems(c->mesh.n_dof, n) * sizeof(double)));
   HIPCHK(c, c->resid_part.ensure((size_t)resid_nchunk(c->mesh.n_dof) * n * sizeof(double)));
   return 0;

@@ -128,14 +128,16 @@ size_t jacobi_work_elems(int n);
 // Many independent eigenproblems at once: every round launch covers all
 // problems still iterating, one host synchronisation per sweep checks them
 // all.  Job k: A (destroyed), work (jacobi_work_elems(n)), evals/Q as above.
-// table: device scratch of jacobi_table_bytes(njobs); norms: device
-// [2 njobs]; host_norms: host [2 njobs].
+// table: device scratch of jacobi_table_bytes(njobs); norms: device and
+// host_norms: host, jacobi_norms_elems(njobs) doubles each (jacobi_eigh:
+// host_scratch of jacobi_norms_elems(1)).
 struct JacobiJob {
   double *A;
   int n;
   double *work, *evals, *Q;
 };
 size_t jacobi_table_bytes(int njobs);
+size_t jacobi_norms_elems(int njobs);
 int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_sweeps, void *table, double *norms,
                       double *host_norms, hipStream_t s, int *sweeps_done);
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,

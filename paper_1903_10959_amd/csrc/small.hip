@@ -293,6 +293,7 @@ __device__ __forceinline__ void jrot(const double *A, int n, int p, int q, doubl
 // A block sweep (nbp - 1 block rounds) applies every plane rotation of a
 // scalar sweep, and more, in 3 (nbp - 1) launches instead of n - 1.
 static constexpr int JB = 32, J2 = 64;
+static constexpr int OFFP = 32;   // work-groups per problem in the off-norm
 
 // One problem of a batched block-Jacobi round: A (n x n) double buffered
 // (A[b]), V updated in place, R the current round's pair rotations
@@ -488,23 +489,29 @@ __global__ __launch_bounds__(256) void jacobi_apply_v_kernel(const JacProb *__re
 
 // out[2k] = sum of squares off the diagonal of problem k's current matrix,
 // out[2k+1] = on the diagonal (one work-group per problem)
-__global__ __launch_bounds__(1024) void offnorm_kernel(const JacProb *__restrict__ probs, double *__restrict__ out) {
-  __shared__ double so[1024], sd[1024];
-  const JacProb &J = probs[blockIdx.x];
+// Squared off-diagonal and diagonal Frobenius norms of each problem's A, as
+// OFFP partial sums per problem (work-group part takes rows part*4 + wave,
+// stepping by 4 OFFP); the host adds the partials in a fixed order.
+__global__ __launch_bounds__(256) void offnorm_kernel(const JacProb *__restrict__ probs, double *__restrict__ out) {
+  __shared__ double so[256], sd[256];
+  const int a = blockIdx.x / OFFP, part = blockIdx.x % OFFP;
+  const JacProb &J = probs[a];
   const double *A = J.A[J.par0];
   const int n = J.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double o = 0, d = 0;
-  const int64_t total = (int64_t)n * n;
-  for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int i = (int)(idx / n), jj = (int)(idx % n);
-    const double v = A[idx];
-    if (i == jj) d += v * v;
-    else o += v * v;
+  for (int i = part * 4 + wave; i < n; i += OFFP * 4) {
+    const double *row = A + (int64_t)i * n;
+    for (int j = lane; j < n; j += 64) {
+      const double v = row[j];
+      if (j == i) d += v * v;
+      else o += v * v;
+    }
   }
   so[threadIdx.x] = o;
   sd[threadIdx.x] = d;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       so[threadIdx.x] += so[threadIdx.x + w];
       sd[threadIdx.x] += sd[threadIdx.x + w];
@@ -545,8 +552,10 @@ static int jac_nbp(int n) {
 }
 
 // work: A's second buffer (n^2), V (n^2), the pair rotations
-// (nbp/2 x 64 x 64), a tail of 16 for the single-problem table and norms
-static constexpr int JTAIL = 16;
+// (nbp/2 x 64 x 64), a tail for the single-problem table (16 doubles) and
+// norms (jacobi_norms_elems(1))
+static constexpr int JTAIL = 16 + 2 * OFFP;
+size_t jacobi_norms_elems(int njobs) { return (size_t)2 * OFFP * (njobs > 0 ? njobs : 1); }
 size_t jacobi_work_elems(int n) {
   return (size_t)2 * n * n + (size_t)(jac_nbp(n) / 2) * J2 * J2 + JTAIL;
 }
@@ -587,8 +596,9 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
     if (act.empty()) break;
     if (hipMemcpyAsync(dtab, act.data(), act.size() * sizeof(JacProb), hipMemcpyHostToDevice, s) != hipSuccess)
       return -1;
-    hipLaunchKernelGGL(offnorm_kernel, dim3((unsigned)act.size()), dim3(1024), 0, s, dtab, norms);
-    if (hipMemcpyAsync(host_norms, norms, 2 * act.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    hipLaunchKernelGGL(offnorm_kernel, dim3((unsigned)(act.size() * OFFP)), dim3(256), 0, s, dtab, norms);
+    if (hipMemcpyAsync(host_norms, norms, 2 * OFFP * act.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
       return -1;
     if (hipStreamSynchronize(s) != hipSuccess) return -1;
     std::vector<JacProb> run;
@@ -596,7 +606,12 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
     int64_t n_inner = 0, n_tile = 0, n_panel = 0;
     for (size_t a = 0; a < act.size(); ++a) {
       const int k = ids[a];
-      const double off = host_norms[2 * a], tot = host_norms[2 * a] + host_norms[2 * a + 1];
+      double off = 0, dg = 0;
+      for (int q = 0; q < OFFP; ++q) {
+        off += host_norms[2 * (a * OFFP + q)];
+        dg += host_norms[2 * (a * OFFP + q) + 1];
+      }
+      const double tot = off + dg;
       bool done = off <= tol * tol * tot;
       if (prev_off[k] >= 0 && off >= prev_off[k] && off <= 1e-20 * tot) done = true;  // stagnated at rounding
       prev_off[k] = off;
@@ -639,12 +654,13 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
 
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
                 double *host_scratch, hipStream_t s, int *sweeps_done) {
-  // one problem through the batched driver: the table (one entry) and the two
-  // norms live in the tail of the work array
-  static_assert(sizeof(JacProb) <= (JTAIL - 2) * sizeof(double), "one table entry fits the work tail");
+  // one problem through the batched driver: the table (one entry) and the
+  // norm partials live in the tail of the work array; host_scratch holds at
+  // least jacobi_norms_elems(1) doubles
+  static_assert(sizeof(JacProb) <= 16 * sizeof(double), "one table entry fits the work tail");
   const JacobiJob job{A, n, work, evals, Q};
   double *tail = work + jacobi_work_elems(n) - JTAIL;
-  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + (JTAIL - 2), host_scratch, s, sweeps_done);
+  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + 16, host_scratch, s, sweeps_done);
 }
 
 __global__ void fill_kernel(double *X, int64_t n, double v) {
