@@ -2,8 +2,9 @@
 
 A plain, slow, FP64 CPU implementation (numpy/scipy) of what the GPU library
 computes, written from the paper's description of the spectral finite-element
-Kohn-Sham eigenproblem (Sec. 2.4, eq. hep) and of Chebyshev-filtered subspace
-iteration (Sec. 3.3 eq. chebFilter, Sec. 3.4 Alg. 3 CholGS, Sec. 3.5 RR).
+Kohn-Sham eigenproblem (Sec. 2.4, eq. hep), of Chebyshev-filtered subspace
+iteration (Sec. 3.3 eq. chebFilter, Sec. 3.4 Alg. 3 CholGS, Sec. 3.5 RR) and
+of the electron density (Sec. 3.5, Alg. 5).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It shares no code with the HIP path
@@ -18,6 +19,10 @@ Modules
 ``chfsi``  Chebyshev filter (paper's unscaled recursion and the normalised
            one), CholGS (FP64 and the paper's mixed variant), Rayleigh-Ritz,
            the subspace-iteration loop, dense and Lanczos eigensolves.
+``density`` Spectrum-splitting Rayleigh-Ritz (Alg. 4), Fermi-Dirac occupancy
+           and Fermi level, the nodal electron density by eq. elecDensSP and
+           by eq. elecDens, and the cell-level form of eq. elecDensSums
+           (Sec. 3.5, Alg. 5).
 
 Pinning status (what each function is checked against) is listed in the
 module docstrings.  Mixed-precision accuracy is *parity unpinned* by the paper
