@@ -282,6 +282,72 @@ def rr_split_compare(args, prob):
     ctx.close()
 
 
+def density_bench(args, prob):
+    """Electron density (Alg. 5) on the block: spectrum-splitting RR into a
+    separate X Q_fr (Alg. 4, mixed projection), the Fermi level, and the
+    nodal density kernel, timed with HIP events on the context's stream (the
+    torch current stream).  Roofline: HBM, algorithmic bytes per launch =
+    n_dof (8 (N_b + N_fr) + 16): read X and X Q_fr rows, M^-1/2, write rho."""
+    import numpy as np
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
+    ctx.set_potential(workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords()))
+    X = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device=dev)
+    ctx.orthonormalize(X)
+    ev0, _ = ctx.rayleigh_ritz(X)
+    # one filter pass, so the Ritz values (and mu) sit in the low spectrum
+    ctx.chebyshev_filter(X, prob.degree, float(ev0[-1]), ctx.upper_bound, float(ev0[0]),
+                         block_width=prob.block_width)
+    ctx.orthonormalize(X)
+    nb = prob.nblock
+    n_fr = max(1, int(round(0.15 * prob.nstates)))
+    n_oc = nb - n_fr
+    Xfr = torch.empty((prob.n_dof, n_fr), dtype=torch.float64, device=dev)
+    t_rr = []
+    for rep in range(args.steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        ev, _ = ctx.rayleigh_ritz_split(X, n_fr, mixed=True, Xfr=Xfr)
+        torch.cuda.synchronize()
+        if rep > 0:
+            t_rr.append(time.time() - t0)
+    sigma = 1.58e-3                                   # k_B T at 500 K
+    ne = 2 * (n_oc + 0.5 * n_fr)
+    t0 = time.perf_counter()
+    mu = P.fermi_level(ev, n_oc, ne, sigma)
+    t_mu = time.perf_counter() - t0
+    rho = torch.empty(prob.n_dof, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        ctx.density(X, Xfr, ev, mu, sigma, rho=rho)
+    reps = max(1, 10 * args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.density(X, Xfr, ev, mu, sigma, rho=rho)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = prob.n_dof * (8 * (nb + n_fr) + 16)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res = {"metric": "electron density (Alg. 5) HBM throughput", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": workload.fmt_problem(prob), "N_b": nb, "n_fr": n_fr, "sigma_Ha": sigma},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                        "traffic": None, "kernel": "density_kernel", "bytes_per_launch": nbytes,
+                        "avg_launch_ms": ms},
+           "ms": {"split_rr_out_of_place": 1e3 * float(np.median(t_rr)), "fermi_level": 1e3 * t_mu,
+                  "density": ms},
+           "mu_Ha": mu, "steps": args.steps}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,9 +359,9 @@ def main():
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=16)
-    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr"],
+    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density"],
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
-                         "rr: Rayleigh-Ritz full vs spectrum splitting")
+                         "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5)")
     ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
@@ -339,6 +405,8 @@ def main():
           file=sys.stderr, flush=True)
     if args.mode == "tts":
         return time_to_solution(args, prob, bw)
+    if args.mode == "density":
+        return density_bench(args, prob)
     if args.mode == "rr":
         return rr_split_compare(args, prob)
     ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)

@@ -140,13 +140,40 @@ int chfsi_rayleigh_ritz(chfsi_ctx *ctx, double *X, int64_t ld, int ncols,
  * (rows and columns >= N_oc, its start rounded down to a multiple of 64) in
  * FP64, every other block with FP32 inputs and products; mixed = 0: all FP64.
  * Hhat Q = Q D (FP64 Jacobi; all pairs are computed, the N_fr largest used);
- * X[:, N_oc:] <- X Q_fr, the partial rotation; the first N_oc columns are left
- * as they are (the paper keeps the fully occupied part unrotated).
+ * the partial rotation X Q_fr goes to Xfr (device [n_dof x ldfr], ldfr >=
+ * n_fr, caller-owned, must not overlap X; X is left unchanged, as Alg. 5
+ * needs both) or, with Xfr = NULL, over the trailing N_fr columns of X (the
+ * first N_oc columns are left as they are).
  * evals_fr, resid_fr: host [n_fr], ascending Ritz values of the N_fr largest
  * pairs and ||Htilde x_i - d_i x_i||_2 of the rotated columns.  Errors:
- * CHFSI_ERR_ARG for n_fr outside 1..ncols or null host arrays. */
+ * CHFSI_ERR_ARG for n_fr outside 1..ncols, null host arrays, ldfr < n_fr or
+ * an Xfr that overlaps X. */
 int chfsi_rayleigh_ritz_split(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int n_fr, int mixed,
-                              double *evals_fr, double *resid_fr);
+                              double *Xfr, int64_t ldfr, double *evals_fr, double *resid_fr);
+
+/* ---- Fermi energy (Alg. 5 step 1) ------------------------------------------
+ * The mu at which 2 (n_oc + sum_k f(evals_fr[k], mu)) = n_electrons, with the
+ * Fermi-Dirac occupancy f(e, mu) = 1 / (1 + exp((e - mu) / sigma)) of Sec. 2.1
+ * (sigma = k_B T in Hartree).  Pure host function (no context, no device):
+ * bisection on the monotone count to the last representable midpoint.
+ * Errors: CHFSI_ERR_ARG for null pointers, n_fr < 1, n_oc < 0, sigma <= 0,
+ * non-finite values, or n_electrons outside (2 n_oc, 2 (n_oc + n_fr)). */
+int chfsi_fermi_level(const double *evals_fr, int n_fr, int n_oc, double n_electrons, double sigma, double *mu);
+
+/* ---- electron density (Alg. 5 steps 2-3, eq. elecDensSP) -----------------
+ * With the collocated GLL quadrature the basis functions are the nodes'
+ * Lagrange polynomials, so the density at interior node j is
+ *   rho[j] = 2 M_jj^-1 ( sum_{i<ncols} X[j,i]^2
+ *                        + sum_{k<n_fr} (f(evals_fr[k], mu) - 1) Xfr[j,k]^2 ),
+ * X the orthonormal basis (Psi^o, all N = N_oc + N_fr columns, unrotated),
+ * Xfr = X Q_fr from chfsi_rayleigh_ritz_split (out of place), evals_fr its
+ * host Ritz values.  n_fr = 0 gives the fully occupied density (Xfr and
+ * evals_fr unused).  rho: device [n_dof], caller-owned; Dirichlet nodes carry
+ * no DoF and have zero density.  One wave per DoF row, HBM-bound.  Errors:
+ * CHFSI_ERR_ARG for bad block arguments, n_fr > 0 without Xfr/evals_fr or
+ * with ldfr < n_fr, sigma <= 0 when n_fr > 0, or a null rho. */
+int chfsi_density(chfsi_ctx *ctx, const double *X, int64_t ld, int ncols, const double *Xfr, int64_t ldfr,
+                  int n_fr, const double *evals_fr, double mu, double sigma, double *rho);
 
 /* ---- solve (Alg. 2 step 7 with the adaptive repeat of Sec. 3.3) ----------
  * X: device [n_dof x ld], ld >= nblock, holds the start (or warm-start) block

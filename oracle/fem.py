@@ -26,7 +26,9 @@ symmetric, PSD with the constants as its only kernel; map bijection,
 multiplicities and colouring; CSR assembly against the Kronecker-sum form and
 against a brute-force quadrature assembly written with general Lagrange
 evaluation; V=0 spectrum against sums of 1D eigenvalues and against the
-continuum particle-in-a-box values; the harmonic oscillator limit.
+continuum particle-in-a-box values; the harmonic oscillator limit.  The
+Kronecker-product diagonal mass (``mass_diag_kron``) against the assembled M
+(tests/test_oracle_density.py).
 """
 from __future__ import annotations
 
@@ -222,6 +224,25 @@ def assemble(L: float, n_el: int, p: int):
                       shape=(nd, nd)).tocsr()
     K.sum_duplicates()
     return K, M
+
+
+def mass_1d(L: float, n_el: int, p: int) -> np.ndarray:
+    """Diagonal 1D GLL mass on the n_el p - 1 interior nodes: sum over the 1D
+    elements of (h/2) w_a at each element's nodes."""
+    h = L / n_el
+    _, w = gll(p)
+    m = np.zeros(n_el * p + 1)
+    for e in range(n_el):
+        m[e * p:e * p + p + 1] += 0.5 * h * w
+    return m[1:-1]
+
+
+def mass_diag_kron(L: float, n_el: int, p: int) -> np.ndarray:
+    """The 3D diagonal GLL mass as the product m(I) m(J) m(K) of 1D masses
+    (the tensor-product rule), dof = I + n J + n^2 K; no assembly loop, so it
+    serves the full-size meshes."""
+    m = mass_1d(L, n_el, p)
+    return np.kron(m, np.kron(m, m))
 
 
 def htilde_csr(L: float, n_el: int, p: int, V: np.ndarray):

@@ -34,6 +34,17 @@ def footprint_bytes(n_el: int, p: int, nblock: int, block_width: int = 0, prec: 
     return int(_lib.load().chfsi_footprint_bytes(n_el, p, nblock, block_width, PRECISIONS[prec]))
 
 
+def fermi_level(evals_fr, n_oc: int, n_electrons: float, sigma: float) -> float:
+    """Fermi energy of Alg. 5 step 1: 2 (n_oc + sum_k f(e_k, mu)) = n_electrons."""
+    ev = np.ascontiguousarray(np.asarray(evals_fr, dtype=np.float64))
+    mu = C.c_double(0.0)
+    st = _lib.load().chfsi_fermi_level(ev.ctypes.data_as(C.c_void_p), int(ev.size), int(n_oc), float(n_electrons),
+                                       float(sigma), C.byref(mu))
+    if st != 0:
+        raise ChfsiError(st, "fermi_level", "n_electrons outside (2 n_oc, 2 (n_oc + n_fr)), or bad input")
+    return float(mu.value)
+
+
 def _prec(p) -> int:
     return PRECISIONS[p] if isinstance(p, str) else int(p)
 
@@ -319,16 +330,46 @@ class Context:
                                                   rs.ctypes.data_as(C.c_void_p), ph), "rayleigh_ritz")
         return ev, rs
 
-    def rayleigh_ritz_split(self, X, n_fr: int, mixed: bool = True):
-        """Spectrum-splitting Rayleigh-Ritz: Ritz values and residuals of the n_fr
-        largest pairs; rotates only the trailing n_fr columns of X."""
+    def rayleigh_ritz_split(self, X, n_fr: int, mixed: bool = True, Xfr=None):
+        """Spectrum-splitting Rayleigh-Ritz (Alg. 4): Ritz values and residuals of
+        the n_fr largest pairs.  The rotated vectors X Q_fr go to Xfr (a float64
+        CUDA tensor [n_dof, >= n_fr], X left unchanged) or, with Xfr None, over
+        the trailing n_fr columns of X."""
         px, ld, n = self._block(X)
+        pf, ldf = C.c_void_p(0), 0
+        if Xfr is not None:
+            pf, ldf, nf = self._block(Xfr)
+            if nf < n_fr:
+                raise ValueError("Xfr needs at least n_fr columns")
         ev = np.empty(int(n_fr))
         rs = np.empty(int(n_fr))
-        self._check(self._lib.chfsi_rayleigh_ritz_split(self._h, px, ld, n, int(n_fr), 1 if mixed else 0,
+        self._check(self._lib.chfsi_rayleigh_ritz_split(self._h, px, ld, n, int(n_fr), 1 if mixed else 0, pf, ldf,
                                                         ev.ctypes.data_as(C.c_void_p), rs.ctypes.data_as(C.c_void_p)),
                     "rayleigh_ritz_split")
         return ev, rs
+
+    def density(self, X, Xfr=None, evals_fr=None, mu: float = 0.0, sigma: float = 0.0, rho=None):
+        """Nodal electron density (Alg. 5, eq. elecDensSP) from the orthonormal
+        basis X and the rotated fractionally occupied vectors Xfr with Ritz
+        values evals_fr; returns rho (float64 CUDA tensor [n_dof])."""
+        import torch
+
+        px, ld, n = self._block(X)
+        pf, ldf, nfr = C.c_void_p(0), 0, 0
+        ev = None
+        if Xfr is not None:
+            pf, ldf, nfr = self._block(Xfr)
+            ev = np.ascontiguousarray(np.asarray(evals_fr, dtype=np.float64))
+            if ev.shape != (nfr,):
+                raise ValueError("evals_fr must have one value per column of Xfr")
+        if rho is None:
+            rho = torch.empty(self.n_dof, dtype=torch.float64, device=X.device)
+        if rho.dtype != torch.float64 or not rho.is_cuda or rho.numel() != self.n_dof or not rho.is_contiguous():
+            raise TypeError("rho must be a contiguous float64 CUDA tensor of n_dof values")
+        self._check(self._lib.chfsi_density(self._h, px, ld, n, pf, ldf, nfr,
+                                            ev.ctypes.data_as(C.c_void_p) if ev is not None else None,
+                                            float(mu), float(sigma), C.c_void_p(rho.data_ptr())), "density")
+        return rho
 
     # ---- solve -----------------------------------------------------------
     def solve(self, X, nstates: int, degree: int, tol: float, max_iter: int = 200, block_width: int = 0,

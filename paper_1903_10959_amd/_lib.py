@@ -56,7 +56,9 @@ SIGNATURES = {
     "chfsi_footprint_bytes": (C.c_size_t, [_int, _int, _int, _int, _int]),
     "chfsi_status_string": (C.c_char_p, [_int]),
     "chfsi_last_error": (C.c_char_p, [_vp]),
-    "chfsi_rayleigh_ritz_split": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp, _vp]),
+    "chfsi_rayleigh_ritz_split": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp, _i64, _vp, _vp]),
+    "chfsi_fermi_level": (_int, [_vp, _int, _int, _dbl, _dbl, _vp]),
+    "chfsi_density": (_int, [_vp, _vp, _i64, _int, _vp, _i64, _int, _vp, _dbl, _dbl, _vp]),
     "chfsi_set_timing": (_int, [_vp, _int]),
     "chfsi_set_tile_variant": (_int, [_vp, _int]),
     "chfsi_set_rr_residual": (_int, [_vp, _int]),

@@ -86,7 +86,7 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32, &c->Kbh, &c->Kbl,
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
                    &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
-                   &c->diag0, &c->minratio, &c->rscratch};
+                   &c->diag0, &c->minratio, &c->rscratch, &c->occ_d};
   for (DevBuf *b : all) b->release();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -630,18 +630,21 @@ static bool rr_reapply(const chfsi_ctx *c, int ncols) {
   return 1.4 * cells * M.np * M.np < (double)M.n_dof * ncols;
 }
 
-// Rotates the columns [col0, col0 + nout) of X (and of HX) by W (ncols x nout,
-// row stride ncols); HX then holds Htilde X on those columns, by rotation or by
-// a fresh application.
+// Rotates X by W (ncols x nout, row stride ncols): in place into the columns
+// [col0, col0 + nout) of X, or into Xout (ldo) when given, leaving X as it is.
+// HX[:, col0 : col0 + nout] then holds Htilde times the rotated columns, by
+// rotation or by a fresh application.
 static int rr_rotate(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, const double *W,
-                     int nout, int col0) {
+                     int nout, int col0, double *Xout = nullptr, int64_t ldo = 0) {
   const int64_t nd = c->mesh.n_dof;
   double *scr = c->rscratch.as<double>();
   const size_t se = c->rscratch.bytes / sizeof(double);
-  if (rmul_cols_launch(X, ld, nd, ncols, W, ncols, nout, col0, 0, 0, scr, se, c->stream) != 0)
-    return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
+  const int st = Xout ? rmul_out_launch(X, ld, nd, ncols, W, ncols, nout, Xout, ldo, c->stream)
+                      : rmul_cols_launch(X, ld, nd, ncols, W, ncols, nout, col0, 0, 0, scr, se, c->stream);
+  if (st != 0) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
   if (rr_reapply(c, ncols))
-    return cheb_step_t<double>(c, X + col0, ld, nullptr, 0, HX + col0, ldh, nout, 1.0, 0.0, 0.0);
+    return cheb_step_t<double>(c, Xout ? Xout : X + col0, Xout ? ldo : ld, nullptr, 0, HX + col0, ldh, nout, 1.0,
+                               0.0, 0.0);
   if (rmul_cols_launch(HX, ldh, nd, ncols, W, ncols, nout, col0, 0, 0, scr, se, c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz: block too wide for the row-panel kernel");
   return 0;
@@ -693,10 +696,16 @@ extern "C" int chfsi_rayleigh_ritz(chfsi_ctx *c, double *X, int64_t ld, int ncol
 // projected Hamiltonian
 // ---------------------------------------------------------------------------
 extern "C" int chfsi_rayleigh_ritz_split(chfsi_ctx *c, double *X, int64_t ld, int ncols, int n_fr, int mixed,
-                                         double *evals_fr, double *resid_fr) {
+                                         double *Xfr, int64_t ldfr, double *evals_fr, double *resid_fr) {
   if (int r = check_block(c, X, ld, ncols)) return r;
   if (n_fr < 1 || n_fr > ncols) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: n_fr must be in 1..ncols");
   if (!evals_fr || !resid_fr) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: evals/resid must be host arrays");
+  if (Xfr) {
+    if (ldfr < n_fr) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: ldfr < n_fr");
+    const double *xe = X + (c->mesh.n_dof - 1) * ld + ncols;
+    const double *fe = Xfr + (c->mesh.n_dof - 1) * ldfr + n_fr;
+    if (Xfr < xe && X < fe) return fail(c, CHFSI_ERR_ARG, "rayleigh_ritz_split: Xfr overlaps X");
+  }
   if (int r = ensure_small(c, ncols)) return r;
   const int64_t nd = c->mesh.n_dof;
   HIPCHK(c, c->HX.ensure((size_t)nd * ncols * sizeof(double)));
@@ -715,14 +724,79 @@ extern "C" int chfsi_rayleigh_ritz_split(chfsi_ctx *c, double *X, int64_t ld, in
   if (jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, 40, c->host_scratch.data(), c->stream,
                   nullptr) != 0)
     return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
-  // step 3: partial rotation of the trailing N_fr columns (and Htilde on
-  // them, for their residuals); the first N_oc columns stay as they are
-  if (int r = rr_rotate(c, X, ld, ncols, HX, ldh, job.Q + n_oc, n_fr, n_oc)) return r;
-  resid_launch(X + n_oc, ld, HX + n_oc, ldh, job.evals + n_oc, nd, n_fr, c->resid_part.as<double>(),
-               c->resid_d.as<double>(), c->stream);
+  // step 3: partial rotation X Q_fr, into Xfr or over the trailing N_fr
+  // columns of X (and Htilde on the rotated columns, for their residuals)
+  if (int r = rr_rotate(c, X, ld, ncols, HX, ldh, job.Q + n_oc, n_fr, n_oc, Xfr, ldfr)) return r;
+  resid_launch(Xfr ? Xfr : X + n_oc, Xfr ? ldfr : ld, HX + n_oc, ldh, job.evals + n_oc, nd, n_fr,
+               c->resid_part.as<double>(), c->resid_d.as<double>(), c->stream);
   HIPCHK(c, hipMemcpyAsync(evals_fr, job.evals + n_oc, n_fr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(resid_fr, c->resid_d.p, n_fr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Electron density (Alg. 5)
+// ---------------------------------------------------------------------------
+// Fermi-Dirac occupancy (Sec. 2.1); exp overflows to +inf for large
+// arguments, giving 0, which is the limit.
+static double fermi_dirac(double e, double mu, double sigma) { return 1.0 / (1.0 + std::exp((e - mu) / sigma)); }
+
+static double electron_count(const double *e, int n, int n_oc, double mu, double sigma) {
+  double s = 0;
+  for (int k = 0; k < n; ++k) s += fermi_dirac(e[k], mu, sigma);
+  return 2.0 * (n_oc + s);
+}
+
+extern "C" int chfsi_fermi_level(const double *evals_fr, int n_fr, int n_oc, double n_electrons, double sigma,
+                                 double *mu) {
+  if (!evals_fr || !mu || n_fr < 1 || n_oc < 0 || !(sigma > 0) || !std::isfinite(sigma)) return CHFSI_ERR_ARG;
+  if (!(n_electrons > 2.0 * n_oc && n_electrons < 2.0 * (n_oc + n_fr))) return CHFSI_ERR_ARG;
+  double lo = evals_fr[0], hi = evals_fr[0];
+  for (int k = 0; k < n_fr; ++k) {
+    if (!std::isfinite(evals_fr[k])) return CHFSI_ERR_ARG;
+    lo = std::min(lo, evals_fr[k]);
+    hi = std::max(hi, evals_fr[k]);
+  }
+  // bracket: the count rises monotonically in mu from 2 n_oc to 2 (n_oc + n_fr)
+  for (double step = 40.0 * sigma + (hi - lo); electron_count(evals_fr, n_fr, n_oc, lo, sigma) >= n_electrons;
+       step *= 2)
+    lo -= step;
+  for (double step = 40.0 * sigma + (hi - lo); electron_count(evals_fr, n_fr, n_oc, hi, sigma) <= n_electrons;
+       step *= 2)
+    hi += step;
+  // bisection to the last representable midpoint
+  for (int it = 0; it < 2000; ++it) {
+    const double m = lo + 0.5 * (hi - lo);
+    if (m <= lo || m >= hi) break;
+    if (electron_count(evals_fr, n_fr, n_oc, m, sigma) < n_electrons) lo = m;
+    else hi = m;
+  }
+  *mu = lo + 0.5 * (hi - lo);
+  return 0;
+}
+
+extern "C" int chfsi_density(chfsi_ctx *c, const double *X, int64_t ld, int ncols, const double *Xfr, int64_t ldfr,
+                             int n_fr, const double *evals_fr, double mu, double sigma, double *rho) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (n_fr < 0 || (n_fr > 0 && (!Xfr || ldfr < n_fr || !evals_fr)))
+    return fail(c, CHFSI_ERR_ARG, "density: Xfr, ldfr >= n_fr and evals_fr are needed when n_fr > 0");
+  if (!rho) return fail(c, CHFSI_ERR_ARG, "density: rho must be a device array of n_dof");
+  if (n_fr > 0 && !(sigma > 0)) return fail(c, CHFSI_ERR_ARG, "density: sigma must be positive");
+  const int64_t nd = c->mesh.n_dof;
+  double *w = nullptr;
+  if (n_fr > 0) {
+    HIPCHK(c, c->occ_d.ensure((size_t)n_fr * sizeof(double)));
+    if (c->host_scratch.size() < (size_t)n_fr) c->host_scratch.resize(n_fr);
+    for (int k = 0; k < n_fr; ++k) c->host_scratch[k] = fermi_dirac(evals_fr[k], mu, sigma) - 1.0;
+    w = c->occ_d.as<double>();
+    HIPCHK(c, hipMemcpyAsync(w, c->host_scratch.data(), n_fr * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // the host staging array is reused by later calls
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  density_launch(X, ld, ncols, Xfr, ldfr, n_fr, w, c->minv64.as<double>(), nd, rho, c->stream);
   HIPCHK(c, hipGetLastError());
   return 0;
 }

@@ -54,6 +54,7 @@ struct chfsi_ctx {
   int rr_residual = 0;    // Ritz residuals: 0 cost model, 1 rotate HX, 2 apply Htilde again
   // workspaces
   chfsi::DevBuf fbuf[3];      // filter recursion buffers
+  chfsi::DevBuf occ_d;    // density: fr occupancy weights
   chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
       rscratch;
   std::vector<double> host_scratch = std::vector<double>(16);

@@ -541,6 +541,100 @@ int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, in
   return rmul_cols_launch(X, ld, nrows, n, W, n, n, 0, upper, mixed, scratch, scratch_elems, s);
 }
 
+int rmul_out_launch(const double *X, int64_t ld, int64_t nrows, int n, const double *W, int64_t ldw, int nout,
+                    double *C, int64_t ldc, hipStream_t s) {
+  if (n <= 0 || nout <= 0 || nrows <= 0) return 0;
+  const bool v16 = ld % 2 == 0 && n % 2 == 0 && ldw % 2 == 0 && nout % 2 == 0 && ((uintptr_t)X % 16) == 0 &&
+                   ((uintptr_t)W % 16) == 0;
+  const int nt = (nout + NTL - 1) / NTL;
+  const int64_t mts = (nrows + MT - 1) / MT;
+  if (mts * nt > INT32_MAX) return -1;
+  const dim3 grid((unsigned)(mts * nt)), block(256);
+  if (v16) hipLaunchKernelGGL((rmul_gemm_kernel<false, 2>), grid, block, 0, s, X, ld, 0, nrows, n, W, ldw, nout, 0, C, ldc);
+  else hipLaunchKernelGGL((rmul_gemm_kernel<false, 1>), grid, block, 0, s, X, ld, 0, nrows, n, W, ldw, nout, 0, C, ldc);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Nodal electron density (Alg. 5, eq. elecDensSP with the collocated GLL
+// rule): rho_j = 2 minv_j^2 (sum_i X[j,i]^2 + sum_k w_k Xfr[j,k]^2), w_k =
+// f(eps_k, mu) - 1.  One wave per DoF row (a row is contiguous in the
+// DoF-major layout, so a wave's loads are coalesced), lanes over columns with
+// 16-byte loads where the layout allows, a fixed shuffle tree for the sum.
+// HBM-bound: 8 (ncols + nfr) + 16 bytes per DoF.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <bool V2, bool F2>
+__global__ __launch_bounds__(256) void density_kernel(const double *__restrict__ X, int64_t ld, int ncols,
+                                                      const double *__restrict__ Xfr, int64_t ldfr, int nfr,
+                                                      const double *__restrict__ w, const double *__restrict__ minv,
+                                                      int64_t nrows, double *__restrict__ rho) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t row = wid; row < nrows; row += stride) {
+    const double *xr = X + row * ld;
+    double s0 = 0, s1 = 0;
+    if (V2) {
+      // two 16-byte loads per lane per step (a deeper unroll measured slower)
+      int c = 2 * lane;
+      for (; c + 128 < ncols; c += 256) {
+        const d2 a = *reinterpret_cast<const d2 *>(xr + c);
+        const d2 b = *reinterpret_cast<const d2 *>(xr + c + 128);
+        s0 += a[0] * a[0] + a[1] * a[1];
+        s1 += b[0] * b[0] + b[1] * b[1];
+      }
+      if (c < ncols) {
+        const d2 a = *reinterpret_cast<const d2 *>(xr + c);
+        s0 += a[0] * a[0] + a[1] * a[1];
+      }
+    } else {
+      for (int c = lane; c < ncols; c += 64) {
+        const double v = xr[c];
+        s0 += v * v;
+      }
+    }
+    const double *fr = Xfr + row * ldfr;
+    if (F2) {
+      for (int c = 2 * lane; c < nfr; c += 128) {
+        const d2 v = *reinterpret_cast<const d2 *>(fr + c);
+        const d2 wk = *reinterpret_cast<const d2 *>(w + c);
+        s1 += wk[0] * (v[0] * v[0]) + wk[1] * (v[1] * v[1]);
+      }
+    } else {
+      for (int c = lane; c < nfr; c += 64) {
+        const double v = fr[c];
+        s1 += w[c] * (v * v);
+      }
+    }
+    const double tot = wave_sum(s0 + s1);
+    if (lane == 0) {
+      const double m = minv[row];
+      rho[row] = 2.0 * (m * m) * tot;
+    }
+  }
+}
+
+void density_launch(const double *X, int64_t ld, int ncols, const double *Xfr, int64_t ldfr, int nfr,
+                    const double *w, const double *minv, int64_t nrows, double *rho, hipStream_t s) {
+  if (nrows <= 0) return;
+  int64_t blocks = (nrows + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  const dim3 g((unsigned)blocks), b(256);
+  const bool v2 = ld % 2 == 0 && ncols % 2 == 0 && ((uintptr_t)X % 16) == 0;
+  const bool f2 = nfr > 0 && ldfr % 2 == 0 && nfr % 2 == 0 && ((uintptr_t)Xfr % 16) == 0 && ((uintptr_t)w % 16) == 0;
+  if (v2 && f2) hipLaunchKernelGGL((density_kernel<true, true>), g, b, 0, s, X, ld, ncols, Xfr, ldfr, nfr, w, minv, nrows, rho);
+  else if (v2) hipLaunchKernelGGL((density_kernel<true, false>), g, b, 0, s, X, ld, ncols, Xfr, ldfr, nfr, w, minv, nrows, rho);
+  else if (f2) hipLaunchKernelGGL((density_kernel<false, true>), g, b, 0, s, X, ld, ncols, Xfr, ldfr, nfr, w, minv, nrows, rho);
+  else hipLaunchKernelGGL((density_kernel<false, false>), g, b, 0, s, X, ld, ncols, Xfr, ldfr, nfr, w, minv, nrows, rho);
+}
+
 // ---------------------------------------------------------------------------
 // Residual column norms
 // ---------------------------------------------------------------------------

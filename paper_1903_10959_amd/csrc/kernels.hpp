@@ -106,6 +106,14 @@ int rmul_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, in
 // rotation when nout < n.  upper/mixed as above (upper requires nout = ldw = n).
 int rmul_cols_launch(double *X, int64_t ld, int64_t nrows, int n, const double *W, int64_t ldw, int nout,
                      int out_col0, int upper, int mixed, double *scratch, size_t scratch_elems, hipStream_t s);
+// C[r, 0:nout] = X[r, 0:n] W[0:n, 0:nout] for all rows, out of place (C must
+// not overlap X); one launch.  Returns -1 when the grid would not fit.
+int rmul_out_launch(const double *X, int64_t ld, int64_t nrows, int n, const double *W, int64_t ldw, int nout,
+                    double *C, int64_t ldc, hipStream_t s);
+// rho[j] = 2 minv[j]^2 (sum_{i<ncols} X[j,i]^2 + sum_{k<nfr} w[k] Xfr[j,k]^2),
+// j < nrows; w on the device.
+void density_launch(const double *X, int64_t ld, int ncols, const double *Xfr, int64_t ldfr, int nfr,
+                    const double *w, const double *minv, int64_t nrows, double *rho, hipStream_t s);
 // resid[j] = || HX[:,j] - lam[j] X[:,j] ||_2 ; part: [nchunk x n]
 int resid_nchunk(int64_t nrows);
 void resid_launch(const double *X, int64_t ldx, const double *HX, int64_t ldh, const double *lam, int64_t nrows,

@@ -55,3 +55,35 @@ def test_residual_certificate_full_size_large_p6():
     del X
     torch.cuda.empty_cache()
     c.close()
+
+
+def test_density_full_size_large_p5():
+    """Spectrum-splitting RR (out of place, N_fr = 15 % of N) and the density
+    on the full large_p5 block: the particle count over all 4.0M nodes, and
+    sampled nodes recomputed on the CPU from the GPU's own rows."""
+    import torch
+    import paper_1903_10959_amd as P
+    from oracle import density as ode
+    prob = workload.PROBLEMS["large_p5"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = workload.start_block_device(prob.n_dof, prob.nblock, prob.x0_seed, device="cuda:0")
+    c.orthonormalize(X)
+    n_fr = int(round(0.15 * prob.nstates))
+    n_oc = prob.nblock - n_fr
+    Xfr = torch.empty((prob.n_dof, n_fr), dtype=torch.float64, device="cuda:0")
+    ev, _ = c.rayleigh_ritz_split(X, n_fr, mixed=True, Xfr=Xfr)
+    ne = 2 * (n_oc + 0.5 * n_fr)
+    sigma = 1.58e-3                                  # k_B T at 500 K, in Ha
+    mu = P.fermi_level(ev, n_oc, ne, sigma)
+    rho = c.density(X, Xfr, ev, mu, sigma)
+    M = torch.from_numpy(fem.mass_diag_kron(prob.L, prob.n_el, prob.p)).to("cuda:0")
+    count = float(torch.sum(M * rho))
+    assert abs(count - ne) < 1e-9 * ne, (count, ne)
+    rows = np.array([0, 1, 12345, prob.n_dof // 2, prob.n_dof - 1])
+    idx = torch.from_numpy(rows).to("cuda:0")
+    minv = 1.0 / np.sqrt(M[idx].cpu().numpy())
+    r_cpu = ode.density_split(X[idx].cpu().numpy(), Xfr[idx].cpu().numpy(), ev, mu, sigma, minv)
+    np.testing.assert_allclose(rho[idx].cpu().numpy(), r_cpu, rtol=1e-13, atol=0)
+    del X, Xfr, rho, M
+    torch.cuda.empty_cache()
+    c.close()

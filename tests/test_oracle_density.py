@@ -142,3 +142,9 @@ def test_box_ground_state_density_is_the_product_of_1d_densities():
     expect = np.kron(g, np.kron(g, g))             # dof = I + n J + n^2 K
     np.testing.assert_allclose(rho, expect, rtol=1e-9, atol=1e-12 * np.max(expect))
     np.testing.assert_allclose(M, np.kron(m1, np.kron(m1, m1)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("L,n_el,p", [(9.0, 3, 4), (6.0, 2, 3), (10.0, 4, 5)])
+def test_kron_mass_equals_assembled_mass(L, n_el, p):
+    _, M = fem.assemble(L, n_el, p)
+    np.testing.assert_allclose(fem.mass_diag_kron(L, n_el, p), M, rtol=1e-14)
