@@ -23,6 +23,10 @@ Modules
            and Fermi level, the nodal electron density by eq. elecDensSP and
            by eq. elecDens, and the cell-level form of eq. elecDensSums
            (Sec. 3.5, Alg. 5).
+``kpoint`` The periodic Bloch operator at a k-point (Sec. 2.2 eq.
+           ksproblemPer): periodic numbering, the GLL first-derivative cell
+           matrices, the complex Hermitian standard-form CSR and its
+           Kronecker-sum apply.
 
 Pinning status (what each function is checked against) is listed in the
 module docstrings.  Mixed-precision accuracy is *parity unpinned* by the paper
