@@ -348,6 +348,52 @@ def density_bench(args, prob):
     ctx.close()
 
 
+def kpoint_bench(args, prob):
+    """Complex Bloch operator (Sec. 2.2 eq. ksproblemPer) on the periodic cell
+    with the workload's element size and degree: Y = Htilde_k X for a complex
+    block of 64 vectors (one filter block of 128 real columns), timed with HIP
+    events on the context's stream.  Roofline: FP64 MFMA, algorithmic flops =
+    8 n_loc^2 per cell per complex vector (A Xr + B Xi and A Xi - B Xr)."""
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p, periodic=True)
+    ctx.set_potential(workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords()))
+    k = (0.05, 0.11, -0.08)
+    ctx.set_kpoint(k)
+    nc = 64
+    g = torch.Generator(device=dev).manual_seed(prob.x0_seed)
+    X = torch.randn((ctx.n_dof, nc), dtype=torch.complex128, device=dev, generator=g)
+    Y = torch.empty_like(X)
+    for _ in range(max(1, args.warmup)):
+        ctx.apply_complex(X, Y)
+    reps = max(1, 10 * args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.apply_complex(X, Y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 8.0 * ctx.n_loc ** 2 * ctx.n_cells * nc
+    tf = flops / (ms * 1e-3) / 1e12
+    dv = ctx.n_dof * nc / (ms * 1e-3)
+    res = {"metric": "complex Bloch operator Htilde_k X DoF-vecs/s (periodic cell, FP64)", "value": dv,
+           "unit": "complex DoF-vecs/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+           "data": "synthetic", "dtype": "f64 (complex128)",
+           "config": {"workload": f"periodic [0,{prob.L})^3, {prob.n_el}^3 cells, p={prob.p}, {ctx.n_dof} DoFs, "
+                                  f"k={list(k)}, {nc} complex vectors", "steps": args.steps},
+           "roofline": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6,
+                        "traffic": None, "kernel": "hx_cells_cplx_kernel", "avg_apply_ms": ms,
+                        "flop_per_cell_complex_vec": 8 * ctx.n_loc ** 2}}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,9 +405,10 @@ def main():
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=16)
-    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density"],
+    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density", "kpoint"],
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
-                         "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5)")
+                         "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5); "
+                         "kpoint: complex Bloch operator on the periodic cell")
     ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
@@ -407,6 +454,8 @@ def main():
         return time_to_solution(args, prob, bw)
     if args.mode == "density":
         return density_bench(args, prob)
+    if args.mode == "kpoint":
+        return kpoint_bench(args, prob)
     if args.mode == "rr":
         return rr_split_compare(args, prob)
     ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)

@@ -151,6 +151,33 @@ int chfsi_rayleigh_ritz(chfsi_ctx *ctx, double *X, int64_t ld, int ncols,
 int chfsi_rayleigh_ritz_split(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int n_fr, int mixed,
                               double *Xfr, int64_t ldfr, double *evals_fr, double *resid_fr);
 
+/* ---- periodic cell and k-points (Sec. 2.2, eq. ksproblemPer) ------------
+ * chfsi_set_mesh_periodic: as chfsi_set_mesh on the periodic cell [0, L)^3:
+ * node index I = (ex p + a) mod (n_el p), so n = n_el p unknowns per
+ * direction and n_dof = (n_el p)^3, no Dirichlet nodes; n_el must be even
+ * (>= 2) so that the 8-colour parity rule separates cells that share a node
+ * across the wrap.  The real operations (apply, filter, orthonormalize,
+ * rayleighRitz, solve) then act on the k = 0 (Gamma point) operator.
+ * Errors: CHFSI_ERR_ARG for odd n_el or the set_mesh conditions. */
+int chfsi_set_mesh_periodic(chfsi_ctx *ctx, double L, int n_el, int p);
+
+/* chfsi_set_kpoint: the Bloch wave vector k (1/bohr) of the complex operator
+ * Htilde_k = M^-1/2 (K - i k.G) M^-1/2 + diag(V + |k|^2/2), G_d the GLL
+ * first-derivative matrices int N_j d_d N_l (exactly antisymmetric after the
+ * periodic assembly, so Htilde_k is Hermitian).  k = 0 after set_mesh_periodic.
+ * Errors: CHFSI_ERR_STATE without a periodic mesh, CHFSI_ERR_ARG for
+ * non-finite k. */
+int chfsi_set_kpoint(chfsi_ctx *ctx, double kx, double ky, double kz);
+
+/* chfsi_apply_complex: Y = Htilde_k X for complex blocks (interleaved re, im
+ * FP64 pairs, i.e. complex128), DoF-major: element (dof i, column j) at
+ * X[i*ld + j], ld and ncols in complex elements (ld >= ncols).  X and Y are
+ * caller-owned device arrays that must not overlap.  The cell products run on
+ * FP64 MFMA as one real contraction of length 2 n_loc per output (A on the
+ * columns, B on the swapped (re, im) pairs).  Errors: CHFSI_ERR_STATE without
+ * a periodic mesh and potential, CHFSI_ERR_ARG for bad block arguments. */
+int chfsi_apply_complex(chfsi_ctx *ctx, const void *X, void *Y, int64_t ld, int ncols);
+
 /* ---- Fermi energy (Alg. 5 step 1) ------------------------------------------
  * The mu at which 2 (n_oc + sum_k f(evals_fr[k], mu)) = n_electrons, with the
  * Fermi-Dirac occupancy f(e, mu) = 1 / (1 + exp((e - mu) / sigma)) of Sec. 2.1

@@ -220,8 +220,13 @@ class Context:
         self.close()
 
     # ---- setMesh ---------------------------------------------------------
-    def set_mesh(self, L: float, n_el: int, p: int):
-        self._check(self._lib.chfsi_set_mesh(self._h, float(L), int(n_el), int(p)), "set_mesh")
+    def set_mesh(self, L: float, n_el: int, p: int, periodic: bool = False):
+        """Dirichlet cube [0, L]^3 (default) or the periodic cell [0, L)^3 (n_el even)."""
+        if periodic:
+            self._check(self._lib.chfsi_set_mesh_periodic(self._h, float(L), int(n_el), int(p)), "set_mesh_periodic")
+        else:
+            self._check(self._lib.chfsi_set_mesh(self._h, float(L), int(n_el), int(p)), "set_mesh")
+        self.periodic = bool(periodic)
         nd, nc, nl = C.c_int64(), C.c_int64(), C.c_int()
         self._check(self._lib.chfsi_get_sizes(self._h, C.byref(nd), C.byref(nc), C.byref(nl)), "get_sizes")
         self.n_dof, self.n_cells, self.n_loc = nd.value, nc.value, nl.value
@@ -287,6 +292,28 @@ class Context:
         if ldy != ld or ny != n:
             raise ValueError("X and Y must have the same shape and row stride")
         self._check(self._lib.chfsi_apply(self._h, px, py, ld, n, _prec(prec)), "apply")
+        return Y
+
+    def set_kpoint(self, k):
+        """Bloch wave vector (kx, ky, kz) of the complex operator (periodic mesh)."""
+        kx, ky, kz = (float(v) for v in k)
+        self._check(self._lib.chfsi_set_kpoint(self._h, kx, ky, kz), "set_kpoint")
+        return self
+
+    def apply_complex(self, X, Y=None):
+        """Y = Htilde_k X for a complex128 CUDA tensor [n_dof, ncols] (periodic mesh)."""
+        import torch
+
+        if not isinstance(X, torch.Tensor) or X.dtype != torch.complex128 or not X.is_cuda or X.dim() != 2:
+            raise TypeError("expected a 2-D complex128 CUDA tensor [n_dof, ncols]")
+        if X.shape[1] > 1 and X.stride(1) != 1:
+            raise ValueError("columns must be contiguous (stride(1) == 1)")
+        if Y is None:
+            Y = torch.empty_strided(tuple(X.shape), tuple(X.stride()), dtype=X.dtype, device=X.device)
+        if Y.dtype != torch.complex128 or tuple(Y.shape) != tuple(X.shape) or Y.stride() != X.stride():
+            raise ValueError("Y must match X in shape, dtype and strides")
+        self._check(self._lib.chfsi_apply_complex(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                                  int(X.stride(0)), int(X.shape[1])), "apply_complex")
         return Y
 
     def cheb_step(self, X, Xprev, Y, s1: float, s2: float, shift: float):

@@ -58,6 +58,9 @@ SIGNATURES = {
     "chfsi_last_error": (C.c_char_p, [_vp]),
     "chfsi_rayleigh_ritz_split": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp, _i64, _vp, _vp]),
     "chfsi_fermi_level": (_int, [_vp, _int, _int, _dbl, _dbl, _vp]),
+    "chfsi_set_mesh_periodic": (_int, [_vp, _dbl, _int, _int]),
+    "chfsi_set_kpoint": (_int, [_vp, _dbl, _dbl, _dbl]),
+    "chfsi_apply_complex": (_int, [_vp, _vp, _vp, _i64, _int]),
     "chfsi_density": (_int, [_vp, _vp, _i64, _int, _vp, _i64, _int, _vp, _dbl, _dbl, _vp]),
     "chfsi_set_timing": (_int, [_vp, _int]),
     "chfsi_set_tile_variant": (_int, [_vp, _int]),

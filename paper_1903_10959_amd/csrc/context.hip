@@ -86,7 +86,7 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32, &c->Kbh, &c->Kbl,
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
                    &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
-                   &c->diag0, &c->minratio, &c->rscratch, &c->occ_d};
+                   &c->diag0, &c->minratio, &c->rscratch, &c->occ_d, &c->Kc64};
   for (DevBuf *b : all) b->release();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -112,12 +112,14 @@ extern "C" const char *chfsi_status_string(int s) {
 // ---------------------------------------------------------------------------
 // setMesh / setPotential
 // ---------------------------------------------------------------------------
-extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) {
+static int upload_kpoint(chfsi_ctx *c);
+
+static int set_mesh_impl(chfsi_ctx *c, double L, int n_el, int p, bool periodic) {
   if (!c) return CHFSI_ERR_ARG;
   if (c->device >= 0)
     if (int r = set_dev(c)) return r;
   MeshTables m;
-  std::string msg = build_mesh(L, n_el, p, m);
+  std::string msg = build_mesh(L, n_el, p, m, periodic);
   if (!msg.empty()) return fail(c, CHFSI_ERR_ARG, msg);
   if (m.np != 16 && m.np != 32 && m.np != 64 && m.np != 128 && m.np != 224 && m.np != 352 && m.np != 512)
     return fail(c, CHFSI_ERR_ARG, "set_mesh: degree p must be in 1..7 for the device cell kernel");
@@ -171,7 +173,88 @@ extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) {
   HIPCHK(c, hipMemcpyAsync(c->Kbh.p, kh.data(), nb2 * 2, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->Kbl.p, kl.data(), nb2 * 2, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
+  c->kvec[0] = c->kvec[1] = c->kvec[2] = 0.0;
+  if (M.periodic)
+    if (int r = upload_kpoint(c)) return r;
   c->has_mesh = true;
+  return 0;
+}
+
+extern "C" int chfsi_set_mesh(chfsi_ctx *c, double L, int n_el, int p) { return set_mesh_impl(c, L, n_el, p, false); }
+
+extern "C" int chfsi_set_mesh_periodic(chfsi_ctx *c, double L, int n_el, int p) {
+  return set_mesh_impl(c, L, n_el, p, true);
+}
+
+// The complex cell matrix of Htilde_k as the real contraction operator of the
+// interleaved layout: H^e = A - i B with A the stiffness of -1/2 Laplacian and
+// B = k.G; for Y = H^e X with X = Xr + i Xi, Y_re = A Xr + B Xi and
+// Y_im = A Xi - B Xr.  Stored as [A ; B^T] (2 np x np, row kappa holds the
+// weights of contraction index kappa for every output row), so the second half
+// of the contraction runs over the gathered X with its (re, im) pairs swapped
+// and the imaginary outputs negated.
+static int upload_kpoint(chfsi_ctx *c) {
+  const MeshTables &M = c->mesh;
+  const size_t nl = M.n_loc, np = M.np;
+  std::vector<double> kc(2 * np * np, 0.0);
+  for (size_t i = 0; i < nl; ++i)
+    for (size_t j = 0; j < nl; ++j) {
+      kc[i * np + j] = M.kcell[i * nl + j];
+      const double b = c->kvec[0] * M.gcell[0][i * nl + j] + c->kvec[1] * M.gcell[1][i * nl + j] +
+                       c->kvec[2] * M.gcell[2][i * nl + j];
+      kc[(np + j) * np + i] = b;                   // B^T: row kappa = j, output i
+    }
+  HIPCHK(c, c->Kc64.ensure(kc.size() * sizeof(double)));
+  HIPCHK(c, hipMemcpyAsync(c->Kc64.p, kc.data(), kc.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+extern "C" int chfsi_set_kpoint(chfsi_ctx *c, double kx, double ky, double kz) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (!c->has_mesh || !c->mesh.periodic) return fail(c, CHFSI_ERR_STATE, "set_kpoint: needs a periodic mesh");
+  if (!std::isfinite(kx) || !std::isfinite(ky) || !std::isfinite(kz))
+    return fail(c, CHFSI_ERR_ARG, "set_kpoint: k must be finite");
+  c->kvec[0] = kx;
+  c->kvec[1] = ky;
+  c->kvec[2] = kz;
+  if (c->device < 0) return 0;
+  if (int r = set_dev(c)) return r;
+  return upload_kpoint(c);
+}
+
+extern "C" int chfsi_apply_complex(chfsi_ctx *c, const void *X, void *Y, int64_t ld, int ncols) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (!c->mesh.periodic) return fail(c, CHFSI_ERR_STATE, "apply_complex: needs a periodic mesh");
+  if (!Y || Y == X) return fail(c, CHFSI_ERR_ARG, "apply_complex: Y must be a separate device array");
+  const MeshTables &M = c->mesh;
+  HxArgs<double> a;
+  a.X = static_cast<const double *>(X);
+  a.ldx = 2 * ld;
+  a.Xp = nullptr;
+  a.ldp = 0;
+  a.Y = static_cast<double *>(Y);
+  a.ldy = 2 * ld;
+  a.K = c->Kc64.as<double>();
+  a.cmap = c->cmap.as<int32_t>();
+  a.n_loc = M.n_loc;
+  a.np = M.np;
+  a.q = M.q;
+  a.n_el = M.n_el;
+  a.cells = c->cells.as<int32_t>();
+  a.minv = c->minv64.as<double>();
+  a.V = c->V64.as<double>();
+  a.ncols = 2 * ncols;
+  a.s1 = 1.0;
+  a.s2 = 0.0;
+  // V + |k|^2 / 2 on the diagonal: the epilogue adds s1 (V - shift) X
+  a.shift = -0.5 * (c->kvec[0] * c->kvec[0] + c->kvec[1] * c->kvec[1] + c->kvec[2] * c->kvec[2]);
+  a.variant = c->tile_variant;
+  for (int col = 0; col < 8; ++col) {
+    if (hx_cells_cplx_launch(a, M.color_offset[col], M.color_offset[col + 1], c->stream) != 0)
+      return fail(c, CHFSI_ERR_ARG, "apply_complex: unsupported cell size");
+  }
+  HIPCHK(c, hipGetLastError());
   return 0;
 }
 

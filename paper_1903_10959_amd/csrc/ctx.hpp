@@ -55,6 +55,8 @@ struct chfsi_ctx {
   // workspaces
   chfsi::DevBuf fbuf[3];      // filter recursion buffers
   chfsi::DevBuf occ_d;    // density: fr occupancy weights
+  chfsi::DevBuf Kc64;     // periodic mesh: [A ; (k.G)^T] complex cell operator, 2 np x np
+  double kvec[3] = {0, 0, 0};
   chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
       rscratch;
   std::vector<double> host_scratch = std::vector<double>(16);

@@ -131,7 +131,11 @@ struct LdsTile {
   static_assert((SK * sizeof(T)) % 16 == 0, "16-byte LDS stores of K rows");
 };
 
-template <typename T, int NP, int NW, int WR, int CBW, int KC, int EPD>
+// CPLX: complex products on interleaved (re, im) columns with K = [A ; B^T]
+// (2 NP rows): the contraction runs twice as long, and its second half
+// gathers each column's partner (col ^ 1), negated for imaginary outputs, so
+// Y_re = A Xr + B Xi and Y_im = A Xi - B Xr.
+template <typename T, int NP, int NW, int WR, int CBW, int KC, int EPD, bool CPLX = false>
 __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp,
                                               int64_t ldp, T *__restrict__ Y, int64_t ldy,
                                               const T *__restrict__ K, const int32_t *__restrict__ cmap,
@@ -174,6 +178,9 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
   // buffer.  The X values are scaled when stored, so no wait sits at the load.
   vec_t kreg[C::KPT];
   T xreg[C::XPT];
+  constexpr int NCHT = CPLX ? 2 * C::NCH : C::NCH;   // contraction chunks
+  // chunk c covers local nodes c KC - (second half ? NP : 0) + [0, KC)
+  auto node0 = [&](int c) { return c * KC - ((CPLX && c >= C::NCH) ? NP : 0); };
   auto load_chunk = [&](int c) {
     const vec_t *Kc = reinterpret_cast<const vec_t *>(K + (int64_t)c * KC * NP);
 #pragma unroll
@@ -181,10 +188,11 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
       const int v = t + C::NT * i;
       if (v < C::KV) kreg[i] = Kc[v];
     }
+    const int gcol = (CPLX && c >= C::NCH) ? (xcol ^ 1) : xcol;
 #pragma unroll
     for (int i = 0; i < C::XPT; ++i) {
-      const int row = c * KC + xrow0 + i * (C::NT / C::TW);
-      xreg[i] = X[(int64_t)dof_s[row] * ldx + xcol];
+      const int row = node0(c) + xrow0 + i * (C::NT / C::TW);
+      xreg[i] = X[(int64_t)dof_s[row] * ldx + gcol];
     }
   };
   auto store_chunk = [&](int buf, int c) {
@@ -201,10 +209,11 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
         }
       }
     }
+    const T sgn = (CPLX && c >= C::NCH && (xcol & 1)) ? T(-1) : T(1);
 #pragma unroll
     for (int i = 0; i < C::XPT; ++i) {
       const int rr = xrow0 + i * (C::NT / C::TW);
-      Xs[buf][rr * C::SX + xc] = xreg[i] * (mi_s[c * KC + rr] * xscale);
+      Xs[buf][rr * C::SX + xc] = xreg[i] * (mi_s[node0(c) + rr] * (xscale * sgn));
     }
   };
 
@@ -220,9 +229,9 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
   const int arow = wr * C::RBW * 16 + j;            // A fragment: K[k][arow + 16 r]
   const int bcol = wc * CBW * 16 + j;               // B fragment: Xs[k][bcol + 16 cb]
 #pragma unroll 1
-  for (int c = 0; c < C::NCH; ++c) {
+  for (int c = 0; c < NCHT; ++c) {
     const int buf = c & 1;
-    if (c + 1 < C::NCH) load_chunk(c + 1);
+    if (c + 1 < NCHT) load_chunk(c + 1);
     const T *Kb = Ks[buf];
     const T *Xb = Xs[buf];
     // Software pipeline over the chunk's (step, row-block pair) stages: the
@@ -271,7 +280,7 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
         }
       }
     }
-    if (c + 1 < C::NCH) store_chunk(buf ^ 1, c + 1);
+    if (c + 1 < NCHT) store_chunk(buf ^ 1, c + 1);
     __syncthreads();
   }
 
@@ -538,6 +547,21 @@ __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP, V>::WAVES))) void hx_cells_bat
                   P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el, w.y, w.z, P.minv, P.V, P.ncols, coef[0],
                   coef[1], coef[2]);
 }
+
+// Complex Bloch operator on a periodic mesh (FP64): the same tile with the
+// doubled contraction.
+template <int NP, int V>
+__global__ __launch_bounds__((64 * TileCfg<double, NP, V>::NW))
+__attribute__((amdgpu_waves_per_eu(TileCfg<double, NP, V>::WAVES))) void hx_cells_cplx_kernel(
+    const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy, const double *__restrict__ K,
+    const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, const int32_t *__restrict__ cells,
+    const double *__restrict__ minv, const double *__restrict__ V_, int ncols, int ntiles, double shift) {
+  typedef TileCfg<double, NP, V> CF;
+  const int cell_slot = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - cell_slot * ntiles;
+  cell_tile<double, NP, CF::NW, CF::WR, CF::CBW, CF::KC, CF::EPD, true>(
+      X, ldx, nullptr, 0, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols, 1.0, 0.0, shift);
+}
 #undef CHFSI_CELL_TILE
 
 template <typename T, int NP, int V>
@@ -549,6 +573,18 @@ static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hip
   hipLaunchKernelGGL((hx_cells_kernel<T, NP, V>), dim3((unsigned)(ncell * ntiles)),
                      dim3(64 * TileCfg<T, NP, V>::NW), 0, s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.cmap,
                      a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
+}
+
+template <int NP, int V>
+static void launch_cells_cplx(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s) {
+  constexpr int TW = TileCfg<double, NP, V>::L::TW;
+  static_assert(TW % 2 == 0, "complex column pairs must not straddle a tile");
+  const int ntiles = (a.ncols + TW - 1) / TW;
+  const int ncell = color_end - color_begin;
+  if (ncell <= 0 || ntiles <= 0) return;
+  hipLaunchKernelGGL((hx_cells_cplx_kernel<NP, V>), dim3((unsigned)(ncell * ntiles)),
+                     dim3(64 * TileCfg<double, NP, V>::NW), 0, s, a.X, a.ldx, a.Y, a.ldy, a.K, a.cmap, a.n_loc, a.q,
+                     a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.shift);
 }
 
 template <typename T, int NP, int V>
@@ -610,6 +646,18 @@ int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStrea
 }
 template int hx_cells_launch<double>(const HxArgs<double> &, int, int, hipStream_t);
 template int hx_cells_launch<float>(const HxArgs<float> &, int, int, hipStream_t);
+
+struct LaunchCellsCplxOp {
+  const HxArgs<double> &a;
+  int cb, ce;
+  hipStream_t s;
+  template <int NP, int V> void run() { launch_cells_cplx<NP, V>(a, cb, ce, s); }
+};
+int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s) {
+  if (a.ncols % 2) return -1;
+  LaunchCellsCplxOp op{a, color_begin, color_end, s};
+  return with_cfg<double>(a.np, a.variant, op);
+}
 
 template <typename T>
 struct LaunchBatchOp {

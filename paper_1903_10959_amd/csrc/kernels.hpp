@@ -32,6 +32,9 @@ int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStrea
 // np is not supported); column tiles of the batched work list use it.
 template <typename T>
 int hx_tile_width(int np, int variant);
+// Complex cell products on interleaved (re, im) columns: a.K is the
+// [A ; B^T] operator (2 np x np) and a.ncols counts real columns (even).
+int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s);
 
 // One problem of a batched filter sweep (device-resident descriptor).
 template <typename T>

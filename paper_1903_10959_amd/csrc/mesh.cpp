@@ -88,17 +88,19 @@ void sym_eigvals(std::vector<double> a, int n, std::vector<double> &out) {
   std::sort(out.begin(), out.end());
 }
 
-std::string build_mesh(double L, int n_el, int p, MeshTables &m) {
+std::string build_mesh(double L, int n_el, int p, MeshTables &m, bool periodic) {
   if (!(L > 0) || n_el < 1 || p < 1 || p > 12) return "set_mesh: need L > 0, n_el >= 1, 1 <= p <= 12";
   if ((int64_t)n_el * p < 2) return "set_mesh: n_el*p must be >= 2 (at least one interior node)";
   if ((int64_t)n_el * p - 1 > 2000) return "set_mesh: mesh too large";
+  if (periodic && (n_el < 2 || n_el % 2)) return "set_mesh_periodic: n_el must be even and >= 2";
   m = MeshTables();
+  m.periodic = periodic;
   m.L = L;
   m.n_el = n_el;
   m.p = p;
   m.q = p + 1;
   m.h = L / n_el;
-  m.n = n_el * p - 1;
+  m.n = periodic ? n_el * p : n_el * p - 1;
   m.n_loc = m.q * m.q * m.q;
   m.np = (m.n_loc + 15) / 16 * 16;
   m.n_dof = (int64_t)m.n * m.n * m.n;
@@ -169,8 +171,13 @@ std::string build_mesh(double L, int n_el, int p, MeshTables &m) {
             for (int a = 0; a < q; ++a) {
               int I = ex * p + a, J = ey * p + b, K = ez * p + c;
               int l = a + q * b + q * q * c;
-              if (I == 0 || J == 0 || K == 0 || I == edge || J == edge || K == edge) continue;
-              int64_t d = (int64_t)(I - 1) + (int64_t)n * ((J - 1) + (int64_t)n * (K - 1));
+              int64_t d;
+              if (periodic) {
+                d = (int64_t)(I % edge) + (int64_t)n * ((J % edge) + (int64_t)n * (K % edge));
+              } else {
+                if (I == 0 || J == 0 || K == 0 || I == edge || J == edge || K == edge) continue;
+                d = (int64_t)(I - 1) + (int64_t)n * ((J - 1) + (int64_t)n * (K - 1));
+              }
               m.cmap[(size_t)e * nl + l] = (int32_t)d;
               m.mass[d] += jac * m.w[a] * m.w[b] * m.w[c];
             }
@@ -184,21 +191,46 @@ std::string build_mesh(double L, int n_el, int p, MeshTables &m) {
   }
   m.color_offset[8] = pos;
 
+  // first-derivative cell matrices of the k-point operator (periodic only):
+  // G_x[(a,b,c), (a2,b2,c2)] = (h/2)^2 w_a w_b w_c D[a][a2] delta_b,b2 delta_c,c2
+  // and the same along y and z; the GLL rule is exact for this integrand's
+  // degree (2p - 1) in the derivative direction.
+  if (periodic) {
+    const double s2 = (m.h / 2.0) * (m.h / 2.0);
+    for (int dd = 0; dd < 3; ++dd) m.gcell[dd].assign((size_t)nl * nl, 0.0);
+    for (int c = 0; c < q; ++c)
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          const int l = a + q * b + q * q * c;
+          const double wl = s2 * m.w[a] * m.w[b] * m.w[c];
+          for (int t = 0; t < q; ++t) {
+            m.gcell[0][(size_t)l * nl + (t + q * b + q * q * c)] = wl * m.D[(size_t)a * q + t];
+            m.gcell[1][(size_t)l * nl + (a + q * t + q * q * c)] = wl * m.D[(size_t)b * q + t];
+            m.gcell[2][(size_t)l * nl + (a + q * b + q * q * t)] = wl * m.D[(size_t)c * q + t];
+          }
+        }
+  }
+
   // 1D operator A = 1/2 M1^-1/2 K1D M1^-1/2 on the n interior nodes, for the
   // spectral upper bound; n <= 2000 keeps the host Jacobi affordable only for
   // small n, so beyond 400 nodes a Gershgorin bound (still rigorous) is used.
   {
-    const int n1 = edge + 1;
+    // assembled over the n_el p + 1 nodes of the line (periodic: indices
+    // wrapped onto n_el p nodes), then restricted to the n unknowns
+    const int n1 = periodic ? edge : edge + 1, off = periodic ? 0 : 1;
     std::vector<double> K1D((size_t)n1 * n1, 0.0), M1(n1, 0.0);
     for (int e = 0; e < n_el; ++e)
       for (int a = 0; a < q; ++a) {
-        M1[e * p + a] += (m.h / 2.0) * m.w[a];
-        for (int b = 0; b < q; ++b) K1D[(size_t)(e * p + a) * n1 + (e * p + b)] += (2.0 / m.h) * m.K1[(size_t)a * q + b];
+        const int ia = (e * p + a) % n1;
+        M1[ia] += (m.h / 2.0) * m.w[a];
+        for (int b = 0; b < q; ++b)
+          K1D[(size_t)ia * n1 + (e * p + b) % n1] += (2.0 / m.h) * m.K1[(size_t)a * q + b];
       }
     std::vector<double> A((size_t)n * n);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j)
-        A[(size_t)i * n + j] = 0.5 * K1D[(size_t)(i + 1) * n1 + (j + 1)] / std::sqrt(M1[i + 1] * M1[j + 1]);
+        A[(size_t)i * n + j] =
+            0.5 * K1D[(size_t)(i + off) * n1 + (j + off)] / std::sqrt(M1[i + off] * M1[j + off]);
     if (n <= 400) {
       std::vector<double> ev;
       sym_eigvals(A, n, ev);
@@ -219,9 +251,10 @@ std::string build_mesh(double L, int n_el, int p, MeshTables &m) {
 
 void dof_coords(const MeshTables &m, double *xyz) {
   std::vector<double> x1(m.n);
-  for (int I = 1; I <= m.n; ++I) {
-    int ex = I / m.p, a = I % m.p;
-    x1[I - 1] = ex * m.h + (1.0 + m.xi[a]) * m.h / 2.0;
+  const int I0 = m.periodic ? 0 : 1;   // periodic unknowns start at the node x = 0
+  for (int i = 0; i < m.n; ++i) {
+    const int I = i + I0, ex = I / m.p, a = I % m.p;
+    x1[i] = ex * m.h + (1.0 + m.xi[a]) * m.h / 2.0;
   }
   for (int K = 0; K < m.n; ++K)
     for (int J = 0; J < m.n; ++J)

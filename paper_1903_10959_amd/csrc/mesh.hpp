@@ -25,10 +25,16 @@ struct MeshTables {
   int color_offset[9] = {0};
   std::vector<double> mass;        // [n_dof] diagonal of M
   double lam1d_max = 0;            // largest eigenvalue of the assembled 1D operator
+  // periodic cell [0, L)^3: node index I = (ex p + a) mod (n_el p), n = n_el p,
+  // no Dirichlet nodes; gcell[d] = int N_j d_d N_l (GLL rule), n_loc x n_loc
+  bool periodic = false;
+  std::vector<double> gcell[3];
 };
 
 // Builds every table; returns an empty string on success, else a message.
-std::string build_mesh(double L, int n_el, int p, MeshTables &m);
+// periodic: the Bloch-periodic cell of Sec. 2.2 (n_el even, so that the
+// 8-colour parity rule still separates cells that share a node across the wrap).
+std::string build_mesh(double L, int n_el, int p, MeshTables &m, bool periodic = false);
 
 // x,y,z of every interior node in dof order.
 void dof_coords(const MeshTables &m, double *xyz);

@@ -87,3 +87,31 @@ def test_density_full_size_large_p5():
     del X, Xfr, rho, M
     torch.cuda.empty_cache()
     c.close()
+
+
+def test_apply_complex_full_size_sampled_columns():
+    """The complex Bloch operator on a periodic cell with the large_p6 element
+    size (24^3 cells, p = 6: 144^3 = 2,985,984 DoFs), 64 complex columns (two
+    column tiles of the kernel); sampled columns against the oracle's
+    Kronecker-sum apply."""
+    import torch
+    import paper_1903_10959_amd as P
+    from oracle import kpoint
+    L, n_el, p = 40.0, 24, 6
+    k = np.array([0.05, 0.11, -0.08])
+    c = P.Context(0).set_mesh(L, n_el, p, periodic=True)
+    V = workload.eval_wells(workload.draw_wells(64, L, 2, (1.0, 3.0), (0.5, 1.5)), c.dof_coords())
+    c.set_potential(V)
+    c.set_kpoint(k)
+    g = torch.Generator(device="cuda:0").manual_seed(77)
+    X = torch.randn((c.n_dof, 64), dtype=torch.complex128, device="cuda:0", generator=g)
+    Y = c.apply_complex(X)
+    cols = [0, 31, 32, 63]
+    Xs = X[:, cols].cpu().numpy()
+    A = [kpoint.operator_1d_periodic(L, n_el, p, kd) for kd in k]
+    Yo = kpoint.apply_kron_k(*A, V, Xs)
+    rel = np.max(np.abs(Y[:, cols].cpu().numpy() - Yo)) / np.max(np.abs(Yo))
+    assert rel < 1e-13, rel
+    del X, Y
+    torch.cuda.empty_cache()
+    c.close()
