@@ -178,6 +178,19 @@ int chfsi_set_kpoint(chfsi_ctx *ctx, double kx, double ky, double kz);
  * a periodic mesh and potential, CHFSI_ERR_ARG for bad block arguments. */
 int chfsi_apply_complex(chfsi_ctx *ctx, const void *X, void *Y, int64_t ld, int ncols);
 
+/* A group of k-points on one periodic mesh (the paper's k-point
+ * parallelisation, Sec. 3.7, as one launch per colour): chfsi_set_kpoints
+ * takes nk wave vectors (host, 3 nk values, k-point g at k[3g .. 3g+2]) and
+ * uploads one cell operator each; chfsi_apply_complex_kpoints computes
+ * Y_g = Htilde_{k_g} X_g for all g, block g at X + g*stride (and Y + g*stride),
+ * stride in complex elements (>= n_dof * ld), layout as chfsi_apply_complex.
+ * Work items (k-point, cell, column tile) share the mesh tables.  A new mesh
+ * clears the group.  Errors: CHFSI_ERR_STATE without a periodic mesh (or
+ * without a group for the apply), CHFSI_ERR_ARG for nk < 1, non-finite k,
+ * stride < n_dof * ld or overlapping X and Y. */
+int chfsi_set_kpoints(chfsi_ctx *ctx, int nk, const double *k);
+int chfsi_apply_complex_kpoints(chfsi_ctx *ctx, const void *X, void *Y, int64_t ld, int ncols, int64_t stride);
+
 /* ---- Fermi energy (Alg. 5 step 1) ------------------------------------------
  * The mu at which 2 (n_oc + sum_k f(evals_fr[k], mu)) = n_electrons, with the
  * Fermi-Dirac occupancy f(e, mu) = 1 / (1 + exp((e - mu) / sigma)) of Sec. 2.1

@@ -300,6 +300,31 @@ class Context:
         self._check(self._lib.chfsi_set_kpoint(self._h, kx, ky, kz), "set_kpoint")
         return self
 
+    def set_kpoints(self, ks):
+        """A group of wave vectors [[kx, ky, kz], ...] for apply_complex_kpoints."""
+        k = np.ascontiguousarray(np.asarray(ks, dtype=np.float64).reshape(-1, 3))
+        self._check(self._lib.chfsi_set_kpoints(self._h, int(k.shape[0]), k.ctypes.data_as(C.c_void_p)),
+                    "set_kpoints")
+        self.nk = int(k.shape[0])
+        return self
+
+    def apply_complex_kpoints(self, X, Y=None):
+        """Y[g] = Htilde_{k_g} X[g] for a complex128 CUDA tensor [nk, n_dof, ncols]."""
+        import torch
+
+        if not isinstance(X, torch.Tensor) or X.dtype != torch.complex128 or not X.is_cuda or X.dim() != 3:
+            raise TypeError("expected a 3-D complex128 CUDA tensor [nk, n_dof, ncols]")
+        if X.shape[0] != self.nk or X.shape[1] != self.n_dof or (X.shape[2] > 1 and X.stride(2) != 1):
+            raise ValueError("X must be [nk, n_dof, ncols] with contiguous columns")
+        if Y is None:
+            Y = torch.empty_strided(tuple(X.shape), tuple(X.stride()), dtype=X.dtype, device=X.device)
+        if Y.dtype != torch.complex128 or tuple(Y.shape) != tuple(X.shape) or Y.stride() != X.stride():
+            raise ValueError("Y must match X in shape, dtype and strides")
+        self._check(self._lib.chfsi_apply_complex_kpoints(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                                          int(X.stride(1)), int(X.shape[2]), int(X.stride(0))),
+                    "apply_complex_kpoints")
+        return Y
+
     def apply_complex(self, X, Y=None):
         """Y = Htilde_k X for a complex128 CUDA tensor [n_dof, ncols] (periodic mesh)."""
         import torch

@@ -86,7 +86,8 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32, &c->Kbh, &c->Kbl,
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
                    &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
-                   &c->diag0, &c->minratio, &c->rscratch, &c->occ_d, &c->Kc64};
+                   &c->diag0, &c->minratio, &c->rscratch, &c->occ_d, &c->Kc64,
+                   &c->Kcg, &c->kshift};
   for (DevBuf *b : all) b->release();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -174,6 +175,7 @@ static int set_mesh_impl(chfsi_ctx *c, double L, int n_el, int p, bool periodic)
   HIPCHK(c, hipMemcpyAsync(c->Kbl.p, kl.data(), nb2 * 2, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
   c->kvec[0] = c->kvec[1] = c->kvec[2] = 0.0;
+  c->nk = 0;                                     // a k-point group belongs to its mesh
   if (M.periodic)
     if (int r = upload_kpoint(c)) return r;
   c->has_mesh = true;
@@ -221,6 +223,77 @@ extern "C" int chfsi_set_kpoint(chfsi_ctx *c, double kx, double ky, double kz) {
   if (c->device < 0) return 0;
   if (int r = set_dev(c)) return r;
   return upload_kpoint(c);
+}
+
+extern "C" int chfsi_set_kpoints(chfsi_ctx *c, int nk, const double *k) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (!c->has_mesh || !c->mesh.periodic) return fail(c, CHFSI_ERR_STATE, "set_kpoints: needs a periodic mesh");
+  if (nk < 1 || !k) return fail(c, CHFSI_ERR_ARG, "set_kpoints: need nk >= 1 and a host array of 3 nk values");
+  for (int i = 0; i < 3 * nk; ++i)
+    if (!std::isfinite(k[i])) return fail(c, CHFSI_ERR_ARG, "set_kpoints: k must be finite");
+  c->kgroup.assign(k, k + 3 * nk);
+  c->nk = nk;
+  if (c->device < 0) return 0;
+  if (int r = set_dev(c)) return r;
+  const MeshTables &M = c->mesh;
+  const size_t nl = M.n_loc, np = M.np, per = 2 * np * np;
+  std::vector<double> kc(per * nk, 0.0), sh(nk);
+  for (int g = 0; g < nk; ++g) {
+    const double *kv = k + 3 * g;
+    double *o = kc.data() + g * per;
+    for (size_t i = 0; i < nl; ++i)
+      for (size_t j = 0; j < nl; ++j) {
+        o[i * np + j] = M.kcell[i * nl + j];
+        o[(np + j) * np + i] =
+            kv[0] * M.gcell[0][i * nl + j] + kv[1] * M.gcell[1][i * nl + j] + kv[2] * M.gcell[2][i * nl + j];
+      }
+    sh[g] = -0.5 * (kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]);
+  }
+  HIPCHK(c, c->Kcg.ensure(kc.size() * sizeof(double)));
+  HIPCHK(c, c->kshift.ensure(sh.size() * sizeof(double)));
+  HIPCHK(c, hipMemcpyAsync(c->Kcg.p, kc.data(), kc.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->kshift.p, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+extern "C" int chfsi_apply_complex_kpoints(chfsi_ctx *c, const void *X, void *Y, int64_t ld, int ncols,
+                                           int64_t stride) {
+  if (int r = check_block(c, X, ld, ncols)) return r;
+  if (!c->mesh.periodic || c->nk < 1)
+    return fail(c, CHFSI_ERR_STATE, "apply_complex_kpoints: needs a periodic mesh and set_kpoints");
+  const MeshTables &M = c->mesh;
+  if (!Y || stride < M.n_dof * ld) return fail(c, CHFSI_ERR_ARG, "apply_complex_kpoints: stride < n_dof * ld");
+  const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
+  const int64_t span = (int64_t)(c->nk - 1) * stride * 16 + M.n_dof * ld * 16;
+  if (yb < xb + span && xb < yb + span) return fail(c, CHFSI_ERR_ARG, "apply_complex_kpoints: Y overlaps X");
+  HxArgs<double> a;
+  a.X = static_cast<const double *>(X);
+  a.ldx = 2 * ld;
+  a.Xp = nullptr;
+  a.ldp = 0;
+  a.Y = static_cast<double *>(Y);
+  a.ldy = 2 * ld;
+  a.K = c->Kcg.as<double>();
+  a.cmap = c->cmap.as<int32_t>();
+  a.n_loc = M.n_loc;
+  a.np = M.np;
+  a.q = M.q;
+  a.n_el = M.n_el;
+  a.cells = c->cells.as<int32_t>();
+  a.minv = c->minv64.as<double>();
+  a.V = c->V64.as<double>();
+  a.ncols = 2 * ncols;
+  a.s1 = 1.0;
+  a.s2 = 0.0;
+  a.shift = 0.0;
+  a.variant = c->tile_variant;
+  const CplxKpts g{c->nk, 2 * stride, 2 * stride, (int64_t)2 * M.np * M.np, c->kshift.as<double>()};
+  for (int col = 0; col < 8; ++col)
+    if (hx_cells_cplx_kpts_launch(a, g, M.color_offset[col], M.color_offset[col + 1], c->stream) != 0)
+      return fail(c, CHFSI_ERR_ARG, "apply_complex_kpoints: unsupported cell size or grid too large");
+  HIPCHK(c, hipGetLastError());
+  return 0;
 }
 
 extern "C" int chfsi_apply_complex(chfsi_ctx *c, const void *X, void *Y, int64_t ld, int ncols) {

@@ -57,6 +57,9 @@ struct chfsi_ctx {
   chfsi::DevBuf occ_d;    // density: fr occupancy weights
   chfsi::DevBuf Kc64;     // periodic mesh: [A ; (k.G)^T] complex cell operator, 2 np x np
   double kvec[3] = {0, 0, 0};
+  chfsi::DevBuf Kcg, kshift; // k-point group: nk cell operators and |k|^2/2 shifts
+  int nk = 0;
+  std::vector<double> kgroup;
   chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,
       rscratch;
   std::vector<double> host_scratch = std::vector<double>(16);

@@ -562,6 +562,26 @@ __attribute__((amdgpu_waves_per_eu(TileCfg<double, NP, V>::WAVES))) void hx_cell
   cell_tile<double, NP, CF::NW, CF::WR, CF::CBW, CF::KC, CF::EPD, true>(
       X, ldx, nullptr, 0, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols, 1.0, 0.0, shift);
 }
+
+// A group of k-points on one mesh: work item (k, cell, column tile); k's
+// block, cell operator and |k|^2/2 shift sit at fixed strides.
+template <int NP, int V>
+__global__ __launch_bounds__((64 * TileCfg<double, NP, V>::NW))
+__attribute__((amdgpu_waves_per_eu(TileCfg<double, NP, V>::WAVES))) void hx_cells_cplx_kpts_kernel(
+    const double *__restrict__ X, int64_t ldx, int64_t xstride, double *__restrict__ Y, int64_t ldy,
+    int64_t ystride, const double *__restrict__ K, int64_t kstride, const double *__restrict__ shifts,
+    const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, const int32_t *__restrict__ cells,
+    const double *__restrict__ minv, const double *__restrict__ V_, int ncols, int ntiles, int ncell) {
+  typedef TileCfg<double, NP, V> CF;
+  const int per_k = ncell * ntiles;
+  const int kk = blockIdx.x / per_k;
+  const int rest = blockIdx.x - kk * per_k;
+  const int cell_slot = rest / ntiles;
+  const int tile = rest - cell_slot * ntiles;
+  cell_tile<double, NP, CF::NW, CF::WR, CF::CBW, CF::KC, CF::EPD, true>(
+      X + kk * xstride, ldx, nullptr, 0, Y + kk * ystride, ldy, K + kk * kstride, cmap, n_loc, q, n_el,
+      cells[cell_slot], tile, minv, V_, ncols, 1.0, 0.0, shifts[kk]);
+}
 #undef CHFSI_CELL_TILE
 
 template <typename T, int NP, int V>
@@ -585,6 +605,19 @@ static void launch_cells_cplx(const HxArgs<double> &a, int color_begin, int colo
   hipLaunchKernelGGL((hx_cells_cplx_kernel<NP, V>), dim3((unsigned)(ncell * ntiles)),
                      dim3(64 * TileCfg<double, NP, V>::NW), 0, s, a.X, a.ldx, a.Y, a.ldy, a.K, a.cmap, a.n_loc, a.q,
                      a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.shift);
+}
+
+template <int NP, int V>
+static void launch_cells_cplx_kpts(const HxArgs<double> &a, const CplxKpts &g, int color_begin, int color_end,
+                                   hipStream_t s) {
+  constexpr int TW = TileCfg<double, NP, V>::L::TW;
+  const int ntiles = (a.ncols + TW - 1) / TW;
+  const int ncell = color_end - color_begin;
+  if (ncell <= 0 || ntiles <= 0 || g.nk <= 0) return;
+  hipLaunchKernelGGL((hx_cells_cplx_kpts_kernel<NP, V>), dim3((unsigned)(g.nk * ncell * ntiles)),
+                     dim3(64 * TileCfg<double, NP, V>::NW), 0, s, a.X, a.ldx, g.xstride, a.Y, a.ldy, g.ystride, a.K,
+                     g.kstride, g.shifts, a.cmap, a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols,
+                     ntiles, ncell);
 }
 
 template <typename T, int NP, int V>
@@ -656,6 +689,21 @@ struct LaunchCellsCplxOp {
 int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s) {
   if (a.ncols % 2) return -1;
   LaunchCellsCplxOp op{a, color_begin, color_end, s};
+  return with_cfg<double>(a.np, a.variant, op);
+}
+
+struct LaunchCellsCplxKptsOp {
+  const HxArgs<double> &a;
+  const CplxKpts &g;
+  int cb, ce;
+  hipStream_t s;
+  template <int NP, int V> void run() { launch_cells_cplx_kpts<NP, V>(a, g, cb, ce, s); }
+};
+int hx_cells_cplx_kpts_launch(const HxArgs<double> &a, const CplxKpts &g, int color_begin, int color_end,
+                              hipStream_t s) {
+  if (a.ncols % 2) return -1;
+  if ((int64_t)g.nk * (color_end - color_begin) * ((a.ncols + 31) / 32) > INT32_MAX) return -1;   // TW >= 32
+  LaunchCellsCplxKptsOp op{a, g, color_begin, color_end, s};
   return with_cfg<double>(a.np, a.variant, op);
 }
 

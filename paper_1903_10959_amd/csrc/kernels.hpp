@@ -35,6 +35,16 @@ int hx_tile_width(int np, int variant);
 // Complex cell products on interleaved (re, im) columns: a.K is the
 // [A ; B^T] operator (2 np x np) and a.ncols counts real columns (even).
 int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s);
+// A group of nk k-points in one launch per colour: block k at X + k xstride
+// (Y + k ystride, real elements), cell operator at a.K + k kstride, shift[k]
+// on the potential term (a.Xp, a.s1, a.s2 and a.shift unused).
+struct CplxKpts {
+  int nk;
+  int64_t xstride, ystride, kstride;
+  const double *shifts;
+};
+int hx_cells_cplx_kpts_launch(const HxArgs<double> &a, const CplxKpts &g, int color_begin, int color_end,
+                              hipStream_t s);
 
 // One problem of a batched filter sweep (device-resident descriptor).
 template <typename T>

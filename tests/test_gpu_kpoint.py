@@ -92,3 +92,26 @@ def test_gamma_point_solve_on_periodic_mesh():
     assert out["converged"]
     np.testing.assert_allclose(out["evals"][:N], ev[:N], rtol=1e-10, atol=1e-10)
     c.close()
+
+
+def test_kpoint_group_equals_single_applies():
+    """A group of k-points in one launch per colour gives each k-point's own
+    apply (padded row stride and a block stride beyond n_dof * ld)."""
+    import torch
+    L, n_el, p = 6.0, 2, 4
+    ks = np.array([[0.0, 0.0, 0.0], [0.26, 0.26, 0.0], [0.26, -0.26, 0.52], [-0.7, 0.1, 0.3]])
+    c, V = _ctx(L, n_el, p, (0.0, 0.0, 0.0))
+    c.set_kpoints(ks)
+    nk, ncols = ks.shape[0], 33
+    big = torch.zeros((nk, c.n_dof + 3, 40), dtype=torch.complex128, device="cuda:0")
+    Xh = np.stack([_rand(c.n_dof, ncols, 50 + g) for g in range(nk)])
+    big[:, :c.n_dof, :ncols] = torch.from_numpy(Xh).to("cuda:0")
+    X = big[:, :c.n_dof, :ncols]
+    Y = c.apply_complex_kpoints(X).cpu().numpy()
+    for g in range(nk):
+        c.set_kpoint(ks[g])
+        Yg = c.apply_complex(_cgpu(Xh[g])).cpu().numpy()
+        np.testing.assert_allclose(Y[g], Yg, rtol=0, atol=1e-15 * np.abs(Yg).max())
+    Yo = kpoint.htilde_k_csr(L, n_el, p, V, ks[-1]) @ Xh[-1]
+    assert np.max(np.abs(Y[-1] - Yo)) < 1e-13 * np.max(np.abs(Yo))
+    c.close()

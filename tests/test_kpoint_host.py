@@ -46,3 +46,15 @@ def test_periodic_argument_checks():
     with pytest.raises(P.ChfsiError):
         c.set_kpoint((np.inf, 0.0, 0.0))
     c.close()
+
+
+def test_kpoint_group_argument_checks():
+    c = P.Context(device=-1).set_mesh(5.0, 2, 3)
+    with pytest.raises(P.ChfsiError):
+        c.set_kpoints([[0.1, 0.0, 0.0]])                            # not periodic
+    c.close()
+    c = P.Context(device=-1).set_mesh(5.0, 2, 3, periodic=True)
+    c.set_kpoints([[0.1, 0.0, 0.0], [0.0, 0.2, 0.0]])
+    with pytest.raises(P.ChfsiError):
+        c.set_kpoints([[0.1, np.nan, 0.0]])
+    c.close()
