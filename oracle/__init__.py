@@ -27,6 +27,9 @@ Modules
            ksproblemPer): periodic numbering, the GLL first-derivative cell
            matrices, the complex Hermitian standard-form CSR and its
            Kronecker-sum apply.
+``poisson`` The discrete Poisson problem of the electrostatics (Sec. 2.4 eq.
+           phiTotDiscreteSolve, Dirichlet) and the Jacobi-preconditioned
+           conjugate-gradient solver the paper uses for it.
 
 Pinning status (what each function is checked against) is listed in the
 module docstrings.  Mixed-precision accuracy is *parity unpinned* by the paper
