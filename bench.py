@@ -433,6 +433,57 @@ def kpoint_bench(args, prob):
     ctx.close()
 
 
+def poisson_bench(args, prob):
+    """Electrostatics (eq. phiTotDiscreteSolve, Dirichlet) on the workload's
+    mesh: Jacobi-PCG to a 1e-10 relative residual for the density of the
+    workload's wells plus point charges at two nodes.  Roofline of the
+    matrix-free product: HBM, algorithmic bytes = 16 per DoF (read x, write y)."""
+    import numpy as np
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
+    rho = torch.from_numpy(-workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords())).to(dev)
+    charges = [(prob.n_dof // 3, -6.0), (2 * prob.n_dof // 3, -4.0)]
+    times, its = [], []
+    for rep in range(args.steps + 1):
+        phi = torch.zeros_like(rho)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = ctx.poisson_solve(rho, phi, charges=charges, tol=1e-10)
+        torch.cuda.synchronize()
+        if rep > 0:
+            times.append(time.time() - t0)
+            its.append(out["iters"])
+    x = torch.randn(prob.n_dof, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.poisson_apply(x, y)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.poisson_apply(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 16.0 * prob.n_dof / (ms * 1e-3) / 1e9
+    t = float(np.median(times))
+    res = {"metric": "Poisson solve (Jacobi-PCG to 1e-10) time", "value": t, "unit": "s", "n_gpus": 1,
+           "higher_is_better": False, "vs_baseline": None, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": f"Dirichlet [0,{prob.L}]^3, {prob.n_el}^3 cells, p={prob.p}, {prob.n_dof} DoFs; "
+                                  f"density of the workload's 64 wells + 2 point charges", "steps": args.steps},
+           "iterations": its[-1], "ms_per_iteration": 1e3 * t / max(1, its[-1]), "rel_resid": out["rel_resid"],
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                        "traffic": None, "kernel": "poisson_apply_kernel", "avg_launch_ms": ms,
+                        "bytes_per_launch": 16 * prob.n_dof}}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,10 +495,10 @@ def main():
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=16)
-    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density", "kpoint"],
+    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density", "kpoint", "poisson"],
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
                          "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5); "
-                         "kpoint: complex Bloch operator on the periodic cell")
+                         "kpoint: complex Bloch operator on the periodic cell; poisson: electrostatics (Jacobi-PCG)")
     ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
@@ -495,6 +546,8 @@ def main():
         return density_bench(args, prob)
     if args.mode == "kpoint":
         return kpoint_bench(args, prob)
+    if args.mode == "poisson":
+        return poisson_bench(args, prob)
     if args.mode == "rr":
         return rr_split_compare(args, prob)
     ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)

@@ -191,6 +191,28 @@ int chfsi_apply_complex(chfsi_ctx *ctx, const void *X, void *Y, int64_t ld, int 
 int chfsi_set_kpoints(chfsi_ctx *ctx, int nk, const double *k);
 int chfsi_apply_complex_kpoints(chfsi_ctx *ctx, const void *X, void *Y, int64_t ld, int ncols, int64_t stride);
 
+/* ---- electrostatics: the discrete Poisson problem (Sec. 2.4 eq.
+ * phiTotDiscreteSolve), homogeneous Dirichlet conditions ------------------
+ * A phi = f with A = 1/(4 pi) int grad N_i . grad N_j on the mesh's GLL
+ * elements and f = M rho + q (the GLL rule makes int rho N_i = M_ii rho_i; a
+ * point charge q_I on node d_I adds q_I to f_{d_I}: the paper's nuclear
+ * charges b_I = -Z_I delta sit on nodes).  On the uniform mesh A is applied
+ * matrix-free as the Kronecker sum of the banded 1D stiffness and the 1D
+ * masses (the assembled form of the paper's matrix-free operator).
+ * chfsi_poisson_apply: y = A x (device [n_dof] each, not overlapping).
+ * chfsi_poisson_solve: Jacobi-preconditioned conjugate gradients (the paper's
+ * solver, Sec. 3.2) from the initial guess in phi (device [n_dof], in/out) to
+ * ||f - A phi|| <= tol ||f||; rho device [n_dof] (Dirichlet nodes carry no
+ * DoF); charge_dofs/charges host [ncharges] (charges on one node add up).
+ * iters and rel_resid (the true residual of the returned phi, recomputed at
+ * the end) may be NULL.  Returns 0, or CHFSI_WARN_NOT_CONVERGED when max_iter
+ * ends the iteration first.  Needs a mesh (no potential); CHFSI_ERR_STATE on
+ * a periodic mesh (a periodic cell needs a neutral charge); CHFSI_ERR_ARG for
+ * bad pointers, tol <= 0 or a charge dof outside 0..n_dof-1. */
+int chfsi_poisson_apply(chfsi_ctx *ctx, const double *x, double *y);
+int chfsi_poisson_solve(chfsi_ctx *ctx, const double *rho, int ncharges, const int64_t *charge_dofs,
+                        const double *charges, double *phi, double tol, int max_iter, int *iters, double *rel_resid);
+
 /* ---- Fermi energy (Alg. 5 step 1) ------------------------------------------
  * The mu at which 2 (n_oc + sum_k f(evals_fr[k], mu)) = n_electrons, with the
  * Fermi-Dirac occupancy f(e, mu) = 1 / (1 + exp((e - mu) / sigma)) of Sec. 2.1

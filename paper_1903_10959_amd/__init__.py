@@ -300,6 +300,39 @@ class Context:
         self._check(self._lib.chfsi_set_kpoint(self._h, kx, ky, kz), "set_kpoint")
         return self
 
+    def poisson_apply(self, x, y=None):
+        """y = A x, A = 1/(4 pi) int grad N_i . grad N_j (Dirichlet mesh)."""
+        import torch
+
+        if y is None:
+            y = torch.empty_like(x)
+        for t in (x, y):
+            if t.dtype != torch.float64 or not t.is_cuda or t.numel() != self.n_dof or not t.is_contiguous():
+                raise TypeError("x, y: contiguous float64 CUDA tensors of n_dof values")
+        self._check(self._lib.chfsi_poisson_apply(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())),
+                    "poisson_apply")
+        return y
+
+    def poisson_solve(self, rho, phi=None, charges=(), tol: float = 1e-10, max_iter: int = 10000):
+        """Electrostatic potential of the nodal density rho plus point charges
+        [(dof, q), ...] (Jacobi-PCG).  Returns dict(phi, iters, rel_resid, converged)."""
+        import torch
+
+        if phi is None:
+            phi = torch.zeros_like(rho)
+        for t in (rho, phi):
+            if t.dtype != torch.float64 or not t.is_cuda or t.numel() != self.n_dof or not t.is_contiguous():
+                raise TypeError("rho, phi: contiguous float64 CUDA tensors of n_dof values")
+        cd = np.ascontiguousarray(np.array([int(d) for d, _ in charges], dtype=np.int64))
+        cq = np.ascontiguousarray(np.array([float(q) for _, q in charges], dtype=np.float64))
+        it, rr = C.c_int(0), C.c_double(0.0)
+        st = self._lib.chfsi_poisson_solve(self._h, C.c_void_p(rho.data_ptr()), int(cd.size),
+                                           cd.ctypes.data_as(C.c_void_p), cq.ctypes.data_as(C.c_void_p),
+                                           C.c_void_p(phi.data_ptr()), float(tol), int(max_iter), C.byref(it),
+                                           C.byref(rr))
+        self._check(st, "poisson_solve", ok=(0, _lib.WARN_NOT_CONVERGED))
+        return dict(phi=phi, iters=it.value, rel_resid=rr.value, converged=(st == 0))
+
     def set_kpoints(self, ks):
         """A group of wave vectors [[kx, ky, kz], ...] for apply_complex_kpoints."""
         k = np.ascontiguousarray(np.asarray(ks, dtype=np.float64).reshape(-1, 3))

@@ -62,6 +62,8 @@ SIGNATURES = {
     "chfsi_set_kpoint": (_int, [_vp, _dbl, _dbl, _dbl]),
     "chfsi_apply_complex": (_int, [_vp, _vp, _vp, _i64, _int]),
     "chfsi_set_kpoints": (_int, [_vp, _int, _vp]),
+    "chfsi_poisson_apply": (_int, [_vp, _vp, _vp]),
+    "chfsi_poisson_solve": (_int, [_vp, _vp, _int, _vp, _vp, _vp, _dbl, _int, _vp, _vp]),
     "chfsi_apply_complex_kpoints": (_int, [_vp, _vp, _vp, _i64, _int, _i64]),
     "chfsi_density": (_int, [_vp, _vp, _i64, _int, _vp, _i64, _int, _vp, _dbl, _dbl, _vp]),
     "chfsi_set_timing": (_int, [_vp, _int]),

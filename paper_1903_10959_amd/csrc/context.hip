@@ -87,7 +87,7 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
                    &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
                    &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
                    &c->diag0, &c->minratio, &c->rscratch, &c->occ_d, &c->Kc64,
-                   &c->Kcg, &c->kshift};
+                   &c->Kcg, &c->kshift, &c->pois_kb, &c->pois_m, &c->pois_work, &c->pois_q};
   for (DevBuf *b : all) b->release();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

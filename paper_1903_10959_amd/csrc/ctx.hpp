@@ -58,6 +58,11 @@ struct chfsi_ctx {
   chfsi::DevBuf Kc64;     // periodic mesh: [A ; (k.G)^T] complex cell operator, 2 np x np
   double kvec[3] = {0, 0, 0};
   chfsi::DevBuf Kcg, kshift; // k-point group: nk cell operators and |k|^2/2 shifts
+  // Poisson: 1D band / mass tables (for the mesh they were built for), CG
+  // workspace, point charges
+  chfsi::DevBuf pois_kb, pois_m, pois_work, pois_q;
+  int pois_n = 0, pois_p = 0;
+  double pois_h = 0;
   int nk = 0;
   std::vector<double> kgroup;
   chfsi::DevBuf gram_part, Smat, dinv, Zmat, Wmat, jac_work, evals_d, resid_part, resid_d, flag, HX, diag0, minratio,

@@ -1,0 +1,429 @@
+// Electrostatics: the discrete Poisson problem (Sec. 2.4 eq.
+// phiTotDiscreteSolve) with homogeneous Dirichlet conditions, solved by the
+// Jacobi-preconditioned conjugate-gradient method the paper uses for it
+// (Sec. 3.2, matrix-free operator).
+//
+//   A phi = f,  A = 1/(4 pi) int grad N_i . grad N_j,  f = M rho + point charges.
+//
+// On the uniform Cartesian GLL mesh the assembled stiffness is the Kronecker
+// sum k (+) k (+) k weighted by the diagonal 1D masses:
+//   (A x)(I,J,K) = s [ m_J m_K sum_I' k(I,I') x(I',J,K) + m_I m_K sum_J' k(J,J') x(I,J',K)
+//                    + m_I m_J sum_K' k(K,K') x(I,J,K') ],   s = 1/(4 pi),
+// k the assembled 1D Laplacian stiffness (band half-width p), m the 1D GLL
+// mass.  This is the matrix-free operator in its assembled form, applied as a
+// blocked stencil that reads x about once from HBM and writes y once (16 bytes
+// per DoF).  Per CG iteration: the
+// product fused with the partial p.q, one kernel for x, r, z and the partial
+// r.z, r.r, one for the new direction, and two single-work-group reductions
+// in a fixed order that keep alpha and beta on the device.  The host reads
+// r.r every few iterations to stop.
+#include "common.hpp"
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+#include <cmath>
+#include <map>
+#include <vector>
+
+namespace chfsi {
+
+static constexpr int PB = 256;              // threads per work-group
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_FF, S_NSCAL };
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = PB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = sh[0];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double poisson_diag(const double *__restrict__ kb, const double *__restrict__ m, int p,
+                                               int I, int J, int K, double s) {
+  const int bw = 2 * p + 1;
+  return s * (kb[I * bw + p] * m[J] * m[K] + m[I] * kb[J * bw + p] * m[K] + m[I] * m[J] * kb[K * bw + p]);
+}
+
+// y = A x with 2.5D blocking: work-group = 64 consecutive I (one wave) x TY
+// rows J, marching over KB planes K.  Per plane the work-group stages the
+// plane's (TX + 2P) x (TY + 2P) halo tile of x in LDS (the x- and y-direction
+// neighbours), and each thread keeps its z-window of 2P + 1 values in
+// registers, so an output costs about 6 global loads instead of 3 (2P + 1).
+// The band coefficients of the tile's I and J rows sit in LDS too.
+// Grid (ceil(n/TX), ceil(n/TY), ceil(n/KB)); part[linear block] = the block's
+// sum of x . y over its outputs (when part is given).
+constexpr int TX = 64, TY = 4, KB = 8;
+template <int P>
+__global__ __launch_bounds__(PB) void poisson_apply_kernel(const double *__restrict__ x, double *__restrict__ y,
+                                                           const double *__restrict__ kb, const double *__restrict__ m,
+                                                           int n, double s, double *__restrict__ part) {
+  constexpr int BW = 2 * P + 1, WX = TX + 2 * P, WY = TY + 2 * P;
+  __shared__ double sh[PB];
+  __shared__ double xs[WY][WX];
+  __shared__ double kx[TX][BW], ky[TY][BW];
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> 6;
+  const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TY, K0 = blockIdx.z * KB;
+  const int I = I0 + tx, J = J0 + ty;
+  const int64_t n2 = (int64_t)n * n;
+  for (int e = threadIdx.x; e < TX * BW; e += PB) {
+    const int i = I0 + e / BW;
+    kx[e / BW][e % BW] = i < n ? kb[(int64_t)i * BW + e % BW] : 0.0;
+  }
+  for (int e = threadIdx.x; e < TY * BW; e += PB) {
+    const int j = J0 + e / BW;
+    ky[e / BW][e % BW] = j < n ? kb[(int64_t)j * BW + e % BW] : 0.0;
+  }
+  const bool live = I < n && J < n;
+  const double mI = live ? m[I] : 0.0, mJ = live ? m[J] : 0.0;
+  // z-window: x(I, J, K - P .. K + P), zero outside the mesh (Dirichlet)
+  double win[BW];
+  const int64_t col = (int64_t)I + (int64_t)n * J;
+#pragma unroll
+  for (int d = 0; d < BW; ++d) {
+    const int k = K0 - P + d - 1;                  // shifted in at the first plane
+    win[d] = (live && k >= 0 && k < n) ? x[col + k * n2] : 0.0;
+  }
+  // the plane tile is loaded into registers one plane ahead (its latency
+  // hides behind the current plane's sums), then stored to LDS
+  constexpr int NTL = (WY * WX + PB - 1) / PB;    // tile values per thread
+  double treg[NTL];
+  double wnext;
+  auto load_plane = [&](int K) {
+#pragma unroll
+    for (int u = 0; u < NTL; ++u) {
+      const int e = threadIdx.x + u * PB;
+      const int r = e / WX, cc = e - r * WX;
+      const int i = I0 - P + cc, j = J0 - P + r;
+      treg[u] = (e < WY * WX && i >= 0 && i < n && j >= 0 && j < n) ? x[(int64_t)i + (int64_t)n * j + K * n2] : 0.0;
+    }
+    const int k = K + P;
+    wnext = (live && k < n) ? x[col + k * n2] : 0.0;
+  };
+  double dot = 0;
+  const int K1 = min(K0 + KB, n);
+  load_plane(K0);
+  for (int K = K0; K < K1; ++K) {
+    __syncthreads();                               // previous plane's tile consumed
+#pragma unroll
+    for (int u = 0; u < NTL; ++u) {
+      const int e = threadIdx.x + u * PB;
+      if (e < WY * WX) xs[e / WX][e % WX] = treg[u];
+    }
+#pragma unroll
+    for (int d = 0; d < BW - 1; ++d) win[d] = win[d + 1];
+    win[BW - 1] = wnext;
+    __syncthreads();
+    if (K + 1 < K1) load_plane(K + 1);
+    if (live) {
+      double sx = 0, sy = 0, sz = 0;
+      const double *kz = kb + (int64_t)K * BW;
+#pragma unroll
+      for (int d = 0; d < BW; ++d) {
+        sx += kx[tx][d] * xs[ty + P][tx + d];
+        sy += ky[ty][d] * xs[ty + d][tx + P];
+        sz += kz[d] * win[d];
+      }
+      const double mK = m[K];
+      const double v = s * (mJ * mK * sx + mI * mK * sy + mI * mJ * sz);
+      const int64_t idx = col + K * n2;
+      y[idx] = v;
+      dot += xs[ty + P][tx + P] * v;
+    }
+  }
+  if (part) {
+    const double b = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = b;
+  }
+}
+
+// x += alpha p, r -= alpha q, z = r / diag(A); partials of r.z and r.r
+__global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__ x, double *__restrict__ r,
+                                                            double *__restrict__ z, const double *__restrict__ pv,
+                                                            const double *__restrict__ q,
+                                                            const double *__restrict__ dinv, int64_t nd,
+                                                            const double *__restrict__ scal,
+                                                            double *__restrict__ part_rz, double *__restrict__ part_rr) {
+  __shared__ double sh[PB];
+  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
+  double rz = 0, rr = 0;
+  if (idx < nd) {
+    const double alpha = scal[S_ALPHA];
+    x[idx] += alpha * pv[idx];
+    const double rv = r[idx] - alpha * q[idx];
+    r[idx] = rv;
+    const double zv = rv * dinv[idx];
+    z[idx] = zv;
+    rz = rv * zv;
+    rr = rv * rv;
+  }
+  const double a = block_sum(rz, sh);
+  const double b = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = a;
+    part_rr[blockIdx.x] = b;
+  }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(PB) void poisson_dir_kernel(double *__restrict__ pv, const double *__restrict__ z,
+                                                         const double *__restrict__ scal, int64_t nd) {
+  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
+  if (idx < nd) pv[idx] = z[idx] + scal[S_BETA] * pv[idx];
+}
+
+// Setup: f = M rho (M = 1/minv^2) into r0's place; r = f - A x (q = A x given),
+// z = r / diag, p = z; partials of r.z, r.r and f.f.
+__global__ __launch_bounds__(PB) void poisson_init_kernel(const double *__restrict__ f, const double *__restrict__ q,
+                                                          double *__restrict__ r, double *__restrict__ z,
+                                                          double *__restrict__ pv, double *__restrict__ dinv,
+                                                          const double *__restrict__ kb,
+                                                          const double *__restrict__ m, int n, int p, double s,
+                                                          double *__restrict__ part_rz, double *__restrict__ part_rr,
+                                                          double *__restrict__ part_ff) {
+  __shared__ double sh[PB];
+  const int64_t nd = (int64_t)n * n * n;
+  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
+  double rz = 0, rr = 0, ff = 0;
+  if (idx < nd) {
+    const int I = (int)(idx % n), J = (int)((idx / n) % n), K = (int)(idx / ((int64_t)n * n));
+    const double fv = f[idx];
+    const double rv = fv - q[idx];
+    const double di = 1.0 / poisson_diag(kb, m, p, I, J, K, s);
+    dinv[idx] = di;
+    const double zv = rv * di;
+    r[idx] = rv;
+    z[idx] = zv;
+    pv[idx] = zv;
+    rz = rv * zv;
+    rr = rv * rv;
+    ff = fv * fv;
+  }
+  const double a = block_sum(rz, sh);
+  const double b = block_sum(rr, sh);
+  const double c = block_sum(ff, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = a;
+    part_rr[blockIdx.x] = b;
+    part_ff[blockIdx.x] = c;
+  }
+}
+
+// f = M rho, M = 1 / minv^2
+__global__ __launch_bounds__(PB) void poisson_rhs_kernel(const double *__restrict__ rho,
+                                                         const double *__restrict__ minv, double *__restrict__ f,
+                                                         int64_t nd) {
+  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
+  if (idx < nd) f[idx] = rho[idx] / (minv[idx] * minv[idx]);
+}
+
+// point charges on their nodes (distinct dofs)
+__global__ __launch_bounds__(PB) void poisson_charges_kernel(double *__restrict__ f, const int64_t *__restrict__ dofs,
+                                                             const double *__restrict__ q, int nq) {
+  const int i = blockIdx.x * PB + threadIdx.x;
+  if (i < nq) f[dofs[i]] += q[i];
+}
+
+// Fixed-order sums of the partials, then the scalar recurrences:
+// mode 0: pq = sum a; alpha = rz / pq.
+// mode 1: rz' = sum a, rr = sum b; beta = rz' / rz; rz = rz'.
+// mode 2 (setup): rz = sum a, rr = sum b, ff = sum c.
+__global__ __launch_bounds__(PB) void poisson_reduce_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                                                            const double *__restrict__ c, int nparts, int mode,
+                                                            double *__restrict__ scal) {
+  __shared__ double sh[PB];
+  double sa = 0, sb = 0, sc = 0;
+  for (int i = threadIdx.x; i < nparts; i += PB) {
+    sa += a[i];
+    if (mode >= 1) sb += b[i];
+    if (mode == 2) sc += c[i];
+  }
+  sa = block_sum(sa, sh);
+  if (mode >= 1) sb = block_sum(sb, sh);
+  if (mode == 2) sc = block_sum(sc, sh);
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      scal[S_PQ] = sa;
+      scal[S_ALPHA] = sa != 0 ? scal[S_RZ] / sa : 0.0;
+    } else if (mode == 1) {
+      scal[S_BETA] = scal[S_RZ] != 0 ? sa / scal[S_RZ] : 0.0;
+      scal[S_RZ] = sa;
+      scal[S_RR] = sb;
+    } else {
+      scal[S_RZ] = sa;
+      scal[S_RR] = sb;
+      scal[S_FF] = sc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+// 1D Laplacian stiffness (band, half-width p) and GLL mass on the interior
+// nodes, assembled from the reference matrices.
+static void poisson_tables(const MeshTables &M, std::vector<double> &kb, std::vector<double> &m1) {
+  const int p = M.p, q = M.q, n = M.n, n1 = M.n_el * p + 1, bw = 2 * p + 1;
+  std::vector<double> K((size_t)n1 * n1, 0.0), mm(n1, 0.0);
+  for (int e = 0; e < M.n_el; ++e)
+    for (int a = 0; a < q; ++a) {
+      mm[e * p + a] += (M.h / 2.0) * M.w[a];
+      for (int b = 0; b < q; ++b) K[(size_t)(e * p + a) * n1 + (e * p + b)] += (2.0 / M.h) * M.K1[(size_t)a * q + b];
+    }
+  kb.assign((size_t)n * bw, 0.0);
+  m1.resize(n);
+  for (int i = 0; i < n; ++i) {
+    m1[i] = mm[i + 1];
+    for (int d = -p; d <= p; ++d) {
+      const int j = i + d;
+      if (j >= 0 && j < n) kb[(size_t)i * bw + d + p] = K[(size_t)(i + 1) * n1 + (j + 1)];
+    }
+  }
+}
+
+static int poisson_ready(chfsi_ctx *c) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (c->device < 0) return fail(c, CHFSI_ERR_STATE, "host-only context: no device work");
+  if (!c->has_mesh) return fail(c, CHFSI_ERR_STATE, "poisson: set_mesh first");
+  if (c->mesh.periodic)
+    return fail(c, CHFSI_ERR_STATE, "poisson: the periodic cell needs a neutral charge (not supported)");
+  if (int r = set_dev(c)) return r;
+  const MeshTables &M = c->mesh;
+  const size_t bw = 2 * M.p + 1;
+  if (c->pois_n != M.n || c->pois_p != M.p || c->pois_h != M.h) {
+    std::vector<double> kb, m1;
+    poisson_tables(M, kb, m1);
+    HIPCHK(c, c->pois_kb.ensure(kb.size() * sizeof(double)));
+    HIPCHK(c, c->pois_m.ensure(m1.size() * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(c->pois_kb.p, kb.data(), (size_t)M.n * bw * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pois_m.p, m1.data(), m1.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->pois_n = M.n;
+    c->pois_p = M.p;
+    c->pois_h = M.h;
+  }
+  return 0;
+}
+
+static const double kInv4Pi = 0.25 / 3.14159265358979323846;
+
+static dim3 apply_grid(int n) {
+  return dim3((unsigned)((n + TX - 1) / TX), (unsigned)((n + TY - 1) / TY), (unsigned)((n + KB - 1) / KB));
+}
+
+// y = A x (part: per-work-group x . y, when given); -1 for an unsupported degree
+static int poisson_apply_launch(const MeshTables &M, const double *x, double *y, const double *kb, const double *m,
+                                double *part, hipStream_t s) {
+  const dim3 g = apply_grid(M.n), b(PB);
+  switch (M.p) {
+#define CHFSI_POIS_P(P)                                                                                  \
+  case P:                                                                                                \
+    hipLaunchKernelGGL((poisson_apply_kernel<P>), g, b, 0, s, x, y, kb, m, M.n, kInv4Pi, part);          \
+    return 0;
+    CHFSI_POIS_P(1) CHFSI_POIS_P(2) CHFSI_POIS_P(3) CHFSI_POIS_P(4) CHFSI_POIS_P(5) CHFSI_POIS_P(6)
+    CHFSI_POIS_P(7)
+#undef CHFSI_POIS_P
+    default: return -1;
+  }
+}
+
+}  // namespace chfsi
+
+using namespace chfsi;
+
+extern "C" int chfsi_poisson_apply(chfsi_ctx *c, const double *x, double *y) {
+  if (int r = poisson_ready(c)) return r;
+  if (!x || !y || x == y) return fail(c, CHFSI_ERR_ARG, "poisson_apply: x and y must be separate device arrays");
+  if (poisson_apply_launch(c->mesh, x, y, c->pois_kb.as<double>(), c->pois_m.as<double>(), nullptr, c->stream))
+    return fail(c, CHFSI_ERR_ARG, "poisson_apply: degree p must be in 1..7");
+  HIPCHK(c, hipGetLastError());
+  return 0;
+}
+
+extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges, const int64_t *charge_dofs,
+                                   const double *charges, double *phi, double tol, int max_iter, int *iters,
+                                   double *rel_resid) {
+  if (int r = poisson_ready(c)) return r;
+  const MeshTables &M = c->mesh;
+  const int64_t nd = M.n_dof;
+  if (!rho || !phi || !(tol > 0) || max_iter < 0 || ncharges < 0 || (ncharges > 0 && (!charge_dofs || !charges)))
+    return fail(c, CHFSI_ERR_ARG, "poisson_solve: bad arguments");
+  if (M.p < 1 || M.p > 7) return fail(c, CHFSI_ERR_ARG, "poisson_solve: degree p must be in 1..7");
+  // point charges: combined per node on the host, so the device adds each once
+  std::map<int64_t, double> qmap;
+  for (int i = 0; i < ncharges; ++i) {
+    if (charge_dofs[i] < 0 || charge_dofs[i] >= nd || !std::isfinite(charges[i]))
+      return fail(c, CHFSI_ERR_ARG, "poisson_solve: charge dof out of range or non-finite charge");
+    qmap[charge_dofs[i]] += charges[i];
+  }
+  const int64_t nb = (nd + PB - 1) / PB;           // element-wise grids
+  const dim3 ga = apply_grid(M.n);
+  const int64_t na = (int64_t)ga.x * ga.y * ga.z;  // product grid
+  const int64_t npart = nb > na ? nb : na;
+  // workspace: f, r, z, p, q, 1/diag(A) (nd each), partials (3 npart), scalars
+  HIPCHK(c, c->pois_work.ensure((size_t)(6 * nd + 3 * npart + S_NSCAL) * sizeof(double)));
+  double *f = c->pois_work.as<double>(), *r = f + nd, *z = r + nd, *pv = z + nd, *q = pv + nd, *dinv = q + nd;
+  double *pa = dinv + nd, *pb = pa + npart, *pc = pb + npart, *scal = pc + npart;
+  const double *kb = c->pois_kb.as<double>(), *m = c->pois_m.as<double>();
+  const dim3 grid((unsigned)nb), block(PB);
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(poisson_rhs_kernel, grid, block, 0, s, rho, c->minv64.as<double>(), f, nd);
+  if (!qmap.empty()) {
+    std::vector<int64_t> qd;
+    std::vector<double> qv;
+    for (auto &e : qmap) {
+      qd.push_back(e.first);
+      qv.push_back(e.second);
+    }
+    HIPCHK(c, c->pois_q.ensure(qd.size() * (sizeof(int64_t) + sizeof(double))));
+    int64_t *dq = c->pois_q.as<int64_t>();
+    double *vq = reinterpret_cast<double *>(dq + qd.size());
+    HIPCHK(c, hipMemcpyAsync(dq, qd.data(), qd.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(vq, qv.data(), qv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(poisson_charges_kernel, dim3((unsigned)((qd.size() + PB - 1) / PB)), block, 0, s, f, dq, vq,
+                       (int)qd.size());
+    HIPCHK(c, hipStreamSynchronize(s));            // the host staging vectors go out of scope
+  }
+  poisson_apply_launch(M, phi, q, kb, m, nullptr, s);
+  hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
+                     pc);
+  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)nb, 2, scal);
+  double hs[S_NSCAL];
+  HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const double ff = hs[S_FF];
+  double rr = hs[S_RR];
+  int it = 0;
+  constexpr int CHECK = 4;                          // iterations between host reads of r.r
+  const double stop = tol * tol * ff;
+  while (rr > stop && it < max_iter) {
+    poisson_apply_launch(M, pv, q, kb, m, pa, s);
+    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)na, 0, scal);
+    hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pa, pb);
+    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)nb, 1, scal);
+    ++it;
+    if (it % CHECK == 0 || it == max_iter) {
+      HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      rr = hs[S_RR];
+      if (rr <= stop) break;
+    }
+    hipLaunchKernelGGL(poisson_dir_kernel, grid, block, 0, s, pv, z, scal, nd);
+  }
+  // the true residual of the returned phi
+  poisson_apply_launch(M, phi, q, kb, m, nullptr, s);
+  hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
+                     pc);
+  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)nb, 2, scal);
+  HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, hipGetLastError());
+  if (iters) *iters = it;
+  const double res = ff > 0 ? std::sqrt(hs[S_RR] / ff) : 0.0;
+  if (rel_resid) *rel_resid = res;
+  return res <= tol ? 0 : CHFSI_WARN_NOT_CONVERGED;
+}

@@ -115,3 +115,27 @@ def test_apply_complex_full_size_sampled_columns():
     del X, Y
     torch.cuda.empty_cache()
     c.close()
+
+
+def test_poisson_full_size_large_p6_mesh():
+    """Jacobi-PCG on the large_p6 mesh (2,924,207 DoFs): the relative residual
+    of the returned potential, recomputed on the CPU through the oracle's
+    Kronecker form of the operator, meets the tolerance."""
+    import torch
+    import paper_1903_10959_amd as P
+    from oracle import poisson
+    prob = workload.PROBLEMS["large_p6"]
+    c = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p)
+    xyz = c.dof_coords()
+    rho = -workload.eval_wells(workload.problem_wells(prob), xyz)
+    out = c.poisson_solve(torch.from_numpy(rho).to("cuda:0"), charges=[(123456, -4.0)], tol=1e-10)
+    assert out["converged"]
+    phi = out["phi"].cpu().numpy()
+    M = fem.mass_diag_kron(prob.L, prob.n_el, prob.p)
+    A1 = fem.operator_1d(prob.L, prob.n_el, prob.p)
+    sq = np.sqrt(M)
+    Aphi = sq * fem.apply_kron(A1, np.zeros_like(phi), sq * phi) / (2 * np.pi)   # K_half / (2 pi)
+    f = poisson.load_vector(M, rho, [123456], [-4.0])
+    rel = np.linalg.norm(f - Aphi) / np.linalg.norm(f)
+    assert rel < 2e-10, rel
+    c.close()
