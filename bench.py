@@ -512,7 +512,7 @@ def main():
                          "the reference for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only; there is no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 

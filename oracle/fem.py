@@ -9,7 +9,7 @@ Follows the paper's Sec. 2.4 (discrete Kohn-Sham equations):
 * mass matrix        M_jk = int N_j N_k, made diagonal by GLL quadrature;
 * standard form      Htilde = M^-1/2 H M^-1/2  (eq. hep), eigenvectors psi_hat = M^-1/2 psi_tilde.
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
 
 * all three integrals use the (p+1)^3-point GLL rule collocated with the nodes,
   so the potential term is diag(M_j V(x_j)) and Htilde = M^-1/2 K M^-1/2 + diag(V);
