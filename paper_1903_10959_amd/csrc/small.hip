@@ -285,13 +285,19 @@ __device__ __forceinline__ void jrot(const double *A, int n, int p, int q, doubl
 // block round pairs the blocks in round-robin order (as the scalar method
 // pairs indices), and for every pair (I, J) of blocks
 //   1. one work-group takes the 64 x 64 submatrix S = A[I u J, I u J] into
-//      LDS and runs one cyclic sweep of plane rotations over its 64 indices,
+//      LDS and rotates it in parallel rounds of 32 disjoint plane rotations,
 //      accumulating them in R (64 x 64, orthogonal);
 //   2. A <- R^T A R tile by tile (every pair of pairs: one 64 x 64 triple
 //      product), into the other buffer;
 //   3. V <- V R in place, panel by panel.
-// A block sweep (nbp - 1 block rounds) applies every plane rotation of a
-// scalar sweep, and more, in 3 (nbp - 1) launches instead of n - 1.
+// A sweep is one block round g = 0 that rotates the pairs inside each block
+// (31 rounds of 16 pairs in I and 16 in J), then nbp - 1 block rounds g >= 1
+// (block pairing g - 1) that rotate only the pairs across I and J (32 rounds
+// (t, 32 + (t + ir) mod 32)): every index pair once per sweep, a cyclic
+// ordering, in 3 nbp launches instead of n - 1.  (Sweeping all 64 indices in
+// every block round re-rotates the pairs inside blocks nbp - 1 times per
+// sweep; checked on the host, it needs about as many sweeps for twice the
+// inner rounds.)
 static constexpr int JB = 32, J2 = 64;
 static constexpr int OFFP = 32;   // work-groups per problem in the off-norm
 
@@ -319,17 +325,34 @@ __device__ __forceinline__ int jac_find(const JacProb *__restrict__ probs, int n
 // global index of local index i (0..63) of block pair (I, J); >= n: padding
 __device__ __forceinline__ int jac_gidx(int i, int I, int J) { return i < JB ? I * JB + i : J * JB + (i - JB); }
 
+// Local pair t (0..31) of inner round ir: inside the blocks (within) or
+// across them.
+__device__ __forceinline__ void jac_pair(int t, int ir, bool within, int &p, int &q) {
+  if (within) {
+    const int h = t >> 4, u = t & 15;                // block half, pair in it
+    p = JB * h + rr_index(u, ir, JB);
+    q = JB * h + rr_index(JB - 1 - u, ir, JB);
+  } else {
+    p = t;
+    q = JB + (t + ir) % JB;
+  }
+}
+
 // 1. one sweep of the 64-index pair submatrix in LDS; R out
-__global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+// g: block round of the sweep (0: pairs inside the blocks, pairing 0;
+// g >= 1: pairs across the blocks, pairing g - 1).
+__global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__restrict__ probs, int nprob, int g) {
   __shared__ double S[J2][J2 + 1];
   __shared__ double Rs[J2][J2 + 1];
   __shared__ double cs[J2 / 2], sn[J2 / 2], tn[J2 / 2];
   const JacProb &P = probs[jac_find(probs, nprob, 0)];
-  if (r >= P.nbp - 1) return;                      // this problem's sweep is complete
+  if (g >= P.nbp) return;                          // this problem's sweep is complete
+  const int r = g == 0 ? 0 : g - 1;
+  const bool within = g == 0;
   const int k = (int)(blockIdx.x - P.first_inner);
   const int n = P.n;
   const int I = rr_index(k, r, P.nbp), J = rr_index(P.nbp - 1 - k, r, P.nbp);
-  const double *A = P.A[(P.par0 + r) & 1];
+  const double *A = P.A[(P.par0 + g) & 1];
   const int t = threadIdx.x;
   for (int e = t; e < J2 * J2; e += 1024) {
     const int i = e / J2, j = e % J2;
@@ -338,9 +361,11 @@ __global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__res
     Rs[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int ir = 0; ir < J2 - 1; ++ir) {
+  const int nround = within ? JB - 1 : JB;
+  for (int ir = 0; ir < nround; ++ir) {
     if (t < J2 / 2) {
-      const int p = rr_index(t, ir, J2), q = rr_index(J2 - 1 - t, ir, J2);
+      int p, q;
+      jac_pair(t, ir, within, p, q);
       double c = 1.0, s = 0.0, tt = 0.0;
       const double apq = S[p][q];
       if (fabs(apq) >= 1e-300) {
@@ -357,8 +382,9 @@ __global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__res
     {
       // 2x2 block (pair a rows, pair b columns), one per thread, in place
       const int a = t / (J2 / 2), b = t % (J2 / 2);
-      const int pa = rr_index(a, ir, J2), qa = rr_index(J2 - 1 - a, ir, J2);
-      const int pb = rr_index(b, ir, J2), qb = rr_index(J2 - 1 - b, ir, J2);
+      int pa, qa, pb, qb;
+      jac_pair(a, ir, within, pa, qa);
+      jac_pair(b, ir, within, pb, qb);
       if (a == b) {
         const double apq = S[pa][qa];
         S[pa][pa] -= tn[a] * apq;
@@ -414,18 +440,19 @@ __device__ __forceinline__ void jac_mm64(const double (*X)[J2 + 1], const double
 }
 
 // 2. A_next[P1 rows, P2 cols] = R_P1^T A[P1, P2] R_P2 for every pair of pairs
-__global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+__global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__restrict__ probs, int nprob, int g) {
   __shared__ double T[J2][J2 + 1], R1[J2][J2 + 1], R2[J2][J2 + 1];
   const JacProb &P = probs[jac_find(probs, nprob, 1)];
-  if (r >= P.nbp - 1) return;
+  if (g >= P.nbp) return;
+  const int r = g == 0 ? 0 : g - 1;
   const int np2 = P.nbp / 2;
   const int tile = (int)(blockIdx.x - P.first_tile);
   const int k1 = tile / np2, k2 = tile % np2;
   const int n = P.n;
   const int I1 = rr_index(k1, r, P.nbp), J1 = rr_index(P.nbp - 1 - k1, r, P.nbp);
   const int I2 = rr_index(k2, r, P.nbp), J2b = rr_index(P.nbp - 1 - k2, r, P.nbp);
-  const double *A = P.A[(P.par0 + r) & 1];
-  double *An = P.A[(P.par0 + r + 1) & 1];
+  const double *A = P.A[(P.par0 + g) & 1];
+  double *An = P.A[(P.par0 + g + 1) & 1];
   const double *Rg1 = P.R + (int64_t)k1 * J2 * J2, *Rg2 = P.R + (int64_t)k2 * J2 * J2;
   const int t = threadIdx.x;
   for (int e = t; e < J2 * J2; e += 256) {
@@ -456,10 +483,11 @@ __global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__re
 }
 
 // 3. V[panel rows, P cols] <- V[panel rows, P cols] R_P, in place
-__global__ __launch_bounds__(256) void jacobi_apply_v_kernel(const JacProb *__restrict__ probs, int nprob, int r) {
+__global__ __launch_bounds__(256) void jacobi_apply_v_kernel(const JacProb *__restrict__ probs, int nprob, int g) {
   __shared__ double T[J2][J2 + 1], Rl[J2][J2 + 1];
   const JacProb &P = probs[jac_find(probs, nprob, 2)];
-  if (r >= P.nbp - 1) return;
+  if (g >= P.nbp) return;
+  const int r = g == 0 ? 0 : g - 1;
   const int np2 = P.nbp / 2;
   const int w = (int)(blockIdx.x - P.first_panel);
   const int panel = w / np2, k = w % np2;
@@ -627,18 +655,18 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
       n_inner += np2;
       n_tile += (int64_t)np2 * np2;
       n_panel += (int64_t)((J.n + J2 - 1) / J2) * np2;
-      rmax = std::max(rmax, J.nbp - 1);
+      rmax = std::max(rmax, J.nbp);                // block rounds g = 0 .. nbp - 1
       run.push_back(J);
-      J.par0 ^= (J.nbp - 1) & 1;                  // buffer holding A after this sweep
+      J.par0 ^= J.nbp & 1;                         // buffer holding A after this sweep (nbp is even)
     }
     if (run.empty()) break;
     if (hipMemcpyAsync(dtab, run.data(), run.size() * sizeof(JacProb), hipMemcpyHostToDevice, s) != hipSuccess)
       return -1;
     const int nr = (int)run.size();
-    for (int r = 0; r < rmax; ++r) {
-      hipLaunchKernelGGL(jacobi_inner_kernel, dim3((unsigned)n_inner), dim3(1024), 0, s, dtab, nr, r);
-      hipLaunchKernelGGL(jacobi_apply_a_kernel, dim3((unsigned)n_tile), dim3(256), 0, s, dtab, nr, r);
-      hipLaunchKernelGGL(jacobi_apply_v_kernel, dim3((unsigned)n_panel), dim3(256), 0, s, dtab, nr, r);
+    for (int g = 0; g < rmax; ++g) {
+      hipLaunchKernelGGL(jacobi_inner_kernel, dim3((unsigned)n_inner), dim3(1024), 0, s, dtab, nr, g);
+      hipLaunchKernelGGL(jacobi_apply_a_kernel, dim3((unsigned)n_tile), dim3(256), 0, s, dtab, nr, g);
+      hipLaunchKernelGGL(jacobi_apply_v_kernel, dim3((unsigned)n_panel), dim3(256), 0, s, dtab, nr, g);
     }
     // the table is rewritten next sweep: this sweep's launches must have read it
     if (hipStreamSynchronize(s) != hipSuccess) return -1;
