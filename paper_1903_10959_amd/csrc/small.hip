@@ -416,26 +416,22 @@ __global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__res
   for (int e = t; e < J2 * J2; e += 1024) Rg[e] = Rs[e / J2][e % J2];
 }
 
-// C = op(X) Y for 64 x 64 LDS operands, 16 outputs (4 x 4) per thread of 256;
-// TRANS: X used transposed
+// C = op(X) Y for 64 x 64 LDS operands on FP64 MFMA (16x16x4): wave w of 4
+// computes rows 16 w .. 16 w + 15 as four 16 x 16 tiles along the columns;
+// c[b][q] is row 16 w + acc_row(kq, q), column 16 b + (lane & 15).
+// TRANS: X used transposed.
 template <bool TRANS>
-__device__ __forceinline__ void jac_mm64(const double (*X)[J2 + 1], const double (*Y)[J2 + 1], double (&c)[4][4],
-                                         int i0, int j0) {
+__device__ __forceinline__ void jac_mm64(const double (*X)[J2 + 1], const double (*Y)[J2 + 1], v4d (&c)[4], int w,
+                                         int lane) {
+  const int j = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) c[u][v] = 0.0;
+  for (int b = 0; b < 4; ++b) c[b] = v4d{0, 0, 0, 0};
 #pragma unroll 4
-  for (int kk = 0; kk < J2; ++kk) {
-    double x[4], y[4];
+  for (int kk = 0; kk < J2; kk += 4) {
+    const int k = kk + kq;
+    const double a = TRANS ? X[k][16 * w + j] : X[16 * w + j][k];   // A[16 w + j][k]
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = TRANS ? X[kk][i0 + 16 * u] : X[i0 + 16 * u][kk];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) y[v] = Y[kk][j0 + 16 * v];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) c[u][v] += x[u] * y[v];
+    for (int b = 0; b < 4; ++b) c[b] = mfma16x4(a, Y[k][16 * b + j], c[b]);
   }
 }
 
@@ -463,22 +459,22 @@ __global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__re
     R2[i][j] = Rg2[e];
   }
   __syncthreads();
-  const int i0 = t / 16, j0 = t % 16;
-  double c[4][4];
-  jac_mm64<false>(T, R2, c, i0, j0);               // U = T R2
+  const int wv = t >> 6, lane = t & 63, jl = lane & 15, kq = lane >> 4;
+  v4d c[4];
+  jac_mm64<false>(T, R2, c, wv, lane);             // U = T R2
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) T[i0 + 16 * u][j0 + 16 * v] = c[u][v];
+    for (int q = 0; q < 4; ++q) T[16 * wv + acc_row<double>(kq, q)][16 * b + jl] = c[b][q];
   __syncthreads();
-  jac_mm64<true>(R1, T, c, i0, j0);                // R1^T U
+  jac_mm64<true>(R1, T, c, wv, lane);              // R1^T U
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gi = jac_gidx(i0 + 16 * u, I1, J1), gj = jac_gidx(j0 + 16 * v, I2, J2b);
-      if (gi < n && gj < n) An[(int64_t)gi * n + gj] = c[u][v];
+    for (int q = 0; q < 4; ++q) {
+      const int gi = jac_gidx(16 * wv + acc_row<double>(kq, q), I1, J1), gj = jac_gidx(16 * b + jl, I2, J2b);
+      if (gi < n && gj < n) An[(int64_t)gi * n + gj] = c[b][q];
     }
 }
 
@@ -503,20 +499,18 @@ __global__ __launch_bounds__(256) void jacobi_apply_v_kernel(const JacProb *__re
     Rl[i][j] = Rg[e];
   }
   __syncthreads();
-  const int i0 = t / 16, j0 = t % 16;
-  double c[4][4];
-  jac_mm64<false>(T, Rl, c, i0, j0);
+  const int wv = t >> 6, lane = t & 63, jl = lane & 15, kq = lane >> 4;
+  v4d c[4];
+  jac_mm64<false>(T, Rl, c, wv, lane);
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gr = row0 + i0 + 16 * u, gj = jac_gidx(j0 + 16 * v, I, J);
-      if (gr < n && gj < n) P.V[(int64_t)gr * n + gj] = c[u][v];
+    for (int q = 0; q < 4; ++q) {
+      const int gr = row0 + 16 * wv + acc_row<double>(kq, q), gj = jac_gidx(16 * b + jl, I, J);
+      if (gr < n && gj < n) P.V[(int64_t)gr * n + gj] = c[b][q];
     }
 }
 
-// out[2k] = sum of squares off the diagonal of problem k's current matrix,
-// out[2k+1] = on the diagonal (one work-group per problem)
 // Squared off-diagonal and diagonal Frobenius norms of each problem's A, as
 // OFFP partial sums per problem (work-group part takes rows part*4 + wave,
 // stepping by 4 OFFP); the host adds the partials in a fixed order.
