@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
   typedef typename std::conditional<MODE == 1 || MODE == 3, float, double>::type CT;   // product type
   typedef typename acc4<CT>::type acc_t;
   typedef CT lds_vec_t __attribute__((ext_vector_type(VEC)));
-  constexpr int KR = 16;                          // rows per chunk
+  constexpr int KR = sizeof(CT) == 4 ? 32 : 16;   // rows per chunk (FP32 chunks: same LDS bytes)
   constexpr int PT = KR * GT / (256 * VEC);       // vectors per thread per operand
   // staged in the product type: FP32 modes round once, at the LDS store
   __shared__ __align__(16) CT As[2][KR][GT];
