@@ -21,6 +21,7 @@
 #include "ctx.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <vector>
@@ -28,12 +29,15 @@
 namespace chfsi {
 
 static constexpr int PB = 256;              // threads per work-group
+static constexpr int PR = 1024;             // threads of the final reductions
+static constexpr int MAXG = 2048;           // element-wise grids: at most this many work-groups (grid-stride)
 enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_FF, S_NSCAL };
 
+template <int NT = PB>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   sh[threadIdx.x] = v;
   __syncthreads();
-  for (int w = PB / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
@@ -48,32 +52,32 @@ __device__ __forceinline__ double poisson_diag(const double *__restrict__ kb, co
   return s * (kb[I * bw + p] * m[J] * m[K] + m[I] * kb[J * bw + p] * m[K] + m[I] * m[J] * kb[K * bw + p]);
 }
 
-// y = A x with 2.5D blocking: work-group = 64 consecutive I (one wave) x TY
-// rows J, marching over KB planes K.  Per plane the work-group stages the
+// y = A x with 2.5D blocking: work-group = 64 consecutive I (one wave per row)
+// x TY rows J, marching over KB planes K.  Per plane the work-group stages the
 // plane's (TX + 2P) x (TY + 2P) halo tile of x in LDS (the x- and y-direction
 // neighbours), and each thread keeps its z-window of 2P + 1 values in
 // registers, so an output costs about 6 global loads instead of 3 (2P + 1).
 // The band coefficients of the tile's I and J rows sit in LDS too.
 // Grid (ceil(n/TX), ceil(n/TY), ceil(n/KB)); part[linear block] = the block's
 // sum of x . y over its outputs (when part is given).
-constexpr int TX = 64, TY = 4, KB = 8;
+constexpr int TX = 64, TY = 4, KB = 8, PA = TX * TY;
 template <int P>
-__global__ __launch_bounds__(PB) void poisson_apply_kernel(const double *__restrict__ x, double *__restrict__ y,
+__global__ __launch_bounds__(PA) void poisson_apply_kernel(const double *__restrict__ x, double *__restrict__ y,
                                                            const double *__restrict__ kb, const double *__restrict__ m,
                                                            int n, double s, double *__restrict__ part) {
   constexpr int BW = 2 * P + 1, WX = TX + 2 * P, WY = TY + 2 * P;
-  __shared__ double sh[PB];
+  __shared__ double sh[PA];
   __shared__ double xs[WY][WX];
   __shared__ double kx[TX][BW], ky[TY][BW];
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> 6;
   const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TY, K0 = blockIdx.z * KB;
   const int I = I0 + tx, J = J0 + ty;
   const int64_t n2 = (int64_t)n * n;
-  for (int e = threadIdx.x; e < TX * BW; e += PB) {
+  for (int e = threadIdx.x; e < TX * BW; e += PA) {
     const int i = I0 + e / BW;
     kx[e / BW][e % BW] = i < n ? kb[(int64_t)i * BW + e % BW] : 0.0;
   }
-  for (int e = threadIdx.x; e < TY * BW; e += PB) {
+  for (int e = threadIdx.x; e < TY * BW; e += PA) {
     const int j = J0 + e / BW;
     ky[e / BW][e % BW] = j < n ? kb[(int64_t)j * BW + e % BW] : 0.0;
   }
@@ -88,14 +92,15 @@ __global__ __launch_bounds__(PB) void poisson_apply_kernel(const double *__restr
     win[d] = (live && k >= 0 && k < n) ? x[col + k * n2] : 0.0;
   }
   // the plane tile is loaded into registers one plane ahead (its latency
-  // hides behind the current plane's sums), then stored to LDS
-  constexpr int NTL = (WY * WX + PB - 1) / PB;    // tile values per thread
+  // hides behind the current plane's sums), then stored to LDS (two planes
+  // ahead measured no faster: the extra registers cost occupancy)
+  constexpr int NTL = (WY * WX + PA - 1) / PA;    // tile values per thread
   double treg[NTL];
   double wnext;
   auto load_plane = [&](int K) {
 #pragma unroll
     for (int u = 0; u < NTL; ++u) {
-      const int e = threadIdx.x + u * PB;
+      const int e = threadIdx.x + u * PA;
       const int r = e / WX, cc = e - r * WX;
       const int i = I0 - P + cc, j = J0 - P + r;
       treg[u] = (e < WY * WX && i >= 0 && i < n && j >= 0 && j < n) ? x[(int64_t)i + (int64_t)n * j + K * n2] : 0.0;
@@ -110,7 +115,7 @@ __global__ __launch_bounds__(PB) void poisson_apply_kernel(const double *__restr
     __syncthreads();                               // previous plane's tile consumed
 #pragma unroll
     for (int u = 0; u < NTL; ++u) {
-      const int e = threadIdx.x + u * PB;
+      const int e = threadIdx.x + u * PA;
       if (e < WY * WX) xs[e / WX][e % WX] = treg[u];
     }
 #pragma unroll
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(PB) void poisson_apply_kernel(const double *__restr
     }
   }
   if (part) {
-    const double b = block_sum(dot, sh);
+    const double b = block_sum<PA>(dot, sh);
     if (threadIdx.x == 0) part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = b;
   }
 }
@@ -148,17 +153,16 @@ __global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__
                                                             const double *__restrict__ scal,
                                                             double *__restrict__ part_rz, double *__restrict__ part_rr) {
   __shared__ double sh[PB];
-  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
   double rz = 0, rr = 0;
-  if (idx < nd) {
-    const double alpha = scal[S_ALPHA];
+  const double alpha = scal[S_ALPHA];
+  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB) {
     x[idx] += alpha * pv[idx];
     const double rv = r[idx] - alpha * q[idx];
     r[idx] = rv;
     const double zv = rv * dinv[idx];
     z[idx] = zv;
-    rz = rv * zv;
-    rr = rv * rv;
+    rz += rv * zv;
+    rr += rv * rv;
   }
   const double a = block_sum(rz, sh);
   const double b = block_sum(rr, sh);
@@ -171,8 +175,9 @@ __global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__
 // p = z + beta p
 __global__ __launch_bounds__(PB) void poisson_dir_kernel(double *__restrict__ pv, const double *__restrict__ z,
                                                          const double *__restrict__ scal, int64_t nd) {
-  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
-  if (idx < nd) pv[idx] = z[idx] + scal[S_BETA] * pv[idx];
+  const double beta = scal[S_BETA];
+  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB)
+    pv[idx] = z[idx] + beta * pv[idx];
 }
 
 // Setup: f = M rho (M = 1/minv^2) into r0's place; r = f - A x (q = A x given),
@@ -186,9 +191,8 @@ __global__ __launch_bounds__(PB) void poisson_init_kernel(const double *__restri
                                                           double *__restrict__ part_ff) {
   __shared__ double sh[PB];
   const int64_t nd = (int64_t)n * n * n;
-  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
   double rz = 0, rr = 0, ff = 0;
-  if (idx < nd) {
+  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB) {
     const int I = (int)(idx % n), J = (int)((idx / n) % n), K = (int)(idx / ((int64_t)n * n));
     const double fv = f[idx];
     const double rv = fv - q[idx];
@@ -198,9 +202,9 @@ __global__ __launch_bounds__(PB) void poisson_init_kernel(const double *__restri
     r[idx] = rv;
     z[idx] = zv;
     pv[idx] = zv;
-    rz = rv * zv;
-    rr = rv * rv;
-    ff = fv * fv;
+    rz += rv * zv;
+    rr += rv * rv;
+    ff += fv * fv;
   }
   const double a = block_sum(rz, sh);
   const double b = block_sum(rr, sh);
@@ -216,8 +220,8 @@ __global__ __launch_bounds__(PB) void poisson_init_kernel(const double *__restri
 __global__ __launch_bounds__(PB) void poisson_rhs_kernel(const double *__restrict__ rho,
                                                          const double *__restrict__ minv, double *__restrict__ f,
                                                          int64_t nd) {
-  const int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x;
-  if (idx < nd) f[idx] = rho[idx] / (minv[idx] * minv[idx]);
+  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB)
+    f[idx] = rho[idx] / (minv[idx] * minv[idx]);
 }
 
 // point charges on their nodes (distinct dofs)
@@ -231,19 +235,19 @@ __global__ __launch_bounds__(PB) void poisson_charges_kernel(double *__restrict_
 // mode 0: pq = sum a; alpha = rz / pq.
 // mode 1: rz' = sum a, rr = sum b; beta = rz' / rz; rz = rz'.
 // mode 2 (setup): rz = sum a, rr = sum b, ff = sum c.
-__global__ __launch_bounds__(PB) void poisson_reduce_kernel(const double *__restrict__ a, const double *__restrict__ b,
+__global__ __launch_bounds__(PR) void poisson_reduce_kernel(const double *__restrict__ a, const double *__restrict__ b,
                                                             const double *__restrict__ c, int nparts, int mode,
                                                             double *__restrict__ scal) {
-  __shared__ double sh[PB];
+  __shared__ double sh[PR];
   double sa = 0, sb = 0, sc = 0;
-  for (int i = threadIdx.x; i < nparts; i += PB) {
+  for (int i = threadIdx.x; i < nparts; i += PR) {
     sa += a[i];
     if (mode >= 1) sb += b[i];
     if (mode == 2) sc += c[i];
   }
-  sa = block_sum(sa, sh);
-  if (mode >= 1) sb = block_sum(sb, sh);
-  if (mode == 2) sc = block_sum(sc, sh);
+  sa = block_sum<PR>(sa, sh);
+  if (mode >= 1) sb = block_sum<PR>(sb, sh);
+  if (mode == 2) sc = block_sum<PR>(sc, sh);
   if (threadIdx.x == 0) {
     if (mode == 0) {
       scal[S_PQ] = sa;
@@ -318,7 +322,7 @@ static dim3 apply_grid(int n) {
 // y = A x (part: per-work-group x . y, when given); -1 for an unsupported degree
 static int poisson_apply_launch(const MeshTables &M, const double *x, double *y, const double *kb, const double *m,
                                 double *part, hipStream_t s) {
-  const dim3 g = apply_grid(M.n), b(PB);
+  const dim3 g = apply_grid(M.n), b(PA);
   switch (M.p) {
 #define CHFSI_POIS_P(P)                                                                                  \
   case P:                                                                                                \
@@ -360,7 +364,7 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
       return fail(c, CHFSI_ERR_ARG, "poisson_solve: charge dof out of range or non-finite charge");
     qmap[charge_dofs[i]] += charges[i];
   }
-  const int64_t nb = (nd + PB - 1) / PB;           // element-wise grids
+  const int64_t nb = std::min<int64_t>((nd + PB - 1) / PB, MAXG);   // element-wise grids (grid-stride)
   const dim3 ga = apply_grid(M.n);
   const int64_t na = (int64_t)ga.x * ga.y * ga.z;  // product grid
   const int64_t npart = nb > na ? nb : na;
@@ -391,7 +395,7 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
   poisson_apply_launch(M, phi, q, kb, m, nullptr, s);
   hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
                      pc);
-  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)nb, 2, scal);
+  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, 2, scal);
   double hs[S_NSCAL];
   HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -402,9 +406,9 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
   const double stop = tol * tol * ff;
   while (rr > stop && it < max_iter) {
     poisson_apply_launch(M, pv, q, kb, m, pa, s);
-    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)na, 0, scal);
+    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)na, 0, scal);
     hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pa, pb);
-    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)nb, 1, scal);
+    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, 1, scal);
     ++it;
     if (it % CHECK == 0 || it == max_iter) {
       HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -418,7 +422,7 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
   poisson_apply_launch(M, phi, q, kb, m, nullptr, s);
   hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
                      pc);
-  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), block, 0, s, pa, pb, pc, (int)nb, 2, scal);
+  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, 2, scal);
   HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   HIPCHK(c, hipGetLastError());
