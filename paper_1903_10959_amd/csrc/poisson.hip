@@ -58,8 +58,8 @@ __device__ __forceinline__ double poisson_diag(const double *__restrict__ kb, co
 // neighbours), and each thread keeps its z-window of 2P + 1 values in
 // registers, so an output costs about 6 global loads instead of 3 (2P + 1).
 // The band coefficients of the tile's I and J rows sit in LDS too.
-// Grid (ceil(n/TX), ceil(n/TY), ceil(n/KB)); part[linear block] = the block's
-// sum of x . y over its outputs (when part is given).
+// Grid: ceil(n/TX) ceil(n/TY) ceil(n/KB) work-groups (1D, XCD-grouped);
+// part[block] = the block's sum of x . y over its outputs (when part is given).
 constexpr int TX = 64, TY = 4, KB = 8, PA = TX * TY;
 template <int P>
 __global__ __launch_bounds__(PA) void poisson_apply_kernel(const double *__restrict__ x, double *__restrict__ y,
@@ -70,7 +70,15 @@ __global__ __launch_bounds__(PA) void poisson_apply_kernel(const double *__restr
   __shared__ double xs[WY][WX];
   __shared__ double kx[TX][BW], ky[TY][BW];
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> 6;
-  const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TY, K0 = blockIdx.z * KB;
+  // XCD-grouped block order: the hardware deals consecutive work-groups to the
+  // 8 XCDs in turn; the logical index below is contiguous per XCD, and tiles
+  // adjacent in J (which share 12 of their 16 halo rows) get consecutive
+  // logical indices, so their shared rows are fetched into one L2
+  const int g = (int)gridDim.x, b = (int)blockIdx.x;
+  const int lid = (b & 7) * (g >> 3) + min(b & 7, g & 7) + (b >> 3);
+  const int gx = (n + TX - 1) / TX, gy = (n + TY - 1) / TY;
+  const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
+  const int I0 = bx * TX, J0 = by * TY, K0 = bz * KB;
   const int I = I0 + tx, J = J0 + ty;
   const int64_t n2 = (int64_t)n * n;
   for (int e = threadIdx.x; e < TX * BW; e += PA) {
@@ -140,8 +148,8 @@ __global__ __launch_bounds__(PA) void poisson_apply_kernel(const double *__restr
     }
   }
   if (part) {
-    const double b = block_sum<PA>(dot, sh);
-    if (threadIdx.x == 0) part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = b;
+    const double bsum = block_sum<PA>(dot, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = bsum;
   }
 }
 
@@ -316,7 +324,7 @@ static int poisson_ready(chfsi_ctx *c) {
 static const double kInv4Pi = 0.25 / 3.14159265358979323846;
 
 static dim3 apply_grid(int n) {
-  return dim3((unsigned)((n + TX - 1) / TX), (unsigned)((n + TY - 1) / TY), (unsigned)((n + KB - 1) / KB));
+  return dim3((unsigned)((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + KB - 1) / KB));
 }
 
 // y = A x (part: per-work-group x . y, when given); -1 for an unsupported degree
