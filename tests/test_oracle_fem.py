@@ -105,6 +105,32 @@ def test_cell_mass_volume():
         assert abs(fem.cell_mass(p, h).sum() - h ** 3) < 1e-13 * h ** 3
 
 
+@pytest.mark.parametrize("L,n_el,p", [(6.0, 1, 4), (9.0, 3, 4), (10.0, 4, 5), (7.5, 5, 2)])
+def test_mass_1d_closed_forms(L, n_el, p):
+    """The 1D GLL mass integrates constants exactly: the interior nodal masses
+    add up to L less the two wall nodes' (h/2) w_0 = h / (p (p + 1)) each;
+    a node on an element boundary carries twice the end weight, and the
+    pattern repeats with period p."""
+    m = fem.mass_1d(L, n_el, p)
+    h = L / n_el
+    assert m.shape == (n_el * p - 1,)
+    w_end = h / (p * (p + 1))
+    assert abs(m.sum() - (L - 2 * w_end)) < 1e-13 * L
+    shared = np.arange(1, n_el * p)[np.arange(1, n_el * p) % p == 0] - 1
+    np.testing.assert_allclose(m[shared], 2 * w_end, rtol=1e-14)
+    if n_el > 1:
+        np.testing.assert_allclose(m[p:], m[:-p], rtol=1e-14)
+
+
+@pytest.mark.parametrize("n_el,p", [(1, 2), (2, 3), (3, 5)])
+def test_sizes_agree_with_the_map(n_el, p):
+    s = fem.sizes(n_el, p)
+    cmap = fem.cell_dof_map(n_el, p)
+    assert cmap.shape == (s["n_cells"], s["n_loc"])
+    assert int(cmap.max()) + 1 == s["n_dof"] == s["n"] ** 3
+    assert fem.dof_coords(1.0, n_el, p).shape == (s["n_dof"], 3)
+
+
 # ---------------------------------------------------------------- numbering
 
 @pytest.mark.parametrize("n_el,p", [(1, 2), (2, 3), (4, 4), (3, 5), (4, 2)])
