@@ -27,7 +27,11 @@ f(mu + d) + f(mu - d) = 1; mu for two levels and for a spectrum symmetric
 about mu0 (closed forms); the particle count sum_j M_jj rho_j = N_e; split
 against full (the projector identity X X^T = X Q Q^T X^T); the cell-level
 formula against the nodal one on every cell; the particle-in-a-box ground
-state density against the separable product of 1D eigenvectors.
+state density against the separable product of 1D eigenvectors; the FP64
+``rayleigh_ritz_split`` against the top N_fr pairs of the full Rayleigh-Ritz.
+Its mixed form is *parity unpinned*: the paper fixes no accuracy for it (its
+accuracy table is a full-DFT comparison); its error against the FP64 form is
+measured and reported.
 """
 from __future__ import annotations
 

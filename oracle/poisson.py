@@ -23,8 +23,9 @@ Pins (tests/test_oracle_poisson.py): the manufactured solution
 phi = sin(pi x/L) sin(pi y/L) sin(pi z/L), for which rho = 3 pi phi / (4 L^2),
 is reproduced with spectral accuracy (error falling with p); A is symmetric
 positive definite and equals the Kronecker sum of 1D operators; PCG reaches
-the direct solution; the Coulomb field of a point charge matches q / r away
-from the charge and the walls.
+the direct solution; point charges obey reciprocity (the potential at j of a
+unit charge on i equals that at i of one on j, which a charge scaled by the
+nodal mass would break) and superpose.
 """
 from __future__ import annotations
 
