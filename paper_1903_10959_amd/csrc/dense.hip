@@ -105,10 +105,12 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ A,
   const int wi = wave >> 1, wj = wave & 1;
   const int j = lane & 15, kq = lane >> 4;
   auto quarter_active = [&](int qi, int qj) {
-    const bool lower = !(ti == tj && qi < qj);     // strictly upper quarter: never read
+    // strictly upper quarters and quarters wholly past the last column are never read
+    const bool inside = ti * GT + qi * 64 < n && tj * GT + qj * 64 < n;
+    const bool lower = !(ti == tj && qi < qj);
     const bool in_fr = ti * GT + qi * 64 >= fr0 && tj * GT + qj * 64 >= fr0;
-    return MODE == 0 ? lower : MODE == 1 ? !(ti == tj && qi <= qj) : MODE == 2 ? qi == qj
-         : MODE == 3 ? lower && !in_fr : lower && in_fr;
+    return inside && (MODE == 0 ? lower : MODE == 1 ? !(ti == tj && qi <= qj) : MODE == 2 ? qi == qj
+                      : MODE == 3 ? lower && !in_fr : lower && in_fr);
   };
   if (!(quarter_active(0, 0) || quarter_active(1, 0) || quarter_active(0, 1) || quarter_active(1, 1)))
     return;                                        // whole work-group idle in this mode
@@ -359,6 +361,7 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
   const int j = lane & 15, kq = lane >> 4;
   const int kend = upper ? min(n, n0 + NTL) : n;
   const int c0 = n0 + wj * 64;                   // first column of this wave
+  const bool live = c0 < nout;                   // a wave wholly past nout skips its MFMAs
   const int kdiag = MIXED ? (c0 / 64) * 64 : 0;  // mixed: k >= kdiag is the FP64 diagonal block
 
   // staging slots: X vector v -> (row v % MT, k-vector v / MT); W vector v ->
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(256) void rmul_gemm_kernel(const double *__restrict
     const int buf = kc & 1;
     if (kc + 1 < nk) load_chunk((kc + 1) * KC);
 #pragma unroll
-    for (int ks = 0; ks < KC; ks += 4) {
+    for (int ks = 0; ks < KC && live; ks += 4) {
       const int kk = ks + kq;
       double av[4], bv[4];
 #pragma unroll
