@@ -55,7 +55,7 @@ def cpu_baseline(prob, ncols: int, budget_s: float = 30.0):
             "seconds": dt}
 
 
-def profiled_traffic(tag: str):
+def profiled_traffic(tag: str, sources=("hx.hip", "common.hpp")):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary profiles/<tag>.md, or None when that summary is missing or
     the kernel source changed since the counters were taken."""
@@ -68,9 +68,9 @@ def profiled_traffic(tag: str):
     for line in open(path):
         if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
             k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
+            vals[k.strip()] = (v.split() or [""])[0]     # a trailing "(files)" note is not part of it
     csrc = os.path.join(ROOT, "paper_1903_10959_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ["hx.hip", "common.hpp"])
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in sources)
     if vals.get("kernel_source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None
     try:
@@ -339,7 +339,8 @@ def density_bench(args, prob):
            "higher_is_better": True, "vs_baseline": None, "data": "synthetic", "dtype": "f64",
            "config": {"workload": workload.fmt_problem(prob), "N_b": nb, "n_fr": n_fr, "sigma_Ha": sigma},
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                        "traffic": None, "kernel": "density_kernel", "bytes_per_launch": nbytes,
+                        "traffic": profiled_traffic(f"density_{prob.name}", ("dense.hip",)),
+                        "kernel": "density_kernel", "bytes_per_launch": nbytes,
                         "avg_launch_ms": ms},
            "ms": {"split_rr_out_of_place": 1e3 * float(np.median(t_rr)), "fermi_level": 1e3 * t_mu,
                   "density": ms},
@@ -478,7 +479,8 @@ def poisson_bench(args, prob):
                                   f"density of the workload's 64 wells + 2 point charges", "steps": args.steps},
            "iterations": its[-1], "ms_per_iteration": 1e3 * t / max(1, its[-1]), "rel_resid": out["rel_resid"],
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                        "traffic": None, "kernel": "poisson_apply_kernel", "avg_launch_ms": ms,
+                        "traffic": profiled_traffic(f"poisson_{prob.name}", ("poisson.hip",)),
+                        "kernel": "poisson_apply_kernel", "avg_launch_ms": ms,
                         "bytes_per_launch": 16 * prob.n_dof}}
     print(json.dumps(res), flush=True)
     ctx.close()
