@@ -362,6 +362,20 @@ __global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__res
   }
   __syncthreads();
   const int nround = within ? JB - 1 : JB;
+  // Across the blocks pair b is (b, JB + (b + ir) % JB): column b of R stays
+  // with the threads of pair b, and the second column passes each round to
+  // the lane of pair b - 1 in the same 32-lane half.  So R lives in
+  // registers there (rows 2 a, 2 a + 1 of both columns), with one lane shift
+  // per round; inside the blocks the pairing has no such shape and R stays
+  // in LDS.
+  const int a = t / (J2 / 2), b = t % (J2 / 2);
+  const int src = (t & 32) | ((b + 1) & 31);         // lane holding pair b + 1
+  double rP[2], rQ[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    rP[h] = 2 * a + h == b ? 1.0 : 0.0;
+    rQ[h] = 2 * a + h == JB + b ? 1.0 : 0.0;
+  }
   for (int ir = 0; ir < nround; ++ir) {
     if (t < J2 / 2) {
       int p, q;
@@ -381,7 +395,6 @@ __global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__res
     __syncthreads();
     {
       // 2x2 block (pair a rows, pair b columns), one per thread, in place
-      const int a = t / (J2 / 2), b = t % (J2 / 2);
       int pa, qa, pb, qb;
       jac_pair(a, ir, within, pa, qa);
       jac_pair(b, ir, within, pb, qb);
@@ -402,18 +415,39 @@ __global__ __launch_bounds__(1024) void jacobi_inner_kernel(const JacProb *__res
         S[qa][qb] = sb * r10 + cb * r11;
       }
       // R <- R J: rows 2 per thread, pair b
+      if (within) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int row = 2 * a + h;
-        const double rp = Rs[row][pb], rq = Rs[row][qb];
-        Rs[row][pb] = cs[b] * rp - sn[b] * rq;
-        Rs[row][qb] = sn[b] * rp + cs[b] * rq;
+        for (int h = 0; h < 2; ++h) {
+          const int row = 2 * a + h;
+          const double rp = Rs[row][pb], rq = Rs[row][qb];
+          Rs[row][pb] = cs[b] * rp - sn[b] * rq;
+          Rs[row][qb] = sn[b] * rp + cs[b] * rq;
+        }
+      } else {
+        const double cb = cs[b], sb = sn[b];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double rp = rP[h], rq = rQ[h];
+          rP[h] = cb * rp - sb * rq;
+          rQ[h] = sb * rp + cb * rq;
+          rQ[h] = __shfl(rQ[h], src, 64);              // next round's second column
+        }
       }
     }
     __syncthreads();
   }
   double *Rg = P.R + (int64_t)k * J2 * J2;
-  for (int e = t; e < J2 * J2; e += 1024) Rg[e] = Rs[e / J2][e % J2];
+  if (within) {
+    for (int e = t; e < J2 * J2; e += 1024) Rg[e] = Rs[e / J2][e % J2];
+  } else {
+    // after the shift of the last round this thread holds column JB + (b + nround) % JB
+    const int qcol = JB + (b + nround) % JB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      Rg[(2 * a + h) * J2 + b] = rP[h];
+      Rg[(2 * a + h) * J2 + qcol] = rQ[h];
+    }
+  }
 }
 
 // C = op(X) Y for 64 x 64 LDS operands on FP64 MFMA (16x16x4): wave w of 4
