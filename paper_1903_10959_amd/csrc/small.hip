@@ -470,14 +470,20 @@ __device__ __forceinline__ void jac_mm64(const double (*X)[J2 + 1], const double
 }
 
 // 2. A_next[P1 rows, P2 cols] = R_P1^T A[P1, P2] R_P2 for every pair of pairs
+//    k1 <= k2, with the mirror tile A_next[P2, P1] its transpose
 __global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__restrict__ probs, int nprob, int g) {
   __shared__ double T[J2][J2 + 1], R1[J2][J2 + 1], R2[J2][J2 + 1];
   const JacProb &P = probs[jac_find(probs, nprob, 1)];
   if (g >= P.nbp) return;
   const int r = g == 0 ? 0 : g - 1;
-  const int np2 = P.nbp / 2;
+  // A stays exactly symmetric (its start is, and each tile is written with its
+  // mirror), so only the pairs of pairs k1 <= k2 are computed:
+  // tile = k2 (k2 + 1) / 2 + k1
   const int tile = (int)(blockIdx.x - P.first_tile);
-  const int k1 = tile / np2, k2 = tile % np2;
+  int k2 = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+  while (k2 * (k2 + 1) / 2 > tile) --k2;
+  while ((k2 + 1) * (k2 + 2) / 2 <= tile) ++k2;
+  const int k1 = tile - k2 * (k2 + 1) / 2;
   const int n = P.n;
   const int I1 = rr_index(k1, r, P.nbp), J1 = rr_index(P.nbp - 1 - k1, r, P.nbp);
   const int I2 = rr_index(k2, r, P.nbp), J2b = rr_index(P.nbp - 1 - k2, r, P.nbp);
@@ -502,14 +508,23 @@ __global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__re
 #pragma unroll
     for (int q = 0; q < 4; ++q) T[16 * wv + acc_row<double>(kq, q)][16 * b + jl] = c[b][q];
   __syncthreads();
-  jac_mm64<true>(R1, T, c, wv, lane);              // R1^T U
+  jac_mm64<true>(R1, T, c, wv, lane);              // C = R1^T U
+  __syncthreads();                                  // every wave has read U
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gi = jac_gidx(16 * wv + acc_row<double>(kq, q), I1, J1), gj = jac_gidx(16 * b + jl, I2, J2b);
-      if (gi < n && gj < n) An[(int64_t)gi * n + gj] = c[b][q];
+    for (int q = 0; q < 4; ++q) T[16 * wv + acc_row<double>(kq, q)][16 * b + jl] = c[b][q];
+  __syncthreads();
+  // C to rows of pair k1 x columns of pair k2, C^T to the mirror tile
+  for (int e = t; e < J2 * J2; e += 256) {
+    const int i = e / J2, j = e % J2;
+    const int gi = jac_gidx(i, I1, J1), gj = jac_gidx(j, I2, J2b);
+    if (gi < n && gj < n) An[(int64_t)gi * n + gj] = T[i][j];
+    if (k1 != k2) {
+      const int hi = jac_gidx(i, I2, J2b), hj = jac_gidx(j, I1, J1);
+      if (hi < n && hj < n) An[(int64_t)hi * n + hj] = T[j][i];
     }
+  }
 }
 
 // 3. V[panel rows, P cols] <- V[panel rows, P cols] R_P, in place
@@ -681,7 +696,7 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
       J.first_tile = n_tile;
       J.first_panel = n_panel;
       n_inner += np2;
-      n_tile += (int64_t)np2 * np2;
+      n_tile += (int64_t)np2 * (np2 + 1) / 2;
       n_panel += (int64_t)((J.n + J2 - 1) / J2) * np2;
       rmax = std::max(rmax, J.nbp);                // block rounds g = 0 .. nbp - 1
       run.push_back(J);
