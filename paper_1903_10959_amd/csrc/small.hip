@@ -476,9 +476,9 @@ __global__ __launch_bounds__(256) void jacobi_apply_a_kernel(const JacProb *__re
   const JacProb &P = probs[jac_find(probs, nprob, 1)];
   if (g >= P.nbp) return;
   const int r = g == 0 ? 0 : g - 1;
-  // A stays exactly symmetric (its start is, and each tile is written with its
-  // mirror), so only the pairs of pairs k1 <= k2 are computed:
-  // tile = k2 (k2 + 1) / 2 + k1
+  // A is symmetric, so the tile of pairs (k2, k1) is the transpose of that of
+  // (k1, k2): only k1 <= k2 are computed, each written with its mirror
+  // (tile = k2 (k2 + 1) / 2 + k1)
   const int tile = (int)(blockIdx.x - P.first_tile);
   int k2 = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
   while (k2 * (k2 + 1) / 2 > tile) --k2;
