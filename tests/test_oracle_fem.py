@@ -99,6 +99,32 @@ def test_cell_stiffness_energy_of_quadratic(p):
     assert abs(uz @ K @ uz - (2.0 / 3.0) * h ** 5) < 1e-12 * h ** 5
 
 
+def test_stiffness_1d_closed_forms():
+    """int l_a' l_b' on [-1, 1] for linear and quadratic Lagrange elements."""
+    np.testing.assert_allclose(fem.stiffness_1d_ref(1), [[0.5, -0.5], [-0.5, 0.5]], rtol=0, atol=1e-15)
+    k2 = np.array([[7.0, -8.0, 1.0], [-8.0, 16.0, -8.0], [1.0, -8.0, 7.0]]) / 6.0
+    np.testing.assert_allclose(fem.stiffness_1d_ref(2), k2, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("p", [3, 5, 7, 9])
+def test_stiffness_1d_against_exact_polynomial_integrals(p):
+    """Each Lagrange basis polynomial built from its roots (the other nodes),
+    differentiated and the products integrated exactly as polynomials: no
+    quadrature and no derivative matrix involved."""
+    from numpy.polynomial import polynomial as Pn
+    x, _ = fem.gll(p)
+    dl = []
+    for a in range(p + 1):
+        c = Pn.polyfromroots(np.delete(x, a))
+        dl.append(Pn.polyder(c / Pn.polyval(x[a], c)))
+    K = np.empty((p + 1, p + 1))
+    for i in range(p + 1):
+        for j in range(p + 1):
+            prim = Pn.polyint(Pn.polymul(dl[i], dl[j]))
+            K[i, j] = Pn.polyval(1.0, prim) - Pn.polyval(-1.0, prim)
+    np.testing.assert_allclose(fem.stiffness_1d_ref(p), K, rtol=0, atol=1e-11 * np.abs(K).max())
+
+
 def test_cell_mass_volume():
     for p in [2, 4, 7]:
         h = 2.5
