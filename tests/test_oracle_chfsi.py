@@ -142,3 +142,33 @@ def test_dense_and_lanczos_agree_on_small_workload():
     A = fem.operator_1d(prob.L, prob.n_el, prob.p)
     w, _ = chfsi.eig_lanczos(lambda v: fem.apply_kron(A, V, v), prob.n_dof, 20)
     np.testing.assert_allclose(w, ev[:20], rtol=1e-12, atol=1e-12)
+
+
+def test_subspace_angle_closed_form_and_library():
+    """Two lines in the plane at angle theta (closed form), and random
+    subspaces against scipy's principal angles; tiny angles stay resolved."""
+    import scipy.linalg as sla
+    for th in (0.0, 1e-12, 1e-6, 0.3, 1.2):
+        a = np.array([[1.0], [0.0]])
+        b = np.array([[np.cos(th)], [np.sin(th)]])
+        assert abs(chfsi.subspace_angle(a, b) - th) < 1e-15 + 1e-12 * th
+    rng = np.random.default_rng(7)
+    for k in (1, 3, 8):
+        A = rng.standard_normal((40, k))
+        B = rng.standard_normal((40, k))
+        want = np.max(sla.subspace_angles(A, B))
+        assert abs(chfsi.subspace_angle(A, B) - want) < 1e-12
+    # the same span in another basis
+    A = np.linalg.qr(rng.standard_normal((30, 5)))[0]
+    assert chfsi.subspace_angle(A, A @ np.linalg.qr(rng.standard_normal((5, 5)))[0]) < 1e-14
+
+
+def test_cluster_boundaries_by_construction():
+    ev = np.array([-1.0, -0.9995, -0.5, -0.5, -0.49995, 0.2, 0.7])
+    # gaps of at least 1e-3 close the first 2, 5 and 6 values (-0.9995 -> -0.5,
+    # -0.49995 -> 0.2, 0.2 -> 0.7); the others are 5e-4, 0 and 5e-5
+    assert chfsi.cluster_boundaries(ev, 6) == [2, 5, 6]
+    assert chfsi.cluster_boundaries(ev, 3) == [2]
+    assert chfsi.cluster_boundaries(ev, 10) == [2, 5, 6]    # capped at the last index
+    assert chfsi.cluster_boundaries(ev, 6, gap=0.6) == [5]       # only the 0.69995 gap
+    assert chfsi.cluster_boundaries(ev, 6, gap=0.7) == []
