@@ -24,12 +24,19 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
   largest residual of the wanted states is <= tol.
 * ``eig_dense`` / ``eig_lanczos`` -- the plain definition of the result: the
   lowest eigenpairs of Htilde by LAPACK (numpy ``eigh``) or ARPACK Lanczos.
+* ``cheb_T``, ``filter_coefficients`` -- T_m(x) by its closed form, and the
+  (s1, s2, shift) of each step of the normalised recursion (Sec. 3.3).
+* ``subspace_angle``, ``cluster_boundaries`` -- comparison helpers of the tests
+  (largest principal angle; the counts at which the spectrum has a gap), not
+  steps of the method.
 
 Pins (tests/test_oracle_chfsi.py): the filter against the closed form
 T_m(x) = cos(m arccos x) / cosh(m arccosh |x|) on exact eigenvectors and the
 two recursions against each other; CholGS against Householder QR with a
 positive R diagonal; RR on rotated exact eigenvectors; the solve loop against
-dense ``eigh``; dense against Lanczos.
+dense ``eigh``; dense against Lanczos; T_m's closed form against its
+recurrence; the step coefficients against the scaled filter; the subspace
+angle against the planar closed form and scipy's principal angles.
 """
 from __future__ import annotations
 
@@ -187,6 +194,7 @@ def chfsi_solve(apply, X0: np.ndarray, nstates: int, degree: int, b: float,
 # --------------------------------------------------------------------------
 
 def eig_dense(H) -> tuple:
+    """All eigenpairs of the symmetric H, ascending (LAPACK through numpy)."""
     H = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
     return np.linalg.eigh(H)
 

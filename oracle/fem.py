@@ -28,7 +28,8 @@ against a brute-force quadrature assembly written with general Lagrange
 evaluation; V=0 spectrum against sums of 1D eigenvalues and against the
 continuum particle-in-a-box values; the harmonic oscillator limit.  The
 Kronecker-product diagonal mass (``mass_diag_kron``) against the assembled M
-(tests/test_oracle_density.py).
+(tests/test_oracle_density.py); the 1D reference stiffness against closed forms
+and exact polynomial integrals; the 1D mass against its closed forms.
 """
 from __future__ import annotations
 
@@ -143,6 +144,7 @@ def cell_mass(p: int, h: float) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def sizes(n_el: int, p: int):
+    """n interior nodes per direction, n_dof = n^3, cells and local nodes."""
     n = n_el * p - 1
     return dict(n=n, n_dof=n ** 3, n_cells=n_el ** 3, n_loc=(p + 1) ** 3)
 

@@ -52,6 +52,7 @@ def load_vector(M: np.ndarray, rho: np.ndarray, charge_dofs=(), charges=()) -> n
 
 
 def solve(L: float, n_el: int, p: int, rho, charge_dofs=(), charges=()) -> np.ndarray:
+    """phi from A phi = M rho + q by a sparse direct solve (the plain definition)."""
     A, M = poisson_matrix(L, n_el, p)
     return spla.spsolve(A.tocsc(), load_vector(M, rho, charge_dofs, charges))
 
