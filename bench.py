@@ -350,7 +350,7 @@ def density_bench(args, prob):
 
 
 def kpoint_bench(args, prob):
-    """Complex Bloch operator (Sec. 2.2 eq. ksproblemPer) on the periodic cell
+    """Complex Bloch operator (Sec. 2.1 eq. ksproblemPer) on the periodic cell
     with the workload's element size and degree: Y = Htilde_k X for a complex
     block of 64 vectors (one filter block of 128 real columns), timed with HIP
     events on the context's stream.  Roofline: FP64 MFMA, algorithmic flops =

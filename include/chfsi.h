@@ -151,7 +151,7 @@ int chfsi_rayleigh_ritz(chfsi_ctx *ctx, double *X, int64_t ld, int ncols,
 int chfsi_rayleigh_ritz_split(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int n_fr, int mixed,
                               double *Xfr, int64_t ldfr, double *evals_fr, double *resid_fr);
 
-/* ---- periodic cell and k-points (Sec. 2.2, eq. ksproblemPer) ------------
+/* ---- periodic cell and k-points (Sec. 2.1, eq. ksproblemPer) ------------
  * chfsi_set_mesh_periodic: as chfsi_set_mesh on the periodic cell [0, L)^3:
  * node index I = (ex p + a) mod (n_el p), so n = n_el p unknowns per
  * direction and n_dof = (n_el p)^3, no Dirichlet nodes; n_el must be even

@@ -23,7 +23,7 @@ Modules
            and Fermi level, the nodal electron density by eq. elecDensSP and
            by eq. elecDens, and the cell-level form of eq. elecDensSums
            (Sec. 3.5, Alg. 5).
-``kpoint`` The periodic Bloch operator at a k-point (Sec. 2.2 eq.
+``kpoint`` The periodic Bloch operator at a k-point (Sec. 2.1 eq.
            ksproblemPer): periodic numbering, the GLL first-derivative cell
            matrices, the complex Hermitian standard-form CSR and its
            Kronecker-sum apply.
@@ -32,7 +32,8 @@ Modules
            conjugate-gradient solver the paper uses for it.
 
 Pinning status (what each function is checked against) is listed in the
-module docstrings.  Mixed-precision accuracy is *parity unpinned* by the paper
-(its accuracy table is a full-DFT comparison); it is measured against the FP64
-functions here and reported.
+module docstrings.  The paper's mixed-precision steps (CholGS, the projected
+Hamiltonian) are pinned by exactly rounded sums and FP32 error bounds; the
+reduced-precision filters are not the paper's and have no oracle of their
+own: their results are measured against the FP64 functions here.
 """

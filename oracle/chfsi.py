@@ -14,8 +14,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
   X_o = X L^-T.
 * ``cholgs_mixed``        -- Sec. 3.4 eq. overlapmixedprec: diagonal blocks
   of S and of L^-T in FP64, off-diagonal blocks with FP32 inputs and FP32
-  accumulation.  (The paper splits off diagonal *entries*; block width 1 is
-  that case.)  Accuracy: parity unpinned by the paper, measured only.
+  accumulation (``overlap_mixed``, ``rmul_mixed``).  (The paper splits off
+  diagonal *entries*; block width 1 is that case.)
 * ``rayleigh_ritz``       -- Sec. 3.5 steps i-iii: Hhat = X^T Htilde X (lower
   triangle, mirrored), Hhat Q = Q D with D ascending, X <- X Q; also
   HX <- HX Q and the residual norms ||HX_i - D_i X_i||.
@@ -33,7 +33,11 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 Pins (tests/test_oracle_chfsi.py): the filter against the closed form
 T_m(x) = cos(m arccos x) / cosh(m arccosh |x|) on exact eigenvectors and the
 two recursions against each other; CholGS against Householder QR with a
-positive R diagonal; RR on rotated exact eigenvectors; the solve loop against
+positive R diagonal; the mixed split against exactly rounded sums
+(``math.fsum``): FP64-level error on the diagonal blocks, an error inside the
+FP32 accumulation bound and far above FP64 rounding off them, bit-exact
+results where FP32 arithmetic is exact (small integers), and FP64 equality
+when the off-diagonal blocks vanish; RR on rotated exact eigenvectors; the solve loop against
 dense ``eigh``; dense against Lanczos; T_m's closed form against its
 recurrence; the step coefficients against the scaled filter; the subspace
 angle against the planar closed form and scipy's principal angles.
@@ -133,22 +137,39 @@ def _block_masks(n: int, bv: int):
     return diag
 
 
-def cholgs_mixed(X: np.ndarray, bv: int = 64) -> np.ndarray:
-    """Alg. 3 with the mixed-precision split of steps 1 and 4: FP64 on the
-    bv x bv diagonal blocks, FP32 (inputs rounded to nearest, FP32 products
-    and sums) on the off-diagonal blocks, promoted back to FP64."""
+def overlap_mixed(X: np.ndarray, bv: int = 64) -> np.ndarray:
+    """Step 1 of Alg. 3 split as in eq. overlapmixedprec: S = X^T X with the
+    bv x bv diagonal blocks in FP64 and every off-diagonal block from inputs
+    rounded to FP32 (nearest) with FP32 products and sums, promoted to FP64."""
     n = X.shape[1]
     diag = _block_masks(n, bv)
     X32 = X.astype(np.float32)
-    S = np.where(diag, X.T @ X, (X32.T @ X32).astype(np.float64))
+    return np.where(diag, X.T @ X, (X32.T @ X32).astype(np.float64))
+
+
+def rmul_mixed(X: np.ndarray, U: np.ndarray, bv: int = 64) -> np.ndarray:
+    """Step 4 of Alg. 3 split the same way (the product after eq.
+    overlapmixedprec): X U with the bv x bv diagonal blocks of U applied in
+    FP64 and the off-diagonal blocks with FP32 inputs, products and sums."""
+    n = U.shape[0]
+    diag = _block_masks(n, bv)
+    Ud = np.where(diag, U, 0.0)
+    Uod = np.where(diag, 0.0, U).astype(np.float32)
+    return X @ Ud + (X.astype(np.float32) @ Uod).astype(np.float64)
+
+
+def cholgs_mixed(X: np.ndarray, bv: int = 64) -> np.ndarray:
+    """Alg. 3 with the mixed-precision split of steps 1 and 4 (``overlap_mixed``
+    and ``rmul_mixed``); steps 2 and 3 (Cholesky factor and its inverse) in
+    FP64, as in the paper."""
+    n = X.shape[1]
+    S = overlap_mixed(X, bv)
     try:
         L = np.linalg.cholesky(S)
     except np.linalg.LinAlgError as exc:
         raise NotSPD(str(exc)) from exc
     U = sla.solve_triangular(L, np.eye(n), lower=True).T      # L^-T, upper
-    Ud = np.where(diag, U, 0.0)
-    Uod = np.where(diag, 0.0, U).astype(np.float32)
-    return X @ Ud + (X32 @ Uod).astype(np.float64)
+    return rmul_mixed(X, U, bv)
 
 
 # --------------------------------------------------------------------------
@@ -230,5 +251,5 @@ def cluster_boundaries(evals: np.ndarray, upto: int, gap: float = 1e-3):
 
 
 __all__ = ["cheb_T", "cheb_filter_paper", "cheb_filter_scaled", "filter_coefficients",
-           "NotSPD", "cholgs", "cholgs_mixed", "rayleigh_ritz", "chfsi_solve", "eig_dense",
+           "NotSPD", "cholgs", "overlap_mixed", "rmul_mixed", "cholgs_mixed", "rayleigh_ritz", "chfsi_solve", "eig_dense",
            "eig_lanczos", "subspace_angle", "cluster_boundaries"]

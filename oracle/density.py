@@ -6,10 +6,12 @@ the CPU.  TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 * ``fermi_level``          -- Alg. 5 step 1: the mu at which
   2 (N_oc + sum_{fr} f(eps_k, mu)) = N_e, by Brent's method on that monotone
   function (scipy ``brentq``).
-* ``rayleigh_ritz_split``  -- Alg. 4: Hhat = X^T Htilde X (optionally the
-  mixed form of Sec. 3.5: the fr-fr block in FP64, every other block from
-  FP32 inputs with FP32 products), all eigenpairs of Hhat, the N_fr largest
-  kept, the partial rotation X_fr = X Q_fr and its residual norms.
+* ``projected_split``      -- the mixed-precision projected Hamiltonian of
+  Sec. 3.5 (eq. partialDiagMixedPrec1): the fr-fr block in FP64, every other
+  block from FP32 inputs with FP32 products.
+* ``rayleigh_ritz_split``  -- Alg. 4: Hhat = X^T Htilde X (FP64, or the mixed
+  form above), all eigenpairs of Hhat, the N_fr largest kept, the partial
+  rotation X_fr = X Q_fr and its residual norms.
 * ``density_split``        -- Alg. 5 steps 2-3, eq. elecDensSP: with the
   collocated GLL quadrature (the basis functions are the Lagrange polynomials
   of the nodes, so n^e(x_j) is the unit vector of node j) the density at node
@@ -28,10 +30,13 @@ about mu0 (closed forms); the particle count sum_j M_jj rho_j = N_e; split
 against full (the projector identity X X^T = X Q Q^T X^T); the cell-level
 formula against the nodal one on every cell; the particle-in-a-box ground
 state density against the separable product of 1D eigenvectors; the FP64
-``rayleigh_ritz_split`` against the top N_fr pairs of the full Rayleigh-Ritz.
-Its mixed form is *parity unpinned*: the paper fixes no accuracy for it (its
-accuracy table is a full-DFT comparison); its error against the FP64 form is
-measured and reported.
+``rayleigh_ritz_split`` against the top N_fr pairs of the full Rayleigh-Ritz;
+``projected_split`` against exactly rounded sums (``math.fsum``: FP64-level
+error in the fr-fr block, FP32-level error outside it) and bit-exact where
+FP32 arithmetic is exact; the mixed split on exact eigenvectors, where the
+coupling blocks vanish, against the exact eigenvalues to FP64 level (the
+paper's limit, eq. partialDiagLim2), and on a random block with an error
+between FP32-level bounds.
 """
 from __future__ import annotations
 
@@ -70,20 +75,25 @@ def fermi_level(evals_fr, n_oc: int, n_electrons: float, sigma: float) -> float:
     return float(so.brentq(g, a, b, xtol=1e-15, rtol=4 * np.finfo(float).eps, maxiter=500))
 
 
+def projected_split(X: np.ndarray, HX: np.ndarray, fr0: int) -> np.ndarray:
+    """G = X^T HX as in eq. partialDiagMixedPrec1 (Sec. 3.5): the block of rows
+    and columns >= fr0 (the fractionally occupied states) in FP64, every other
+    entry from inputs rounded to FP32 with FP32 products and sums."""
+    G = (X.astype(np.float32).T @ HX.astype(np.float32)).astype(np.float64)
+    G[fr0:, fr0:] = X[:, fr0:].T @ HX[:, fr0:]
+    return G
+
+
 def rayleigh_ritz_split(apply, X: np.ndarray, n_fr: int, mixed: bool = False, fr0: int | None = None):
     """Alg. 4 on an orthonormal X [n x N].  Returns (X_fr = X Q_fr, D_fr, resid).
 
-    mixed: Hhat from FP32 inputs and FP32 products outside the fr-fr block
-    (rows and columns >= fr0; default N - n_fr), FP64 inside it."""
+    mixed: Hhat by ``projected_split`` with the FP64 block starting at fr0
+    (default N - n_fr); otherwise all FP64."""
     N = X.shape[1]
     HX = apply(X)
     if fr0 is None:
         fr0 = N - n_fr
-    if mixed:
-        G = (X.astype(np.float32).T @ HX.astype(np.float32)).astype(np.float64)
-        G[fr0:, fr0:] = X[:, fr0:].T @ HX[:, fr0:]
-    else:
-        G = X.T @ HX
+    G = projected_split(X, HX, fr0) if mixed else X.T @ HX
     Hhat = np.tril(G) + np.tril(G, -1).T
     D, Q = np.linalg.eigh(Hhat)
     Qfr = Q[:, N - n_fr:]
@@ -131,5 +141,5 @@ def density_cellwise(L: float, n_el: int, p: int, Xr: np.ndarray, occ: np.ndarra
     return out
 
 
-__all__ = ["fermi_dirac", "electron_count", "fermi_level", "rayleigh_ritz_split", "density_split",
+__all__ = ["fermi_dirac", "electron_count", "fermi_level", "projected_split", "rayleigh_ritz_split", "density_split",
            "density_full", "density_cellwise"]

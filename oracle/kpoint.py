@@ -1,7 +1,7 @@
 """Oracle: the periodic (Bloch) Kohn-Sham operator at a k-point, FP64 / complex128
 on the CPU.  TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Sec. 2.2 eq. ksproblemPer: on the periodic cell Omega_p = [0, L]^3 the
+Sec. 2.1 eq. ksproblemPer: on the periodic cell Omega_p = [0, L]^3 the
 Bloch-periodic part u of psi = e^{i k.x} u solves
 
     (-1/2 Laplacian - i k.grad + 1/2 |k|^2 + V) u = eps u,   u periodic.

@@ -32,7 +32,7 @@ struct MeshTables {
 };
 
 // Builds every table; returns an empty string on success, else a message.
-// periodic: the Bloch-periodic cell of Sec. 2.2 (n_el even, so that the
+// periodic: the Bloch-periodic cell of Sec. 2.1 (n_el even, so that the
 // 8-colour parity rule still separates cells that share a node across the wrap).
 std::string build_mesh(double L, int n_el, int p, MeshTables &m, bool periodic = false);
 

@@ -1,4 +1,4 @@
-"""GPU parity of the periodic mesh and the complex Bloch operator (Sec. 2.2,
+"""GPU parity of the periodic mesh and the complex Bloch operator (Sec. 2.1,
 eq. ksproblemPer) against the oracle."""
 import numpy as np
 import pytest

@@ -94,8 +94,8 @@ def test_cholgs_rank_deficient_raises():
 
 
 def test_cholgs_mixed_is_fp32_accurate_and_exact_on_diagonal_blocks():
-    """Mixed CholGS: parity unpinned by the paper; measured: X^T X = I to FP32
-    level, and with bv >= ncols it reduces to the FP64 routine exactly."""
+    """Mixed CholGS: X^T X = I to FP32 level, and with bv >= ncols it reduces
+    to the FP64 routine exactly (its steps are pinned in test_oracle_mixed)."""
     rng = np.random.default_rng(13)
     X = rng.standard_normal((2000, 40))
     Xm = chfsi.cholgs_mixed(X, bv=8)

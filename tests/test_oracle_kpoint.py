@@ -1,4 +1,4 @@
-"""Pins of the oracle's periodic k-point operator (Sec. 2.2 eq. ksproblemPer on
+"""Pins of the oracle's periodic k-point operator (Sec. 2.1 eq. ksproblemPer on
 the GLL discretisation), CPU only."""
 import numpy as np
 import pytest
