@@ -1,11 +1,12 @@
 """Benchmark: ChFSI H.X throughput (DoF-vecs/s) on one MI355X.
 
-One step = one pass of the whole hot path over the 568-vector block of the
-24^3-cell, degree-6 workload (2,924,207 DoFs, 64 seeded Gaussian wells,
-512 wanted states + 56 guard states): Chebyshev filter of degree 30 in
-blocks of 128 vectors, CholGS, Rayleigh-Ritz (one more Htilde application,
-projection, Jacobi eigensolve, two rotations, residuals).  value = Htilde
-applications in the step x n_dof / step time (inputs resident in HBM).
+One step = one pass of the whole hot path over the 1,128-vector block of the
+32^3-cell, degree-5 workload (4,019,679 DoFs, 64 seeded Gaussian wells, 1,024
+wanted states + 104 guard states): Chebyshev filter of degree 30 in blocks of
+128 vectors, CholGS, Rayleigh-Ritz (one more Htilde application, projection,
+Jacobi eigensolve, rotation, residuals).  value = Htilde applications in the
+step x n_dof / step time (inputs resident in HBM).  --workload large_p6 runs
+the 24^3-cell, degree-6 workload (568 vectors) instead.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -23,36 +24,84 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}          # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                              # GB/s
 
 
-def cpu_baseline(prob, ncols: int, budget_s: float = 30.0):
-    """The oracle, as it stands, on a bounded sample: one ChFSI iteration
-    (filter of the same degree + CholGS + RR) on `ncols` of the vectors."""
+def host_cpu():
+    """CPU model and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = "unknown", set()
+    phys = core = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name":
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None:
+                cores.add((phys, core))
+                phys = core = None
+    except OSError:
+        pass
+    return model, (len(cores) or os.cpu_count() or 1)
+
+
+def cpu_baseline(prob, ncols: int, nrows: int = 16384):
+    """The oracle, as it stands, timed on a bounded sample of one ChFSI
+    iteration and scaled by each part's own cost model to the whole block:
+    * filter: the degree-m filter on `ncols` of the vectors (its cost per
+      vector does not depend on the block), scaled by N_b / ncols, plus one
+      more application per vector for Rayleigh-Ritz;
+    * CholGS and the Rayleigh-Ritz products at the full block width N_b on
+      `nrows` rows of the block (their cost is linear in the rows), scaled by
+      n_dof / nrows; the N_b x N_b factorisations and eigensolve inside them
+      are timed on their own and counted once."""
     import numpy as np
+    import scipy.linalg as sla
     from threadpoolctl import threadpool_info
 
     import workload
     from oracle import chfsi as och
     from oracle import fem
 
-    t0 = time.time()
+    nb = prob.nblock
     xyz = fem.dof_coords(prob.L, prob.n_el, prob.p)
     V = workload.eval_wells(workload.problem_wells(prob), xyz)
     A = fem.operator_1d(prob.L, prob.n_el, prob.p)
     apply = lambda X: fem.apply_kron(A, V, X)
-    X = och.cholgs(workload.start_block(prob.n_dof, ncols, prob.x0_seed))
-    X, _, D, _ = och.rayleigh_ritz(apply, X)
     b = fem.upper_bound(A, V)
-    setup = time.time() - t0
+    X = och.cholgs(workload.start_block(prob.n_dof, ncols, prob.x0_seed))
+    _, _, D, _ = och.rayleigh_ritz(apply, X)
     t0 = time.time()
-    Z = och.cheb_filter_scaled(apply, X, prob.degree, float(D[-1]), b, float(D[0]))
-    Z = och.cholgs(Z)
-    och.rayleigh_ritz(apply, Z)
-    dt = time.time() - t0
+    och.cheb_filter_scaled(apply, X, prob.degree, float(D[-1]), b, float(D[0]))
+    t_filter = time.time() - t0
+    per_apply = t_filter / (prob.degree * ncols)
+    Xs = workload.start_block(nrows, nb, prob.x0_seed + 1)
+    t0 = time.time()
+    Xs = och.cholgs(Xs)
+    t_chol = time.time() - t0
+    t0 = time.time()
+    och.rayleigh_ritz(lambda Y: Y * 1.0, Xs)
+    t_rr = time.time() - t0
+    S = Xs.T @ Xs + np.eye(nb)
+    t0 = time.time()
+    Lc = np.linalg.cholesky(S)
+    sla.solve_triangular(Lc, np.eye(nb), lower=True)
+    np.linalg.eigh(S)
+    t_dense = time.time() - t0
+    t_iter = ((prob.degree + 1) * nb * per_apply + max(t_chol + t_rr - t_dense, 0.0) * prob.n_dof / nrows
+              + t_dense)
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    dofvecs = prob.n_dof * ncols * (prob.degree + 1)
-    return {"value": dofvecs / dt, "unit": "DoF-vecs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one ChFSI iteration (degree-{prob.degree} filter + CholGS + RR) on {ncols} of "
-                      f"{prob.nblock} vectors, Kronecker-form FP64 operator, {dt:.1f} s (setup {setup:.1f} s)",
-            "seconds": dt}
+    model, phys = host_cpu()
+    dofvecs = prob.n_dof * nb * (prob.degree + 1)
+    sampled = t_filter + t_chol + t_rr + t_dense
+    return {"value": dofvecs / t_iter, "unit": "DoF-vecs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one ChFSI iteration of the Kronecker-form FP64 oracle, estimated from {sampled:.1f} s "
+                      f"of timed parts: degree-{prob.degree} filter on {ncols} of {nb} vectors (x {nb / ncols:.1f}), "
+                      f"CholGS + Rayleigh-Ritz at width {nb} on {nrows} of {prob.n_dof} rows "
+                      f"(x {prob.n_dof / nrows:.1f}), N_b^3 factorisations once; whole iteration "
+                      f"{t_iter:.0f} s",
+            "seconds_estimated": t_iter, "cpu_model": model, "physical_cores": phys}
 
 
 def profiled_traffic(tag: str, sources=("hx.hip", "common.hpp")):
@@ -491,12 +540,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large_p6")
+    ap.add_argument("--workload", default="large_p5")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16x3"])
     ap.add_argument("--mixed-cholgs", action="store_true")
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=16)
+    ap.add_argument("--cpu-cols", type=int, default=4)
     ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density", "kpoint", "poisson"],
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
                          "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5); "
