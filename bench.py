@@ -545,7 +545,7 @@ def main():
     ap.add_argument("--mixed-cholgs", action="store_true")
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=4)
+    ap.add_argument("--cpu-cols", type=int, default=16)
     ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density", "kpoint", "poisson"],
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
                          "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5); "
