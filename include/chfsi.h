@@ -75,7 +75,8 @@ int chfsi_create(chfsi_ctx **out, int device, void *hip_stream);
 int chfsi_destroy(chfsi_ctx *ctx);
 
 /* ---- setMesh (Sec. 2.4 eq. fem, Sec. 3.1 mesh; uniform cubes only) ------
- * Build the GLL rule of degree p (1..12), the reference cell stiffness
+ * Build the GLL rule of degree p (1..7: the degrees the device cell kernels
+ * are built for; CHFSI_ERR_ARG otherwise), the reference cell stiffness
  * 1/2 (h/2)[K1 (x) W (x) W + W (x) K1 (x) W + W (x) W (x) K1] (h = L/n_el,
  * K1 = D^T W D, W = diag of GLL weights), the cell->dof map, the 8-colour
  * cell colouring (ex&1)+2(ey&1)+4(ez&1) and the diagonal mass M (GLL rule),
@@ -290,7 +291,9 @@ int chfsi_solve(chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
  * wanted residuals are <= opts[i].tol or after opts[i].max_iter passes.
  * X[i]: device [n_dof_i x ld[i]] start block in, Ritz vectors out;
  * evals[i], resid[i]: host [nblock_i]; reps (may be NULL) [n].
- * Returns CHFSI_WARN_NOT_CONVERGED if any problem did not converge. */
+ * Returns CHFSI_WARN_NOT_CONVERGED if any problem did not converge or failed;
+ * reps[i].status then tells which (< 0: that problem's own error, see
+ * chfsi_batch_pass). */
 int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts *opts, double *const *X,
                       const int64_t *ld, double *const *evals, double *const *resid, chfsi_report *reps);
 
@@ -306,7 +309,13 @@ int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts *opts, dou
  * and their ids are written to done_ids (at most max_done; the rest are
  * reported by later calls).  Each problem follows its own precision ladder
  * (FP32 and FP64 rungs only; rung thresholds as in chfsi_solve).
- * A problem's results do not depend on which other problems share its passes. */
+ * A problem's results do not depend on which other problems share its passes.
+ * A problem whose own step fails leaves the session with that status in its
+ * report (rep.status < 0) and its id in done_ids, while the others go on:
+ * CHFSI_ERR_NONFINITE when its Ritz values give no valid filter bounds
+ * (a0 < a < b), CHFSI_ERR_NOT_SPD from its CholGS, CHFSI_ERR_HIP from a call on
+ * its stream.  chfsi_batch_pass itself returns an error only for a failure of
+ * the shared work (the graph-captured sweep, the batched eigensolve). */
 typedef struct chfsi_batch chfsi_batch;
 int chfsi_batch_create(chfsi_batch **out, int device);
 int chfsi_batch_destroy(chfsi_batch *b);
@@ -317,11 +326,27 @@ int chfsi_batch_add(chfsi_batch *b, chfsi_ctx *ctx, const chfsi_opts *o, double 
 int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int max_done);
 int chfsi_batch_report(const chfsi_batch *b, int id, chfsi_report *rep);
 const char *chfsi_batch_last_error(const chfsi_batch *b);
+/* Host threads that run the per-problem CholGS / Rayleigh-Ritz steps of a
+ * pass (default 8).  Problems whose contexts share a HIP stream are always
+ * handled by one thread in turn, so no stream is driven by two threads at
+ * once; threads = 1 runs every problem from the calling thread (for tracers
+ * and debuggers).  A new session (also the one chfsi_solve_batch makes) takes
+ * its default from the environment variable CHFSI_BATCH_THREADS when set to
+ * 1..256.  Errors: CHFSI_ERR_ARG outside 1..256. */
+int chfsi_batch_set_threads(chfsi_batch *b, int threads);
+/* Device bytes a context holds once it is in a batch session with nblock
+ * vectors (mesh and potential tables, the CholGS / Rayleigh-Ritz workspaces,
+ * three FP64-sized recursion buffers and HX), not counting the caller's block
+ * (pure; no device access; 0 for arguments outside the supported range). */
+size_t chfsi_batch_footprint_bytes(int n_el, int p, int nblock);
 
 /* ---- admission / diagnostics ---------------------------------------------
  * Device bytes a context needs for (n_el, p) and a solve of nblock vectors with
  * the given filter block width and precision (pure; no device access). */
 size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_width, chfsi_prec prec);
+/* Device bytes the context holds right now (its buffers only grow until
+ * destroy, so a reused context may hold more than a new problem needs). */
+int chfsi_device_bytes(const chfsi_ctx *ctx, size_t *bytes);
 const char *chfsi_status_string(int status);
 const char *chfsi_last_error(const chfsi_ctx *ctx);
 /* Timing of the cell-product kernel (the filter's dominant kernel): when
@@ -350,6 +375,13 @@ int chfsi_set_tile_variant(chfsi_ctx *ctx, int variant);
  * Htilde again.  Both give the same vectors up to rounding; HX_out receives
  * whichever.  Errors: CHFSI_ERR_ARG for a null ctx or a mode outside 0..2. */
 int chfsi_set_rr_residual(chfsi_ctx *ctx, int mode);
+/* Cap on the Jacobi sweeps of the projected eigensolve (Sec. 3.5 step ii;
+ * default 40; a filtered block needs about 10).  When the cap ends the
+ * eigensolve before its off-diagonal norm meets the tolerance, rayleighRitz
+ * (both forms) returns CHFSI_WARN_NOT_CONVERGED with the last iterate's pairs,
+ * and a solve or batch problem whose last Rayleigh-Ritz did so reports
+ * CHFSI_WARN_NOT_CONVERGED.  Errors: CHFSI_ERR_ARG outside 1..1000. */
+int chfsi_set_jacobi_sweeps(chfsi_ctx *ctx, int max_sweeps);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, Opts, Report
 
-__all__ = ["Context", "ChfsiError", "footprint_bytes", "solve_batch", "BatchSession", "PRECISIONS", "library_path"]
+__all__ = ["Context", "ChfsiError", "footprint_bytes", "batch_footprint_bytes", "solve_batch", "BatchSession", "PRECISIONS", "library_path"]
 
 
 class ChfsiError(RuntimeError):
@@ -32,6 +32,11 @@ def library_path() -> str:
 
 def footprint_bytes(n_el: int, p: int, nblock: int, block_width: int = 0, prec: str = "fp64") -> int:
     return int(_lib.load().chfsi_footprint_bytes(n_el, p, nblock, block_width, PRECISIONS[prec]))
+
+
+def batch_footprint_bytes(n_el: int, p: int, nblock: int) -> int:
+    """Device bytes of a context in a batch session (without the caller's block)."""
+    return int(_lib.load().chfsi_batch_footprint_bytes(n_el, p, nblock))
 
 
 def fermi_level(evals_fr, n_oc: int, n_electrons: float, sigma: float) -> float:
@@ -97,8 +102,16 @@ class BatchSession:
         self._keep[pid] = (o, ev, rs, X, ctx)
         return pid
 
+    def set_threads(self, threads: int):
+        """Host threads for the per-problem CholGS / Rayleigh-Ritz steps."""
+        st = self._lib.chfsi_batch_set_threads(self._h, int(threads))
+        if st != 0:
+            raise ChfsiError(st, "chfsi_batch_set_threads", "threads must be in 1..256")
+        return self
+
     def step(self):
-        """One pass; returns (remaining, [(id, result dict), ...] of problems that left)."""
+        """One pass; returns (remaining, [(id, result dict), ...] of problems that
+        left).  A problem that failed on its own has status < 0 in its dict."""
         nd = C.c_int()
         rem = self._lib.chfsi_batch_pass(self._h, self._done, C.byref(nd), len(self._done))
         if rem < 0:
@@ -411,8 +424,10 @@ class Context:
             ph, ldh, nh = self._block(HX_out)
             if ldh != ld or nh != n:
                 raise ValueError("HX_out must match X")
-        self._check(self._lib.chfsi_rayleigh_ritz(self._h, px, ld, n, ev.ctypes.data_as(C.c_void_p),
-                                                  rs.ctypes.data_as(C.c_void_p), ph), "rayleigh_ritz")
+        st = self._check(self._lib.chfsi_rayleigh_ritz(self._h, px, ld, n, ev.ctypes.data_as(C.c_void_p),
+                                                       rs.ctypes.data_as(C.c_void_p), ph), "rayleigh_ritz",
+                         ok=(0, _lib.WARN_NOT_CONVERGED))
+        self.last_eigensolve_converged = st == 0
         return ev, rs
 
     def rayleigh_ritz_split(self, X, n_fr: int, mixed: bool = True, Xfr=None):
@@ -428,9 +443,11 @@ class Context:
                 raise ValueError("Xfr needs at least n_fr columns")
         ev = np.empty(int(n_fr))
         rs = np.empty(int(n_fr))
-        self._check(self._lib.chfsi_rayleigh_ritz_split(self._h, px, ld, n, int(n_fr), 1 if mixed else 0, pf, ldf,
-                                                        ev.ctypes.data_as(C.c_void_p), rs.ctypes.data_as(C.c_void_p)),
-                    "rayleigh_ritz_split")
+        st = self._check(self._lib.chfsi_rayleigh_ritz_split(self._h, px, ld, n, int(n_fr), 1 if mixed else 0, pf,
+                                                             ldf, ev.ctypes.data_as(C.c_void_p),
+                                                             rs.ctypes.data_as(C.c_void_p)),
+                         "rayleigh_ritz_split", ok=(0, _lib.WARN_NOT_CONVERGED))
+        self.last_eigensolve_converged = st == 0
         return ev, rs
 
     def density(self, X, Xfr=None, evals_fr=None, mu: float = 0.0, sigma: float = 0.0, rho=None):
@@ -477,6 +494,17 @@ class Context:
         self._check(self._lib.chfsi_set_tile_variant(self._h, int(variant)), "set_tile_variant")
         self.tile_variant = int(variant)
         return self
+
+    def set_jacobi_sweeps(self, max_sweeps: int = 40):
+        """Cap on the Jacobi sweeps of the projected eigensolve."""
+        self._check(self._lib.chfsi_set_jacobi_sweeps(self._h, int(max_sweeps)), "set_jacobi_sweeps")
+        return self
+
+    def device_bytes(self) -> int:
+        """Device bytes the context holds now."""
+        b = C.c_size_t()
+        self._check(self._lib.chfsi_device_bytes(self._h, C.byref(b)), "device_bytes")
+        return int(b.value)
 
     def set_rr_residual(self, mode: int = 0):
         """Ritz residuals: 0 cost model, 1 rotate HX with X, 2 apply Htilde again."""

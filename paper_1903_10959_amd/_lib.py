@@ -71,6 +71,10 @@ SIGNATURES = {
     "chfsi_set_rr_residual": (_int, [_vp, _int]),
     "chfsi_reset_timing": (_int, [_vp]),
     "chfsi_last_filter_timing": (_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)]),
+    "chfsi_set_jacobi_sweeps": (_int, [_vp, _int]),
+    "chfsi_batch_set_threads": (_int, [_vp, _int]),
+    "chfsi_batch_footprint_bytes": (C.c_size_t, [_int, _int, _int]),
+    "chfsi_device_bytes": (_int, [_vp, C.POINTER(C.c_size_t)]),
 }
 
 _LIB = None

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -39,29 +40,29 @@ struct Prob {
   bool started = false, done = false;
   int rung = 0;
   double res = INFINITY;
+  bool jac_warn = false;     // the last projected eigensolve ran out of sweeps
 };
 
-// run fn(i) for i in [0, n) on up to `threads` host threads; first non-zero status
+// Runs fn(i) for every i in [0, n) on up to `threads` host threads, with the
+// indices of one group (problems whose contexts share a HIP stream) handled in
+// order by one thread, so that no stream is driven by two host threads at
+// once.  fn's status for each index goes to st[i].
 template <typename F>
-int parallel_for(int n, int threads, F fn) {
-  std::atomic<int> next(0), first_err(0);
+void parallel_for_groups(const std::vector<std::vector<int>> &groups, int threads, std::vector<int> &st, F fn) {
+  std::atomic<int> next(0);
+  const int ng = (int)groups.size();
   auto worker = [&]() {
     for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= n) return;
-      const int st = fn(i);
-      if (st != 0) {
-        int z = 0;
-        first_err.compare_exchange_strong(z, st);
-      }
+      const int g = next.fetch_add(1);
+      if (g >= ng) return;
+      for (int i : groups[g]) st[i] = fn(i);
     }
   };
-  const int t = std::max(1, std::min(threads, n));
+  const int t = std::max(1, std::min(threads, ng));
   std::vector<std::thread> pool;
   for (int k = 1; k < t; ++k) pool.emplace_back(worker);
   worker();
   for (auto &th : pool) th.join();
-  return first_err.load();
 }
 
 chfsi_prec rung_prec(const Prob &p) { return p.o.n_ladder > 0 ? p.o.ladder[p.rung] : CHFSI_FP64; }
@@ -131,7 +132,7 @@ struct chfsi_batch {
   Sweep<double> s64;
   Sweep<float> s32;
   bool verbose = false;
-  int threads = 8;
+  int threads = 8;               // host threads for the per-problem CholGS / Rayleigh-Ritz
   // shared Jacobi eigensolve of the projected Hamiltonians
   chfsi::DevBuf jac_table, jac_norms;
   std::vector<double> jac_host;
@@ -143,6 +144,33 @@ namespace {
 int bfail(chfsi_batch *b, int code, const std::string &msg) {
   if (b) b->err = msg;
   return code;
+}
+
+// A problem leaves the session: converged, out of passes, or failed (status < 0).
+void finish_prob(chfsi_batch *B, Prob &p, int fail_status = 0) {
+  p.done = true;
+  p.rep.max_resid = p.res;
+  p.rep.rung = p.rung;
+  if (fail_status < 0) p.rep.status = fail_status;
+  else p.rep.status = (p.res <= p.o.tol && !p.jac_warn) ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
+  B->finished.push_back(p.id);
+}
+
+// Problems of ids grouped by the HIP stream of their context (positions into ids).
+std::vector<std::vector<int>> stream_groups(chfsi_batch *B, const std::vector<int> &ids) {
+  std::vector<std::vector<int>> groups;
+  std::map<hipStream_t, int> where;
+  for (int i = 0; i < (int)ids.size(); ++i) {
+    hipStream_t s = B->probs[ids[i]].c->stream;
+    auto it = where.find(s);
+    if (it == where.end()) {
+      where[s] = (int)groups.size();
+      groups.push_back({i});
+    } else {
+      groups[it->second].push_back(i);
+    }
+  }
+  return groups;
 }
 
 #define BCHK(b, call)                                                                              \
@@ -255,7 +283,7 @@ int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *m
     Prob &p = B->probs[ids[m]];
     const int nb = p.o.nblock;
     const double a = p.evals[nb - 1], a0 = p.evals[0], b = p.c->ub;
-    if (!(a0 < a && a < b)) return bfail(B, CHFSI_ERR_NONFINITE, "batch: Ritz values outside the filter bounds");
+    if (!(a0 < a && a < b)) return bfail(B, CHFSI_ERR_STATE, "batch: internal: unchecked filter bounds");
     // normalised recursion: rho_1 = 1/xi0, rho_{k+1} = 1/(2 xi0 - rho_k)
     const double cc = 0.5 * (a + b), e = 0.5 * (b - a), xi0 = (a0 - cc) / e;
     double rho = 1.0 / xi0;
@@ -292,14 +320,18 @@ int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *m
   return 0;
 }
 
-// CholGS + RR of problem p; updates its residual, rung and state
 // CholGS + Rayleigh-Ritz of many problems: CholGS and the projection per
 // problem on its own stream (host threads), one batched Jacobi eigensolve of
 // all projected Hamiltonians on the batch stream, then the rotations and
-// residuals per problem.
-int subspace_steps(chfsi_batch *B, const std::vector<int> &ids, bool filtered) {
+// residuals per problem.  A problem whose own step fails (a non-positive-
+// definite overlap, a HIP error on its stream) leaves the session with that
+// status; the others go on.  Returns non-zero only for a failure of the
+// shared eigensolve.
+int subspace_steps(chfsi_batch *B, const std::vector<int> &ids_in, bool filtered) {
+  std::vector<int> ids(ids_in);
   if (ids.empty()) return 0;
-  int st = parallel_for((int)ids.size(), B->threads, [&](int i) {
+  std::vector<int> st(ids.size(), 0);
+  parallel_for_groups(stream_groups(B, ids), B->threads, st, [&](int i) {
     Prob &p = B->probs[ids[i]];
     if (int r = set_dev(p.c)) return r;
     int passes = 0;
@@ -307,21 +339,31 @@ int subspace_steps(chfsi_batch *B, const std::vector<int> &ids, bool filtered) {
     if (int r = rr_project(p.c, p.X, p.ld, p.o.nblock, p.c->HX.as<double>(), p.o.nblock)) return r;
     return hipStreamSynchronize(p.c->stream) == hipSuccess ? 0 : (int)CHFSI_ERR_HIP;
   });
-  if (st) return bfail(B, st, "batch: CholGS or projection of a problem failed");
+  std::vector<int> keep;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    if (st[i] != 0) finish_prob(B, B->probs[ids[i]], st[i] < 0 ? st[i] : CHFSI_ERR_HIP);
+    else keep.push_back(ids[i]);
+  }
+  ids.swap(keep);
+  if (ids.empty()) return 0;
   std::vector<JacobiJob> jobs;
   for (int id : ids) jobs.push_back(rr_eigen_job(B->probs[id].c, B->probs[id].o.nblock));
   BCHK(B, B->jac_table.ensure(jacobi_table_bytes((int)jobs.size())));
   BCHK(B, B->jac_norms.ensure(jacobi_norms_elems((int)jobs.size()) * sizeof(double)));
   B->jac_host.resize(jacobi_norms_elems((int)jobs.size()));
-  if (jacobi_eigh_batch(jobs.data(), (int)jobs.size(), 1e-14, 40, B->jac_table.p, B->jac_norms.as<double>(),
-                        B->jac_host.data(), B->stream, nullptr) != 0)
+  std::vector<int> jconv(jobs.size(), 1);
+  const int jmax = B->probs[ids[0]].c->jac_sweeps;
+  if (jacobi_eigh_batch(jobs.data(), (int)jobs.size(), 1e-14, jmax, B->jac_table.p, B->jac_norms.as<double>(),
+                        B->jac_host.data(), B->stream, nullptr, jconv.data()) < 0)
     return bfail(B, CHFSI_ERR_HIP, "batch: Jacobi eigensolve failed");
   BCHK(B, hipStreamSynchronize(B->stream));
-  st = parallel_for((int)ids.size(), B->threads, [&](int i) {
+  st.assign(ids.size(), 0);
+  parallel_for_groups(stream_groups(B, ids), B->threads, st, [&](int i) {
     Prob &p = B->probs[ids[i]];
     if (int r = set_dev(p.c)) return r;
     if (int r = rr_finish(p.c, p.X, p.ld, p.o.nblock, p.c->HX.as<double>(), p.o.nblock, p.evals, p.resid))
       return r;
+    p.jac_warn = jconv[i] == 0;
     const double nres = max_wanted(p);
     if (filtered) {
       p.rep.iters++;
@@ -333,7 +375,8 @@ int subspace_steps(chfsi_batch *B, const std::vector<int> &ids, bool filtered) {
     p.res = nres;
     return 0;
   });
-  if (st) return bfail(B, st, "batch: Rayleigh-Ritz of a problem failed");
+  for (size_t i = 0; i < ids.size(); ++i)
+    if (st[i] != 0) finish_prob(B, B->probs[ids[i]], st[i] < 0 ? st[i] : CHFSI_ERR_HIP);
   return 0;
 }
 
@@ -353,6 +396,10 @@ extern "C" int chfsi_batch_create(chfsi_batch **out, int device) {
   }
   const char *v = std::getenv("CHFSI_VERBOSE");
   b->verbose = v && v[0] && v[0] != '0';
+  if (const char *t = std::getenv("CHFSI_BATCH_THREADS")) {
+    const int n = std::atoi(t);
+    if (n >= 1 && n <= 256) b->threads = n;
+  }
   *out = b;
   return 0;
 }
@@ -415,13 +462,6 @@ extern "C" int chfsi_batch_report(const chfsi_batch *b, int id, chfsi_report *re
 extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int max_done) {
   if (!b || !n_done || max_done < 0 || (max_done > 0 && !done_ids)) return CHFSI_ERR_ARG;
   if (hipSetDevice(b->device) != hipSuccess) return bfail(b, CHFSI_ERR_HIP, "hipSetDevice");
-  auto finish = [&](Prob &p) {
-    p.done = true;
-    p.rep.max_resid = p.res;
-    p.rep.rung = p.rung;
-    p.rep.status = p.res <= p.o.tol ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
-    b->finished.push_back(p.id);
-  };
   // 1. new problems: CholGS + RR of their start block
   std::vector<int> fresh;
   for (Prob &p : b->probs)
@@ -430,12 +470,21 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   for (int id : fresh) {
     Prob &p = b->probs[id];
     p.started = true;
-    if (p.res <= p.o.tol || p.o.max_iter == 0) finish(p);
+    if (!p.done && (p.res <= p.o.tol || p.o.max_iter == 0)) finish_prob(b, p);
   }
-  // 2. filter sweeps, one per precision group
+  // 2. filter sweeps, one per precision group; a problem whose Ritz values do
+  // not give valid filter bounds (a0 < a < b) leaves with CHFSI_ERR_NONFINITE
   std::vector<int> g32, g64;
-  for (Prob &p : b->probs)
-    if (!p.done) (rung_prec(p) == CHFSI_FP32 ? g32 : g64).push_back(p.id);
+  for (Prob &p : b->probs) {
+    if (p.done) continue;
+    const int nb = p.o.nblock;
+    const double a = p.evals[nb - 1], a0 = p.evals[0], ub = p.c->ub;
+    if (!(a0 < a && a < ub)) {
+      finish_prob(b, p, CHFSI_ERR_NONFINITE);
+      continue;
+    }
+    (rung_prec(p) == CHFSI_FP32 ? g32 : g64).push_back(p.id);
+  }
   float ms32 = 0, ms64 = 0;
   b->build_ms = 0;
   const auto t_sw = std::chrono::steady_clock::now();
@@ -456,7 +505,8 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   int remaining = 0;
   for (int id : swept) {
     Prob &p = b->probs[id];
-    if (p.res <= p.o.tol || p.rep.iters >= p.o.max_iter) finish(p);
+    if (p.done) continue;                         // failed in its CholGS / Rayleigh-Ritz
+    if (p.res <= p.o.tol || p.rep.iters >= p.o.max_iter) finish_prob(b, p);
     else ++remaining;
   }
   if (b->verbose) {
@@ -509,4 +559,30 @@ extern "C" int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts
     if (reps) reps[i] = r;
   }
   return worst;
+}
+
+extern "C" int chfsi_batch_set_threads(chfsi_batch *b, int threads) {
+  if (!b) return CHFSI_ERR_ARG;
+  if (threads < 1 || threads > 256) return bfail(b, CHFSI_ERR_ARG, "batch: threads must be in 1..256");
+  b->threads = threads;
+  return 0;
+}
+
+extern "C" size_t chfsi_batch_footprint_bytes(int n_el, int p, int nblock) {
+  if (n_el < 1 || p < 1 || p > 7 || nblock < 1) return 0;
+  const size_t n = (size_t)n_el * p - 1, nd = n * n * n, ncell = (size_t)n_el * n_el * n_el;
+  if (nd < (size_t)nblock) return 0;
+  const size_t nl = (size_t)(p + 1) * (p + 1) * (p + 1), np = (nl + 15) / 16 * 16, npb = (nl + 31) / 32 * 32;
+  const size_t nb = (size_t)nblock, nb32 = (nb + 31) / 32;
+  // mesh and potential tables (set_mesh, set_potential)
+  size_t b = ncell * nl * 4 + ncell * 4 + np * np * 12 + nd * 24 + npb * npb * 4;
+  // workspaces of the CholGS / Rayleigh-Ritz steps (ensure_small)
+  b += 3 * nb * nb * 8 + nb32 * 32 * 32 * 8 + jacobi_work_elems(nblock) * 8 + 3 * nb * 8 + 4 * sizeof(int) +
+       nb32 * 8;
+  b += rmul_scratch_elems((int64_t)nd, nblock) * 8;
+  b += gram_part_elems_slots((int64_t)nd, nblock, 512) * 8;       // 256 CUs x 2 resident gram work-groups
+  b += (size_t)resid_nchunk((int64_t)nd) * nb * 8;
+  // the session's three recursion buffers (FP64-sized for either rung) and HX
+  b += 4 * nd * nb * 8;
+  return b;
 }

@@ -83,12 +83,7 @@ extern "C" int chfsi_destroy(chfsi_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  DevBuf *all[] = {&c->cmap, &c->cells, &c->K64, &c->K32, &c->minv64, &c->minv32, &c->V64, &c->V32, &c->Kbh, &c->Kbl,
-                   &c->fbuf[0], &c->fbuf[1], &c->fbuf[2], &c->gram_part, &c->Smat, &c->dinv, &c->Zmat,
-                   &c->Wmat, &c->jac_work, &c->evals_d, &c->resid_part, &c->resid_d, &c->flag, &c->HX,
-                   &c->diag0, &c->minratio, &c->rscratch, &c->occ_d, &c->Kc64,
-                   &c->Kcg, &c->kshift, &c->pois_kb, &c->pois_m, &c->pois_work, &c->pois_q};
-  for (DevBuf *b : all) b->release();
+  c->each_buf([](DevBuf &b) { b.release(); });
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return 0;
@@ -431,6 +426,13 @@ extern "C" int chfsi_set_tile_variant(chfsi_ctx *c, int variant) {
   if (!c) return CHFSI_ERR_ARG;
   if (variant < -1 || variant > 1) return fail(c, CHFSI_ERR_ARG, "tile variant must be -1, 0 or 1");
   c->tile_variant = variant;
+  return 0;
+}
+
+extern "C" int chfsi_set_jacobi_sweeps(chfsi_ctx *c, int max_sweeps) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (max_sweeps < 1 || max_sweeps > 1000) return fail(c, CHFSI_ERR_ARG, "Jacobi sweeps must be in 1..1000");
+  c->jac_sweeps = max_sweeps;
   return 0;
 }
 
@@ -806,6 +808,13 @@ static int rr_rotate(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX,
   return 0;
 }
 
+int chfsi::jacobi_warning(chfsi_ctx *c) {
+  char msg[128];
+  std::snprintf(msg, sizeof msg, "Rayleigh-Ritz: the projected eigensolve did not converge in %d Jacobi sweeps",
+                c->jac_sweeps);
+  return fail(c, CHFSI_WARN_NOT_CONVERGED, msg);
+}
+
 // Part 3: X <- X Q, HX = Htilde X (rr_rotate), residual norms; evals and
 // resid to the host.
 int chfsi::rr_finish(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
@@ -825,10 +834,11 @@ int chfsi::rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, i
                    double *resid, int *sweeps) {
   if (int r = rr_project(c, X, ld, ncols, HX, ldh)) return r;
   const JacobiJob job = rr_eigen_job(c, ncols);
-  if (jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, 40, c->host_scratch.data(), c->stream, sweeps) !=
-      0)
-    return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
-  return rr_finish(c, X, ld, ncols, HX, ldh, evals, resid);
+  const int jr = jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, c->jac_sweeps, c->host_scratch.data(),
+                             c->stream, sweeps);
+  if (jr < 0) return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
+  if (int r = rr_finish(c, X, ld, ncols, HX, ldh, evals, resid)) return r;
+  return jr > 0 ? jacobi_warning(c) : 0;
 }
 
 extern "C" int chfsi_rayleigh_ritz(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *evals, double *resid,
@@ -877,9 +887,9 @@ extern "C" int chfsi_rayleigh_ritz_split(chfsi_ctx *c, double *X, int64_t ld, in
     gram_launch(X, ld, HX, ldh, nd, ncols, c->gram_part.as<double>(), G, 0, c->stream);
   // step 2: eigenpairs of Hhat (all of them; the N_fr largest are used)
   const JacobiJob job = rr_eigen_job(c, ncols);
-  if (jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, 40, c->host_scratch.data(), c->stream,
-                  nullptr) != 0)
-    return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
+  const int jr = jacobi_eigh(job.A, ncols, job.work, job.evals, job.Q, 1e-14, c->jac_sweeps, c->host_scratch.data(),
+                             c->stream, nullptr);
+  if (jr < 0) return fail(c, CHFSI_ERR_HIP, "Jacobi eigensolver: HIP error");
   // step 3: partial rotation X Q_fr, into Xfr or over the trailing N_fr
   // columns of X (and Htilde on the rotated columns, for their residuals)
   if (int r = rr_rotate(c, X, ld, ncols, HX, ldh, job.Q + n_oc, n_fr, n_oc, Xfr, ldfr)) return r;
@@ -889,7 +899,7 @@ extern "C" int chfsi_rayleigh_ritz_split(chfsi_ctx *c, double *X, int64_t ld, in
   HIPCHK(c, hipMemcpyAsync(resid_fr, c->resid_d.p, n_fr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipGetLastError());
-  return 0;
+  return jr > 0 ? jacobi_warning(c) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,7 +1017,8 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
   int st = orth_robust(c, X, ld, nb, mixed, &passes);
   if (st) return st;
   HIPCHK(c, hipEventRecord(ev[1], c->stream));
-  if (int r = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr)) return r;
+  int rr_st = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr);
+  if (rr_st < 0) return rr_st;
   HIPCHK(c, hipEventRecord(ev[2], c->stream));
   HIPCHK(c, hipEventSynchronize(ev[2]));
   R.t_cholgs += elapsed_s(ev[0], ev[1]);
@@ -1030,7 +1041,8 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
     st = orth_robust(c, X, ld, nb, mixed, &passes);
     if (st) return st;
     HIPCHK(c, hipEventRecord(ev[5], c->stream));
-    if (int r = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr)) return r;
+    rr_st = rr_impl(c, X, ld, nb, HX, nb, evals, resid, nullptr);
+    if (rr_st < 0) return rr_st;
     HIPCHK(c, hipEventRecord(ev[0], c->stream));
     HIPCHK(c, hipEventSynchronize(ev[0]));
     R.t_filter += elapsed_s(ev[3], ev[4]);
@@ -1055,7 +1067,9 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
   R.iters = it;
   R.rung = rung;
   R.max_resid = res;
-  R.status = res <= o->tol ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
+  // an unconverged projected eigensolve in the last Rayleigh-Ritz leaves
+  // approximate Ritz pairs: reported as not converged
+  R.status = (res <= o->tol && rr_st == 0) ? CHFSI_OK : CHFSI_WARN_NOT_CONVERGED;
   if (rep) *rep = R;
   return R.status;
 }
@@ -1063,6 +1077,14 @@ extern "C" int chfsi_solve(chfsi_ctx *c, const chfsi_opts *o, double *X, int64_t
 // ---------------------------------------------------------------------------
 // footprint
 // ---------------------------------------------------------------------------
+extern "C" int chfsi_device_bytes(const chfsi_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return CHFSI_ERR_ARG;
+  size_t t = 0;
+  const_cast<chfsi_ctx *>(c)->each_buf([&t](DevBuf &b) { t += b.bytes; });
+  *bytes = t;
+  return 0;
+}
+
 extern "C" size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_width, chfsi_prec prec) {
   if (n_el < 1 || p < 1 || p > 7 || nblock < 1) return 0;
   const size_t n = (size_t)n_el * p - 1, nd = n * n * n, ncell = (size_t)n_el * n_el * n_el;

@@ -52,6 +52,7 @@ struct chfsi_ctx {
   int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
   int tile_variant = -1;  // cell-kernel tile configuration (-1: built-in choice)
   int rr_residual = 0;    // Ritz residuals: 0 cost model, 1 rotate HX, 2 apply Htilde again
+  int jac_sweeps = 40;    // cap on Jacobi sweeps of the projected eigensolve
   // workspaces
   chfsi::DevBuf fbuf[3];      // filter recursion buffers
   chfsi::DevBuf occ_d;    // density: fr occupancy weights
@@ -74,6 +75,14 @@ struct chfsi_ctx {
   size_t ev_used = 0;
   int64_t cell_vecs = 0;
   bool verbose = false;   // CHFSI_VERBOSE: one progress line per solve pass on stderr
+  // every device buffer the context owns
+  template <typename F> void each_buf(F f) {
+    chfsi::DevBuf *all[] = {&cmap, &cells, &K64, &K32, &minv64, &minv32, &V64, &V32, &Kbh, &Kbl, &fbuf[0],
+                            &fbuf[1], &fbuf[2], &gram_part, &Smat, &dinv, &Zmat, &Wmat, &jac_work, &evals_d,
+                            &resid_part, &resid_d, &flag, &HX, &diag0, &minratio, &rscratch, &occ_d, &Kc64, &Kcg,
+                            &kshift, &pois_kb, &pois_m, &pois_work, &pois_q};
+    for (chfsi::DevBuf *b : all) f(*b);
+  }
 };
 
 
@@ -91,8 +100,12 @@ int rr_project(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64
 JacobiJob rr_eigen_job(chfsi_ctx *c, int ncols);
 int rr_finish(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals,
               double *resid);
+// Returns CHFSI_WARN_NOT_CONVERGED (with the results of the last Jacobi
+// iterate) when the projected eigensolve ran out of sweeps.
 int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals, double *resid,
             int *sweeps);
+// Records the unconverged-eigensolve message and returns the warning.
+int jacobi_warning(chfsi_ctx *c);
 
 }  // namespace chfsi
 

@@ -159,8 +159,11 @@ struct JacobiJob {
 };
 size_t jacobi_table_bytes(int njobs);
 size_t jacobi_norms_elems(int njobs);
+// Returns -1 on a HIP error, else the number of jobs whose off-diagonal norm
+// had not met tol when max_sweeps sweeps were done (their evals/Q hold the
+// last iterate); converged (may be null) receives 1/0 per job.
 int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_sweeps, void *table, double *norms,
-                      double *host_norms, hipStream_t s, int *sweeps_done);
+                      double *host_norms, hipStream_t s, int *sweeps_done, int *converged);
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
                 double *host_scratch, hipStream_t s, int *sweeps_done);
 // Zero the strictly upper triangle, helpers.

@@ -633,7 +633,7 @@ size_t jacobi_work_elems(int n) {
 size_t jacobi_table_bytes(int njobs) { return (size_t)(njobs > 0 ? njobs : 1) * sizeof(JacProb); }
 
 int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_sweeps, void *table, double *norms,
-                      double *host_norms, hipStream_t s, int *sweeps_done) {
+                      double *host_norms, hipStream_t s, int *sweeps_done, int *converged) {
   if (njobs <= 0) return 0;
   std::vector<JacProb> all(njobs);
   std::vector<int> active(njobs, 1);
@@ -655,8 +655,9 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
   }
   JacProb *dtab = static_cast<JacProb *>(table);
   int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    // convergence of every active problem, one host synchronisation
+  for (;; ++sweep) {
+    // convergence of every active problem, one host synchronisation (also
+    // after the last allowed sweep, so that its result is judged)
     std::vector<JacProb> act;
     std::vector<int> ids;
     for (int k = 0; k < njobs; ++k)
@@ -690,6 +691,7 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
         active[k] = 0;
         continue;
       }
+      if (sweep >= max_sweeps) continue;           // out of sweeps: stays unconverged
       JacProb &J = all[k];
       const int np2 = J.nbp / 2;
       J.first_inner = n_inner;
@@ -720,7 +722,12 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
                        jobs[k].evals, jobs[k].Q);
   }
   if (sweeps_done) *sweeps_done = sweep;
-  return 0;
+  int unconv = 0;
+  for (int k = 0; k < njobs; ++k) {
+    if (converged) converged[k] = active[k] ? 0 : 1;
+    unconv += active[k];
+  }
+  return unconv;
 }
 
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
@@ -731,7 +738,7 @@ int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double
   static_assert(sizeof(JacProb) <= 16 * sizeof(double), "one table entry fits the work tail");
   const JacobiJob job{A, n, work, evals, Q};
   double *tail = work + jacobi_work_elems(n) - JTAIL;
-  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + 16, host_scratch, s, sweeps_done);
+  return jacobi_eigh_batch(&job, 1, tol, max_sweeps, tail, tail + 16, host_scratch, s, sweeps_done, nullptr);
 }
 
 __global__ void fill_kernel(double *X, int64_t n, double v) {

@@ -8,11 +8,15 @@ wavefunctions as the starting guess, Sec. 3.3).
 
 Scheduling (one engine loop over a ``BatchSession``): requests arrive by a
 seeded Poisson process.  At every pass boundary the engine admits waiting
-requests in arrival order while their device footprint (``chfsi_footprint_bytes``
-plus the block) fits the HBM budget next to the requests already running; an
-admitted request gets a context (reused from a pool keyed by mesh, so mesh
-tables stay on the device) and its solve joins the session's shared filter
-sweeps at the next pass.  A solve leaves the session when its wanted
+requests in arrival order while their device footprint (what a context in a
+batch session holds, ``chfsi_batch_footprint_bytes``, plus the block) fits the
+HBM budget next to the requests already running and the idle contexts kept
+for reuse (charged with the bytes they hold; the least recently used are freed
+when a request would not fit otherwise); an admitted request gets a context
+(reused from a pool keyed by mesh, so mesh tables stay on the device) and its
+solve joins the session's shared filter sweeps at the next pass.  A solve that
+fails on its own (its report carries an error status) ends its request, which
+is marked failed; the others go on.  A solve leaves the session when its wanted
 residuals reach the tolerance; the request then starts its next warm solve
 or, after the last one, releases its memory.  The arithmetic of a problem
 does not depend on the other problems sharing its passes, so every result is
@@ -27,7 +31,7 @@ import time
 
 import numpy as np
 
-from . import BatchSession, Context, footprint_bytes
+from . import BatchSession, Context, batch_footprint_bytes
 
 
 @dataclasses.dataclass
@@ -42,6 +46,7 @@ class Request:
     iters: list = dataclasses.field(default_factory=list)
     evals: list = dataclasses.field(default_factory=list)
     converged: bool = True
+    failed: bool = False       # a solve ended with an error status
 
 
 def make_stream(n_requests: int, rate: float, seed: int = 5, sizes=None):
@@ -76,13 +81,15 @@ def _base_potential(prob, ctx):
 
 
 class _ContextPool:
-    """Idle contexts by mesh; each context has its own stream."""
+    """Idle contexts by mesh; each context has its own stream.  ``idle_bytes``
+    is the device memory the idle contexts hold."""
 
     def __init__(self, device: int, idle_cap: int = 16):
         self.device = device
-        self.idle = collections.OrderedDict()   # key -> [ctx, ...]
+        self.idle = collections.OrderedDict()   # key -> [(ctx, bytes), ...]
         self.idle_cap = idle_cap
         self.n_idle = 0
+        self.idle_bytes = 0
 
     def get(self, prob):
         import torch
@@ -91,7 +98,8 @@ class _ContextPool:
         lst = self.idle.get(key)
         if lst:
             self.n_idle -= 1
-            c = lst.pop()
+            c, nb = lst.pop()
+            self.idle_bytes -= nb
             if not lst:
                 del self.idle[key]
             return c
@@ -99,21 +107,40 @@ class _ContextPool:
 
     def put(self, prob, ctx):
         key = (prob.L, prob.n_el, prob.p)
-        self.idle.setdefault(key, []).append(ctx)
+        nb = ctx.device_bytes()
+        self.idle.setdefault(key, []).append((ctx, nb))
         self.idle.move_to_end(key)
         self.n_idle += 1
+        self.idle_bytes += nb
         while self.n_idle > self.idle_cap:
-            k, lst = next(iter(self.idle.items()))
-            lst.pop(0).close()
-            self.n_idle -= 1
-            if not lst:
-                del self.idle[k]
+            self.evict_one()
+
+    def evict_one(self) -> bool:
+        """Free the least recently returned idle context; False if none."""
+        if not self.idle:
+            return False
+        k, lst = next(iter(self.idle.items()))
+        c, nb = lst.pop(0)
+        c.close()
+        self.idle_bytes -= nb
+        self.n_idle -= 1
+        if not lst:
+            del self.idle[k]
+        return True
 
     def close(self):
         for lst in self.idle.values():
-            for c in lst:
+            for c, _ in lst:
                 c.close()
         self.idle.clear()
+        self.n_idle = 0
+        self.idle_bytes = 0
+
+
+def request_footprint(prob) -> int:
+    """Device bytes of one admitted request: its context in the batch session
+    plus its block of vectors."""
+    return batch_footprint_bytes(prob.n_el, prob.p, prob.nblock) + prob.n_dof * prob.nblock * 8
 
 
 def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-6, degree: int = 20,
@@ -126,8 +153,7 @@ def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-
     import workload
 
     for r in requests:
-        r.footprint = footprint_bytes(r.problem.n_el, r.problem.p, r.problem.nblock, 0, ladder[0]) \
-            + r.problem.n_dof * r.problem.nblock * 8
+        r.footprint = request_footprint(r.problem)
         if r.footprint > hbm_budget:
             raise ValueError(f"request {r.rid} needs {r.footprint} B, above the HBM budget")
     order = sorted(requests, key=lambda r: r.arrival)
@@ -155,18 +181,26 @@ def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-
             while nxt < len(order) and (not realtime or order[nxt].arrival <= t):
                 waiting.append(order[nxt])
                 nxt += 1
-            # admission at the pass boundary
-            while waiting and len(running) < max_active and in_use + waiting[0].footprint <= hbm_budget:
+            # admission at the pass boundary; idle contexts count against the
+            # budget and are freed (least recently used first) to make room
+            while waiting and len(running) < max_active:
+                need = waiting[0].footprint
+                while in_use + pool.idle_bytes + need > hbm_budget and pool.evict_one():
+                    pass
+                if in_use + pool.idle_bytes + need > hbm_budget:
+                    break
                 req = waiting.popleft()
-                in_use += req.footprint
                 req.admitted = now()
                 ctx = pool.get(req.problem)
+                # a reused context may hold more than the estimate (buffers only grow)
+                req.footprint = max(need, ctx.device_bytes() + req.problem.n_dof * req.problem.nblock * 8)
+                in_use += req.footprint
                 X = workload.start_block_device(req.problem.n_dof, req.problem.nblock, req.problem.x0_seed,
                                                 device=f"cuda:{device}")
                 torch.cuda.synchronize(device)
                 start_solve([req, ctx, X, _base_potential(req.problem, ctx), 0, 0.0], 0)
             if not running:
-                if waiting:
+                if waiting and pool.idle_bytes == 0:
                     raise RuntimeError("a waiting request cannot be admitted (budget)")
                 if nxt < len(order):
                     time.sleep(max(0.0, order[nxt].arrival - now()))
@@ -179,7 +213,9 @@ def serve(requests, hbm_budget: float = 160e9, solves: int = 5, tol: float = 1e-
                 req.iters.append(res["iters"])
                 req.evals.append(res["evals"][:req.problem.nstates].copy())
                 req.converged = req.converged and res["converged"]
-                if s + 1 < solves:
+                if res["status"] < 0:
+                    req.failed = True
+                if s + 1 < solves and not req.failed:
                     start_solve(entry, s + 1)
                 else:
                     req.done = now()

@@ -62,3 +62,124 @@ def test_batch_fp32_filter_within_its_floor():
     for p in probs:
         p["ctx"].close()
         p["ctx_single"].close()
+
+
+def test_a_failing_problem_leaves_and_the_others_are_unaffected():
+    """A zero start block has a zero overlap matrix: its CholGS fails
+    (CHFSI_ERR_NOT_SPD) even with the shifted Cholesky QR.  That problem
+    leaves the session with its own status; the healthy problems' results are
+    bitwise those of the session without it."""
+    import paper_1903_10959_amd as P
+    probs = _problems()[:3]
+    runs = []
+    for with_bad in (False, True):
+        sess = P.BatchSession(0)
+        Xs = [to_gpu(p["X0"]) for p in probs]
+        ids = [sess.add(p["ctx"], X, p["N"], 20, 1e-9, max_iter=300, ladder=("fp64",)) for p, X in zip(probs, Xs)]
+        bad_id = None
+        if with_bad:
+            pb = probs[0]
+            Xbad = to_gpu(np.zeros_like(pb["X0"]))
+            bad_id = sess.add(pb["ctx_single"], Xbad, pb["N"], 20, 1e-9, max_iter=300, ladder=("fp64",))
+        res = {}
+        while True:
+            rem, fin = sess.step()
+            res.update(dict(fin))
+            if rem == 0:
+                break
+        if with_bad:
+            assert res[bad_id]["status"] == -5 and not res[bad_id]["converged"]
+        runs.append(([res[i] for i in ids], [to_host(X) for X in Xs]))
+        sess.close()
+    for (ra, xa), (rb, xb) in zip(zip(*runs[0]), zip(*runs[1])):
+        assert ra["converged"] and rb["converged"]
+        np.testing.assert_array_equal(ra["evals"], rb["evals"])
+        np.testing.assert_array_equal(xa, xb)
+    for p in probs:
+        p["ctx"].close()
+        p["ctx_single"].close()
+
+
+def test_a_config4_sized_member_matches_the_oracle_on_sampled_columns():
+    """The largest batched size (12^3 cells, p = 7, 571,787 DoFs, 288
+    vectors), one FP64 pass through the session: bitwise the single-context
+    pass, and its Ritz pairs checked column by column against the Kronecker
+    oracle (Rayleigh quotients and residual norms)."""
+    import paper_1903_10959_amd as P
+    from gpu_util import oracle_apply
+    n_el, p, N = 12, 7, 256
+    L = 2.5 * n_el
+    wells = workload.draw_wells(max(4, round(L ** 3 / 1000)), L, 4077, (1.0, 3.0), (0.5, 1.5))
+    c, V = make_ctx(L, n_el, p, wells=wells)
+    c2, _ = make_ctx(L, n_el, p, V=V)
+    nb = workload.block_size(N)
+    X0 = workload.start_block_device(c.n_dof, nb, 4177)
+    Xb, Xs = X0.clone(), X0.clone()
+    sess = P.BatchSession(0)
+    pid = sess.add(c, Xb, N, 20, 1e-30, max_iter=1, ladder=("fp64",))
+    rem, fin = sess.step()
+    assert rem == 0 and fin[0][0] == pid
+    r = fin[0][1]
+    s = c2.solve(Xs, N, 20, 1e-30, max_iter=1, block_width=nb)
+    np.testing.assert_array_equal(r["evals"], s["evals"])
+    assert bool((Xb == Xs).all())
+    ap = oracle_apply(L, n_el, p, V)
+    cols = np.arange(0, nb, 23)
+    Xh = to_host(Xb[:, cols])
+    HX = ap(Xh)
+    rq = np.sum(Xh * HX, axis=0)
+    scale = np.max(np.abs(r["evals"]))
+    np.testing.assert_allclose(r["evals"][cols], rq, rtol=0, atol=1e-11 * scale)
+    res = np.linalg.norm(HX - Xh * r["evals"][cols][None, :], axis=0)
+    np.testing.assert_allclose(r["resid"][cols], res, rtol=1e-6, atol=1e-10 * scale)
+    sess.close()
+    c.close()
+    c2.close()
+
+
+def test_batch_footprint_matches_device_memory_of_the_largest_member():
+    """chfsi_batch_footprint_bytes against what the context holds after it
+    joins a session, and against the device memory that disappeared."""
+    import torch
+    import paper_1903_10959_amd as P
+    n_el, p, N = 12, 7, 256
+    nb = workload.block_size(N)
+    L = 2.5 * n_el
+    X = workload.start_block_device((n_el * p - 1) ** 3, nb, 4178)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    c = P.Context(0).set_mesh(L, n_el, p)
+    c.set_potential(np.zeros(c.n_dof))
+    sess = P.BatchSession(0)
+    sess.add(c, X, N, 20, 1e-6, max_iter=1)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    held = c.device_bytes()
+    est = P.batch_footprint_bytes(n_el, p, nb)
+    assert abs(est - held) <= 0.01 * held + (16 << 20), (est, held)
+    used = free0 - free1
+    assert held <= used + (64 << 20) and used <= 1.05 * held + (256 << 20), (held, used)
+    sess.close()
+    c.close()
+
+
+def test_jacobi_sweep_cap_is_reported():
+    """With one Jacobi sweep the projected eigensolve of a random block cannot
+    converge: both forms of rayleighRitz report CHFSI_WARN_NOT_CONVERGED."""
+    from oracle import chfsi as och
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = to_gpu(och.cholgs(workload.start_block(c.n_dof, 120, 61)))
+    c.rayleigh_ritz(X.clone())
+    assert c.last_eigensolve_converged
+    c.set_jacobi_sweeps(1)
+    ev, rs = c.rayleigh_ritz(X.clone())
+    assert not c.last_eigensolve_converged and np.all(np.isfinite(ev))
+    assert b"Jacobi" in c._lib.chfsi_last_error(c._h)
+    ev, rs = c.rayleigh_ritz_split(X.clone(), 20, mixed=False)
+    assert not c.last_eigensolve_converged and np.all(np.isfinite(ev))
+    c.set_jacobi_sweeps(40)
+    c.rayleigh_ritz_split(X.clone(), 20, mixed=False)
+    assert c.last_eigensolve_converged
+    c.close()

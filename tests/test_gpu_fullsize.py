@@ -24,10 +24,69 @@ def test_apply_full_size_sampled_columns(name):
     Yo = oracle_apply(prob.L, prob.n_el, prob.p, V)(Xs)
     rel = np.max(np.abs(Ys - Yo)) / np.max(np.abs(Yo))
     assert rel < 1e-13, rel
-    # FP32 path on the same block: FP32 rounding level
-    Y32 = c.apply(X, prec="fp32")[:, cols].cpu().numpy()
-    assert np.max(np.abs(Y32 - Yo)) / np.max(np.abs(Yo)) < 2e-6
+    # reduced-precision paths on the same block, per output against a bound
+    # from the format's unit roundoff: |dY_i| <= (k u + n_loc u32) (|H||x|)_i
+    # (k = 3 covers the rounding of both BF16 operands, or the dropped lo*lo
+    # term of the split; n_loc u32 the FP32 accumulation)
+    A = fem.operator_1d(prob.L, prob.n_el, prob.p)
+    HabsX = fem.apply_kron(np.abs(A), np.abs(V), np.abs(Xs))
+    n_loc = (prob.p + 1) ** 3
+    u32 = 2.0 ** -24
+    for prec, u, floor in (("fp32", u32, 0.0), ("bf16", 2.0 ** -8, 1e-4), ("bf16x3", 2.0 ** -16, 1e-8)):
+        Yp = c.apply(X, prec=prec)[:, cols].cpu().numpy()
+        err = np.abs(Yp - Yo)
+        bound = (3.0 * u + n_loc * u32) * HabsX
+        assert np.all(err <= bound), (prec, np.max(err / bound))
+        # and the reduced format really ran (its error is above FP64 level)
+        assert np.max(err / HabsX) > floor, (prec, np.max(err / HabsX))
     del X, Y
+    torch.cuda.empty_cache()
+    c.close()
+
+
+def _ho_levels(L, n_el, p, om, count):
+    """Exact discrete eigenvalues of the separable harmonic-oscillator operator:
+    sums of three eigenvalues of the 1D operator with the 1D potential."""
+    A = fem.operator_1d(L, n_el, p)
+    x = fem.node_coords_1d(L, n_el, p)[1:-1]
+    a = np.linalg.eigvalsh(A + np.diag(0.5 * om * om * (x - L / 2) ** 2))[:12]
+    return np.sort((a[:, None, None] + a[None, :, None] + a[None, None, :]).reshape(-1))[:count]
+
+
+@pytest.mark.parametrize("name,ladder,mixed", [("large_p6", ("fp64",), False),
+                                               ("large_p6", ("bf16", "fp32", "fp64"), True),
+                                               ("large_p5", ("fp64",), False)])
+def test_solve_harmonic_oscillator_at_full_mesh_shape(name, ladder, mixed):
+    """The full solve on the workload's mesh (24^3 cells p = 6, or 32^3 cells
+    p = 5) with V = 1/2 |x - L/2|^2 (separable, so the exact discrete
+    eigenvalues are sums of 1D ones): the lowest 56 states (the shells
+    n = 0..5 of omega (n + 3/2), a cluster boundary) to 1e-10 relative on the
+    FP64 path; on the BF16 -> FP32 -> FP64 ladder with the mixed CholGS to the
+    1e-6 Ha residual target (a residual bounds the eigenvalue error)."""
+    import torch
+    prob = workload.PROBLEMS[name]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, V=None)
+    V = workload.harmonic(c.dof_coords(), 1.0, [prob.L / 2] * 3)
+    c.set_potential(V)
+    N = 56
+    ref = _ho_levels(prob.L, prob.n_el, prob.p, 1.0, N + 1)
+    assert ref[N] - ref[N - 1] > 0.5                   # the shell boundary
+    nb = workload.block_size(N)
+    X = workload.start_block_device(prob.n_dof, nb, 91, device="cuda:0")
+    fp64 = ladder == ("fp64",)
+    tol = 1e-9 * max(1.0, abs(ref[0])) if fp64 else 1e-6
+    out = c.solve(X, N, prob.degree, tol, max_iter=200, ladder=ladder, mixed_cholgs=mixed)
+    assert out["converged"], out
+    err = np.abs(out["evals"][:N] - ref[:N])
+    if fp64:
+        assert np.max(err / np.maximum(np.abs(ref[:N]), 1.0)) < 1e-10, err
+    else:
+        assert np.max(err) < 1e-6, err
+    cols = [0, 9, 20, 55]
+    Xs = X[:, cols].cpu().numpy()
+    r_cpu = np.linalg.norm(oracle_apply(prob.L, prob.n_el, prob.p, V)(Xs) - Xs * out["evals"][cols][None, :], axis=0)
+    np.testing.assert_allclose(out["resid"][cols], r_cpu, rtol=1e-6, atol=1e-12)
+    del X
     torch.cuda.empty_cache()
     c.close()
 

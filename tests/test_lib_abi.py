@@ -101,3 +101,29 @@ def test_footprint_is_consistent():
     # at least X-sized HX workspace plus three filter buffers
     assert big >= nd * 568 * 8 + 3 * nd * 128 * 8
     assert P.footprint_bytes(24, 6, 568, 128, "fp32") < big
+
+
+@pytest.mark.parametrize("p", [8, 9, 12])
+def test_degrees_without_a_cell_kernel_are_rejected_at_set_mesh(p):
+    """The header's range is p = 1..7 (the degrees the device cell kernels
+    are built for): a higher degree fails at set_mesh, not at the first apply."""
+    P = _lib_or_skip()
+    c = P.Context(device=-1)
+    with pytest.raises(P.ChfsiError) as ei:
+        c.set_mesh(10.0, 2, p)
+    assert ei.value.status == -1
+    assert P.footprint_bytes(2, p, 8) == 0 and P.batch_footprint_bytes(2, p, 8) == 0
+
+
+def test_batch_footprint_counts_every_session_buffer():
+    """What a context holds in a batch session: at least its three FP64-sized
+    recursion buffers, HX and the N_b x N_b matrices, and no less than the
+    standalone-solve footprint with an FP32 filter of the same width."""
+    P = _lib_or_skip()
+    n_el, p, nb = 12, 7, 288
+    nd = (n_el * p - 1) ** 3
+    fb = P.batch_footprint_bytes(n_el, p, nb)
+    assert fb >= 4 * nd * nb * 8 + 3 * nb * nb * 8
+    assert fb >= P.footprint_bytes(n_el, p, nb, nb, "fp32")
+    assert fb < 6 * nd * nb * 8
+    assert P.batch_footprint_bytes(4, 4, 24) < fb
