@@ -179,6 +179,40 @@ int chfsi_set_kpoint(chfsi_ctx *ctx, double kx, double ky, double kz);
  * a periodic mesh and potential, CHFSI_ERR_ARG for bad block arguments. */
 int chfsi_apply_complex(chfsi_ctx *ctx, const void *X, void *Y, int64_t ld, int ncols);
 
+/* ---- ChFSI at a k-point (Sec. 2.1 eq. ksproblemPer; Sec. 3.3 - 3.5 in their
+ * Hermitian form) -------------------------------------------------------------
+ * The eigenpairs of the complex Hermitian Htilde_k of chfsi_set_kpoint, on
+ * complex128 blocks laid out as for chfsi_apply_complex (ld, ncols in complex
+ * elements; caller-owned device arrays).  FP64 throughout.  Every call needs
+ * a periodic mesh and a potential (CHFSI_ERR_STATE otherwise) and at most
+ * 2048 columns (CHFSI_ERR_ARG).
+ * chfsi_get_upper_bound_k: b = sum_d lambda_max(A_{k_d}) + max V, the Weyl
+ *   bound of the Kronecker sum of the three 1D Bloch operators plus the
+ *   potential (host eigensolve of each 1D operator; above 200 nodes per
+ *   direction a Gershgorin bound).
+ * chfsi_chebyshev_filter_complex: in place, X <- T_m(Hbar_k) X / T_m(xi0) with
+ *   Hbar_k = (Htilde_k - c)/e as for chfsi_chebyshev_filter (real coefficients,
+ *   the complex cell kernel); CHFSI_ERR_NONFINITE on NaN/Inf.
+ * chfsi_orthonormalize_complex: CholGS in complex arithmetic, S = X^H X =
+ *   L L^H, X <- X L^-H (X^H X = I); CHFSI_ERR_NOT_SPD as the real call.
+ * chfsi_rayleigh_ritz_complex: for orthonormal X, Hhat = X^H Htilde_k X
+ *   (Hermitian), Hhat Q = Q D (D ascending), X <- X Q; evals and resid host
+ *   [ncols], resid[i] = ||Htilde_k x_i - D_i x_i||_2; HX_out (device complex
+ *   [n_dof x ld] or NULL) receives Htilde_k X.  The projected eigensolve runs
+ *   as the real symmetric 2 ncols x 2 ncols form [[Re, Im], [-Im, Re]] (FP64
+ *   Jacobi; every eigenvalue appears twice and one complex eigenvector is
+ *   taken per pair): CHFSI_ERR_NONFINITE if the pairs cannot be resolved,
+ *   CHFSI_WARN_NOT_CONVERGED if the Jacobi sweep cap ended it.
+ * chfsi_solve_complex: the loop of chfsi_solve on these steps; opts as there
+ *   with no precision ladder beyond FP64 and mixed_cholgs = 0 (CHFSI_ERR_ARG
+ *   otherwise); b from chfsi_get_upper_bound_k.  Errors and report as
+ *   chfsi_solve. */
+int chfsi_get_upper_bound_k(const chfsi_ctx *ctx, double *b);
+int chfsi_chebyshev_filter_complex(chfsi_ctx *ctx, void *X, int64_t ld, int ncols, int degree, double a, double b,
+                                   double a0, int block_width);
+int chfsi_orthonormalize_complex(chfsi_ctx *ctx, void *X, int64_t ld, int ncols);
+int chfsi_rayleigh_ritz_complex(chfsi_ctx *ctx, void *X, int64_t ld, int ncols, double *evals, double *resid,
+                                void *HX_out);
 /* A group of k-points on one periodic mesh (the paper's k-point
  * parallelisation, Sec. 3.7, as one launch per colour): chfsi_set_kpoints
  * takes nk wave vectors (host, 3 nk values, k-point g at k[3g .. 3g+2]) and
@@ -278,6 +312,10 @@ typedef struct {
 
 int chfsi_solve(chfsi_ctx *ctx, const chfsi_opts *o, double *X, int64_t ld,
                 double *evals, double *resid, chfsi_report *rep);
+/* The solve on the complex Bloch operator at the context's k-point (see
+ * chfsi_solve_complex above). */
+int chfsi_solve_complex(chfsi_ctx *ctx, const chfsi_opts *o, void *X, int64_t ld,
+                        double *evals, double *resid, chfsi_report *rep);
 
 /* ---- solveBatch (many independent problems; the paper's k-point groups,
  * Sec. 3.7, placed on one device) ---------------------------------------------

@@ -387,6 +387,59 @@ class Context:
                                                   int(X.stride(0)), int(X.shape[1])), "apply_complex")
         return Y
 
+    # ---- ChFSI at the k-point (complex Hermitian operator) -------------------
+    @staticmethod
+    def _cblock(X):
+        import torch
+
+        if not isinstance(X, torch.Tensor) or X.dtype != torch.complex128 or not X.is_cuda or X.dim() != 2:
+            raise TypeError("expected a 2-D complex128 CUDA tensor [n_dof, ncols]")
+        if X.shape[1] > 1 and X.stride(1) != 1:
+            raise ValueError("columns must be contiguous (stride(1) == 1)")
+        return C.c_void_p(X.data_ptr()), int(X.stride(0)), int(X.shape[1])
+
+    @property
+    def upper_bound_k(self) -> float:
+        b = C.c_double()
+        self._check(self._lib.chfsi_get_upper_bound_k(self._h, C.byref(b)), "get_upper_bound_k")
+        return b.value
+
+    def chebyshev_filter_complex(self, X, degree: int, a: float, b: float, a0: float, block_width: int = 0):
+        px, ld, n = self._cblock(X)
+        self._check(self._lib.chfsi_chebyshev_filter_complex(self._h, px, ld, n, int(degree), float(a), float(b),
+                                                             float(a0), int(block_width)), "chebyshev_filter_complex")
+        return X
+
+    def orthonormalize_complex(self, X):
+        px, ld, n = self._cblock(X)
+        self._check(self._lib.chfsi_orthonormalize_complex(self._h, px, ld, n), "orthonormalize_complex")
+        return X
+
+    def rayleigh_ritz_complex(self, X, HX_out=None):
+        px, ld, n = self._cblock(X)
+        ev, rs = np.empty(n), np.empty(n)
+        ph = C.c_void_p(0)
+        if HX_out is not None:
+            ph, ldh, nh = self._cblock(HX_out)
+            if ldh != ld or nh != n:
+                raise ValueError("HX_out must match X")
+        st = self._check(self._lib.chfsi_rayleigh_ritz_complex(self._h, px, ld, n, ev.ctypes.data_as(C.c_void_p),
+                                                               rs.ctypes.data_as(C.c_void_p), ph),
+                         "rayleigh_ritz_complex", ok=(0, _lib.WARN_NOT_CONVERGED))
+        self.last_eigensolve_converged = st == 0
+        return ev, rs
+
+    def solve_complex(self, X, nstates: int, degree: int, tol: float, max_iter: int = 200, block_width: int = 0):
+        px, ld, nb = self._cblock(X)
+        o = _opts(nstates, nb, degree, tol, max_iter, block_width, ("fp64",), None, False)
+        ev, rs = np.empty(nb), np.empty(nb)
+        rep = Report()
+        st = self._lib.chfsi_solve_complex(self._h, C.byref(o), px, ld, ev.ctypes.data_as(C.c_void_p),
+                                           rs.ctypes.data_as(C.c_void_p), C.byref(rep))
+        self._check(st, "solve_complex", ok=(0, _lib.WARN_NOT_CONVERGED))
+        return dict(evals=ev, resid=rs, status=st, converged=(st == 0), iters=rep.iters, t_filter=rep.t_filter,
+                    t_cholgs=rep.t_cholgs, t_rr=rep.t_rr, max_resid=rep.max_resid, dofvecs=rep.dofvecs)
+
     def cheb_step(self, X, Xprev, Y, s1: float, s2: float, shift: float):
         px, ld, n = self._block(X)
         py, ldy, _ = self._block(Y)

@@ -170,6 +170,7 @@ static int set_mesh_impl(chfsi_ctx *c, double L, int n_el, int p, bool periodic)
   HIPCHK(c, hipMemcpyAsync(c->Kbl.p, kl.data(), nb2 * 2, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
   c->kvec[0] = c->kvec[1] = c->kvec[2] = 0.0;
+  c->kin_k = 3.0 * c->mesh.lam1d_max;            // k = 0: the real periodic operator's bound
   c->nk = 0;                                     // a k-point group belongs to its mesh
   if (M.periodic)
     if (int r = upload_kpoint(c)) return r;
@@ -215,6 +216,16 @@ extern "C" int chfsi_set_kpoint(chfsi_ctx *c, double kx, double ky, double kz) {
   c->kvec[0] = kx;
   c->kvec[1] = ky;
   c->kvec[2] = kz;
+  // the kinetic part of the spectral bound at k (A_{-k} is the conjugate of A_k)
+  double kin = 0;
+  for (int d = 0; d < 3; ++d) {
+    const double kd = std::fabs(c->kvec[d]);
+    int same = -1;
+    for (int e = 0; e < d; ++e)
+      if (std::fabs(c->kvec[e]) == kd) same = e;
+    kin += same >= 0 ? bloch_1d_max(c->mesh, std::fabs(c->kvec[same])) : bloch_1d_max(c->mesh, kd);
+  }
+  c->kin_k = kin;
   if (c->device < 0) return 0;
   if (int r = set_dev(c)) return r;
   return upload_kpoint(c);
@@ -410,6 +421,13 @@ extern "C" int chfsi_get_upper_bound(const chfsi_ctx *c, double *b) {
   if (!c || !c->has_pot) return CHFSI_ERR_STATE;
   if (!b) return CHFSI_ERR_ARG;
   *b = c->ub;
+  return 0;
+}
+
+extern "C" int chfsi_get_upper_bound_k(const chfsi_ctx *c, double *b) {
+  if (!c || !c->has_pot || !c->mesh.periodic) return CHFSI_ERR_STATE;
+  if (!b) return CHFSI_ERR_ARG;
+  *b = c->kin_k + c->vmax;
   return 0;
 }
 
@@ -696,24 +714,25 @@ int chfsi::ensure_small(chfsi_ctx *c, int n) {
   return 0;
 }
 
-// CholGS on X (Alg. 3).  shift_rel > 0 factors S + shift_rel * max(diag S) I
-// (shifted Cholesky QR).  *rmin receives min_j d_j / S_jj over the pivots.
-static int cholgs_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed, double shift_rel, double *rmin) {
-  if (int r = ensure_small(c, ncols)) return r;
+// CholGS on X (Alg. 3) with the workspace w.  shift_rel > 0 factors
+// S + shift_rel * max(diag S) I (shifted Cholesky QR).  *rmin receives
+// min_j d_j / S_jj over the pivots.
+int chfsi::cholgs_core(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed, double shift_rel, double *rmin,
+                       const CholWs &w) {
   const int64_t nd = c->mesh.n_dof;
   const int nb32 = (ncols + 31) / 32;
-  double *S = c->Smat.as<double>();
-  gram_launch(X, ld, X, ld, nd, ncols, c->gram_part.as<double>(), S, mixed ? 1 : 0, c->stream);
-  zero_int_launch(c->flag.as<int>(), 1, c->stream);
-  potrf_launch(S, ncols, c->dinv.as<double>(), c->flag.as<int>(), c->diag0.as<double>(), c->minratio.as<double>(),
-               shift_rel, c->stream);
+  if (gram_launch_capped(X, ld, X, ld, nd, ncols, w.part, w.part_elems, w.G ? w.G : w.S, mixed ? 1 : 0,
+                         c->stream) != 0)
+    return fail(c, CHFSI_ERR_ARG, "orthonormalize: overlap workspace too small");
+  if (w.G) herm_embed_launch(w.G, ncols, w.S, c->stream);   // complex: S = emb(X^H X)
+  zero_int_launch(w.flag, 1, c->stream);
+  potrf_launch(w.S, ncols, w.dinv, w.flag, w.diag0, w.minratio, shift_rel, c->stream);
   int hflag = 0;
-  double *hr = c->host_scratch.data();
-  HIPCHK(c, hipMemcpyAsync(&hflag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(hr, c->minratio.p, nb32 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(w.host_ratio, w.minratio, nb32 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double m = 1.0;
-  for (int i = 0; i < nb32; ++i) m = std::min(m, hr[i]);
+  for (int i = 0; i < nb32; ++i) m = std::min(m, w.host_ratio[i]);
   if (rmin) *rmin = m;
   if (hflag) {
     char msg[160];
@@ -721,11 +740,33 @@ static int cholgs_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed
                   hflag - 1, m);
     return fail(c, CHFSI_ERR_NOT_SPD, msg);
   }
-  trtri_t_launch(S, c->dinv.as<double>(), ncols, c->Zmat.as<double>(), c->Wmat.as<double>(), c->stream);
-  if (rmul_launch(X, ld, nd, ncols, c->Wmat.as<double>(), 1, mixed ? 1 : 0, c->rscratch.as<double>(), c->rscratch.bytes / sizeof(double), c->stream) != 0)
+  trtri_t_launch(w.S, w.dinv, ncols, w.Z, w.W, c->stream);
+  if (rmul_launch(X, ld, nd, ncols, w.W, 1, mixed ? 1 : 0, w.panel, w.panel_elems, c->stream) != 0)
     return fail(c, CHFSI_ERR_ARG, "orthonormalize: block too wide for the row-panel kernel");
   HIPCHK(c, hipGetLastError());
   return 0;
+}
+
+// CholGS with the context's own (grown on demand) workspace; cplx: X is a
+// complex block as interleaved reals (ld, ncols count reals).
+static int cholgs_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed, double shift_rel, double *rmin,
+                       bool cplx = false) {
+  if (int r = ensure_small(c, ncols)) return r;
+  CholWs w;
+  if (cplx) w.G = c->Zmat.as<double>();     // consumed before the inverse uses Z
+  w.part = c->gram_part.as<double>();
+  w.part_elems = c->gram_part.bytes / sizeof(double);
+  w.S = c->Smat.as<double>();
+  w.Z = c->Zmat.as<double>();
+  w.W = c->Wmat.as<double>();
+  w.dinv = c->dinv.as<double>();
+  w.diag0 = c->diag0.as<double>();
+  w.minratio = c->minratio.as<double>();
+  w.flag = c->flag.as<int>();
+  w.panel = c->rscratch.as<double>();
+  w.panel_elems = c->rscratch.bytes / sizeof(double);
+  w.host_ratio = c->host_scratch.data();
+  return cholgs_core(c, X, ld, ncols, mixed, shift_rel, rmin, w);
 }
 
 extern "C" int chfsi_orthonormalize(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed) {
@@ -736,21 +777,21 @@ extern "C" int chfsi_orthonormalize(chfsi_ctx *c, double *X, int64_t ld, int nco
 // The solve's orthonormalisation: CholGS, repeated while the smallest relative
 // pivot shows lost orthogonality (CholeskyQR2), with the shifted Cholesky QR
 // of Fukaya et al. when the overlap is numerically singular.
-int chfsi::orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes) {
+int chfsi::orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes, bool cplx) {
   double rmin = 1.0;
   int np = 1;
-  int st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin);
+  int st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin, cplx);
   if (st == CHFSI_ERR_NOT_SPD) {
     const double u = 1.1102230246251565e-16;
     const double m = (double)c->mesh.n_dof, n = nb;
     const double shift_rel = 11.0 * (m * n + n * (n + 1.0)) * u * n;
-    st = cholgs_impl(c, X, ld, nb, mixed, shift_rel, &rmin);
+    st = cholgs_impl(c, X, ld, nb, mixed, shift_rel, &rmin, cplx);
     rmin = 0.0;
     ++np;
   }
   if (st) return st;
   for (int k = 0; k < 3 && rmin < 1e-2; ++k) {
-    st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin);
+    st = cholgs_impl(c, X, ld, nb, mixed, 0.0, &rmin, cplx);
     ++np;
     if (st) return st;
   }
@@ -781,7 +822,7 @@ chfsi::JacobiJob chfsi::rr_eigen_job(chfsi_ctx *c, int ncols) {
 // applied again (the cell products, 2 n_cells np^2 flops per column, which run
 // at a lower fraction of peak than the GEMM: weighted 1.4).  Both give Htilde
 // times the rotated columns; the cheaper is taken unless the mode forces one.
-static bool rr_reapply(const chfsi_ctx *c, int ncols) {
+bool chfsi::rr_reapply(const chfsi_ctx *c, int ncols) {
   if (c->rr_residual != 0) return c->rr_residual == 2;
   const MeshTables &M = c->mesh;
   const double cells = (double)M.n_el * M.n_el * M.n_el;

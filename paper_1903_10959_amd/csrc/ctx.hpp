@@ -58,6 +58,8 @@ struct chfsi_ctx {
   chfsi::DevBuf occ_d;    // density: fr occupancy weights
   chfsi::DevBuf Kc64;     // periodic mesh: [A ; (k.G)^T] complex cell operator, 2 np x np
   double kvec[3] = {0, 0, 0};
+  double kin_k = 0;       // sum over directions of lambda_max of the 1D Bloch operators at kvec
+  chfsi::DevBuf csel;     // complex Rayleigh-Ritz: selected Ritz values and the pairing status
   chfsi::DevBuf Kcg, kshift; // k-point group: nk cell operators and |k|^2/2 shifts
   // Poisson: 1D band / mass tables (for the mesh they were built for), CG
   // workspace, point charges
@@ -80,7 +82,7 @@ struct chfsi_ctx {
     chfsi::DevBuf *all[] = {&cmap, &cells, &K64, &K32, &minv64, &minv32, &V64, &V32, &Kbh, &Kbl, &fbuf[0],
                             &fbuf[1], &fbuf[2], &gram_part, &Smat, &dinv, &Zmat, &Wmat, &jac_work, &evals_d,
                             &resid_part, &resid_d, &flag, &HX, &diag0, &minratio, &rscratch, &occ_d, &Kc64, &Kcg,
-                            &kshift, &pois_kb, &pois_m, &pois_work, &pois_q};
+                            &kshift, &pois_kb, &pois_m, &pois_work, &pois_q, &csel};
     for (chfsi::DevBuf *b : all) f(*b);
   }
 };
@@ -92,8 +94,28 @@ int fail(chfsi_ctx *c, int code, const std::string &msg);
 int set_dev(chfsi_ctx *c);
 int check_block(chfsi_ctx *c, const void *X, int64_t ld, int ncols);
 int ensure_small(chfsi_ctx *c, int n);
-// the solve's CholGS (CholeskyQR2 / shifted Cholesky QR when needed)
-int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes);
+// Workspace of one CholGS: device buffers for the overlap's split partials
+// (part_elems doubles), S, the 32x32 diagonal inverses, Z and W (n x n each),
+// the pivot diagnostics and the rotation's row panel (panel_elems doubles),
+// and a host array of ceil(n/32) doubles for the pivot ratios.
+struct CholWs {
+  double *part = nullptr;
+  size_t part_elems = 0;
+  // complex blocks (interleaved re, im; ncols counts real columns): the raw
+  // real Gram of the interleaved columns goes to G and its Hermitian
+  // embedding to S (null for real blocks)
+  double *G = nullptr;
+  double *S = nullptr, *Z = nullptr, *W = nullptr, *dinv = nullptr, *diag0 = nullptr, *minratio = nullptr;
+  int *flag = nullptr;
+  double *panel = nullptr;
+  size_t panel_elems = 0;
+  double *host_ratio = nullptr;
+};
+int cholgs_core(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed, double shift_rel, double *rmin,
+                const CholWs &w);
+// the solve's CholGS (CholeskyQR2 / shifted Cholesky QR when needed); cplx:
+// X is a complex block seen as interleaved reals (ld and nb count reals)
+int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes, bool cplx = false);
 // Rayleigh-Ritz with HX in a caller buffer; evals/resid on the host
 // Rayleigh-Ritz in three parts (a batch shares the middle one across problems)
 int rr_project(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh);
@@ -106,6 +128,9 @@ int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t 
             int *sweeps);
 // Records the unconverged-eigensolve message and returns the warning.
 int jacobi_warning(chfsi_ctx *c);
+// Whether Rayleigh-Ritz obtains Htilde times the rotated columns by a fresh
+// application (true) or by rotating HX (false), for ncols columns.
+bool rr_reapply(const chfsi_ctx *c, int ncols);
 
 }  // namespace chfsi
 

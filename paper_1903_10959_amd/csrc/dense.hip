@@ -284,8 +284,18 @@ static void gram_mode(bool v16, dim3 grid, const double *A, int64_t lda, const d
 
 void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                  double *G, int mixed, hipStream_t s) {
+  gram_launch_capped(A, lda, B, ldb, nrows, n, part, 0, G, mixed, s);
+}
+
+int gram_launch_capped(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n,
+                       double *part, size_t part_elems, double *G, int mixed, hipStream_t s) {
   const int ntiles = gram_ntiles(n);
-  const int nsplit = gram_nsplit_tiles(nrows, ntiles, gram_slots());
+  int nsplit = gram_nsplit_tiles(nrows, ntiles, gram_slots());
+  if (part_elems > 0) {
+    const size_t fit = part_elems / ((size_t)ntiles * GT * GT);
+    if (fit < 1) return -1;
+    if ((size_t)nsplit > fit) nsplit = (int)fit;
+  }
   const int64_t rps = gram_rows_per_split(nrows, nsplit);
   const bool v16 = gram_v16(A, lda, B, ldb, n);
   const int nt = (n + GT - 1) / GT;
@@ -297,6 +307,7 @@ void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int
     gram_mode<2>(v16, diag, A, lda, B, ldb, nrows, n, nt, ntiles, 0, rps, 0, part, s);
   }
   gram_reduce(part, nsplit, ntiles, n, 0, 0, -1, G, s);
+  return 0;
 }
 
 void gram_split_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,

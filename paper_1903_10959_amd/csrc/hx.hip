@@ -550,17 +550,20 @@ __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP, V>::WAVES))) void hx_cells_bat
 
 // Complex Bloch operator on a periodic mesh (FP64): the same tile with the
 // doubled contraction.
+// The recursion coefficients are real, so a Chebyshev step on complex
+// blocks is the same element-wise epilogue on the interleaved values.
 template <int NP, int V>
 __global__ __launch_bounds__((64 * TileCfg<double, NP, V>::NW))
 __attribute__((amdgpu_waves_per_eu(TileCfg<double, NP, V>::WAVES))) void hx_cells_cplx_kernel(
-    const double *__restrict__ X, int64_t ldx, double *__restrict__ Y, int64_t ldy, const double *__restrict__ K,
-    const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, const int32_t *__restrict__ cells,
-    const double *__restrict__ minv, const double *__restrict__ V_, int ncols, int ntiles, double shift) {
+    const double *__restrict__ X, int64_t ldx, const double *__restrict__ Xp, int64_t ldp, double *__restrict__ Y,
+    int64_t ldy, const double *__restrict__ K, const int32_t *__restrict__ cmap, int n_loc, int q, int n_el,
+    const int32_t *__restrict__ cells, const double *__restrict__ minv, const double *__restrict__ V_, int ncols,
+    int ntiles, double s1, double s2, double shift) {
   typedef TileCfg<double, NP, V> CF;
   const int cell_slot = blockIdx.x / ntiles;
   const int tile = blockIdx.x - cell_slot * ntiles;
   cell_tile<double, NP, CF::NW, CF::WR, CF::CBW, CF::KC, CF::EPD, true>(
-      X, ldx, nullptr, 0, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols, 1.0, 0.0, shift);
+      X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols, s1, s2, shift);
 }
 
 // A group of k-points on one mesh: work item (k, cell, column tile); k's
@@ -603,8 +606,8 @@ static void launch_cells_cplx(const HxArgs<double> &a, int color_begin, int colo
   const int ncell = color_end - color_begin;
   if (ncell <= 0 || ntiles <= 0) return;
   hipLaunchKernelGGL((hx_cells_cplx_kernel<NP, V>), dim3((unsigned)(ncell * ntiles)),
-                     dim3(64 * TileCfg<double, NP, V>::NW), 0, s, a.X, a.ldx, a.Y, a.ldy, a.K, a.cmap, a.n_loc, a.q,
-                     a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.shift);
+                     dim3(64 * TileCfg<double, NP, V>::NW), 0, s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.cmap,
+                     a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
 }
 
 template <int NP, int V>

@@ -101,6 +101,11 @@ size_t gram_part_elems(int64_t nrows, int n);
 size_t gram_part_elems_slots(int64_t nrows, int n, int slots);
 void gram_launch(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n, double *part,
                  double *G, int mixed, hipStream_t s);
+// As gram_launch with a partial buffer of part_elems doubles (0: sized by
+// gram_part_elems): fewer row splits when it holds less; -1 when it cannot
+// hold one split of every tile.
+int gram_launch_capped(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrows, int n,
+                       double *part, size_t part_elems, double *G, int mixed, hipStream_t s);
 // As gram_launch, with the trailing block (rows and columns >= fr0, rounded
 // down to a multiple of 64) in FP64 and everything else with FP32 inputs and
 // products: the split projected Hamiltonian.
@@ -166,6 +171,27 @@ int jacobi_eigh_batch(const JacobiJob *jobs, int njobs, double tol, int max_swee
                       double *host_norms, hipStream_t s, int *sweeps_done, int *converged);
 int jacobi_eigh(double *A, int n, double *work, double *evals, double *Q, double tol, int max_sweeps,
                 double *host_scratch, hipStream_t s, int *sweeps_done);
+// ---- complex (Hermitian) subspace steps on interleaved blocks (complex.hip)
+// A complex n x N block X seen as the real n x 2N block R of its interleaved
+// (re, im) columns.  G = R^T B (real 2N x 2N, lower triangle used) of two such
+// blocks gives the Hermitian N x N matrix M = X^H Y through
+//   Re M_jk = G[2j][2k] + G[2j+1][2k+1],  Im M_jk = G[2j][2k+1] - G[2j+1][2k]
+// (j > k; the diagonal is real and the upper triangle follows by symmetry).
+// herm_embed_launch writes E (2N x 2N real symmetric) = emb(M), the real form
+// with 2 x 2 blocks [[Re, Im], [-Im, Re]], in which right-multiplication of R
+// by emb(W) is the complex product X W.
+void herm_embed_launch(const double *G, int n2, double *E, hipStream_t s);
+// From the eigenvectors V (n2 x n2 row-major, column i = pair i, ascending
+// values ev) of an embedded Hermitian matrix, where every eigenvalue appears
+// twice, picks N = n2/2 complex eigenvectors: candidates in ascending order
+// are orthogonalised (twice) against the kept w and J w (J the pair rotation,
+// (Jw)_2j = -w_2j+1, (Jw)_2j+1 = w_2j) and kept when a tenth of their norm
+// survives.  Q (n2 x n2) = [w_0, J w_0, w_1, J w_1, ...] is the embedding of
+// the complex eigenvector matrix; evals [N] and lam2 [n2] (each value twice)
+// receive the kept values; *status = number kept.  One work-group; n2 <= 4096.
+void herm_select_launch(const double *V, const double *ev, int n2, double *Q, double *evals, double *lam2,
+                        int *status, hipStream_t s);
+
 // Zero the strictly upper triangle, helpers.
 void fill_launch(double *X, int64_t n, double v, hipStream_t s);
 void zero_int_launch(int *p, int n, hipStream_t s);

@@ -249,6 +249,51 @@ std::string build_mesh(double L, int n_el, int p, MeshTables &m, bool periodic) 
   return "";
 }
 
+double bloch_1d_max(const MeshTables &m, double k) {
+  const int q = m.q, p = m.p, n = m.n_el * p;
+  std::vector<double> K1D((size_t)n * n, 0.0), C1D((size_t)n * n, 0.0), M1(n, 0.0);
+  for (int e = 0; e < m.n_el; ++e)
+    for (int a = 0; a < q; ++a) {
+      const int ia = (e * p + a) % n;
+      M1[ia] += (m.h / 2.0) * m.w[a];
+      for (int b = 0; b < q; ++b) {
+        const int ib = (e * p + b) % n;
+        K1D[(size_t)ia * n + ib] += (2.0 / m.h) * m.K1[(size_t)a * q + b];
+        C1D[(size_t)ia * n + ib] += m.w[a] * m.D[(size_t)a * q + b];   // int phi_a phi_b'
+      }
+    }
+  // A = Re + i Im, Re = m^-1/2 (K1D/2 + k^2 m/2) m^-1/2, Im = -k m^-1/2 C1D m^-1/2
+  std::vector<double> re((size_t)n * n), im((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double s = 1.0 / std::sqrt(M1[i] * M1[j]);
+      re[(size_t)i * n + j] = s * (0.5 * K1D[(size_t)i * n + j] + (i == j ? 0.5 * k * k * M1[i] : 0.0));
+      im[(size_t)i * n + j] = -k * s * C1D[(size_t)i * n + j];
+    }
+  if (n <= 200) {
+    // the real symmetric form [[Re, -Im], [Im, Re]] carries every eigenvalue of A twice
+    const int n2 = 2 * n;
+    std::vector<double> E((size_t)n2 * n2);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        E[(size_t)i * n2 + j] = re[(size_t)i * n + j];
+        E[(size_t)i * n2 + n + j] = -im[(size_t)i * n + j];
+        E[(size_t)(n + i) * n2 + j] = im[(size_t)i * n + j];
+        E[(size_t)(n + i) * n2 + n + j] = re[(size_t)i * n + j];
+      }
+    std::vector<double> ev;
+    sym_eigvals(E, n2, ev);
+    return ev[n2 - 1] * (1.0 + 64 * 2.220446049250313e-16);
+  }
+  double g = 0;
+  for (int i = 0; i < n; ++i) {
+    double r = 0;
+    for (int j = 0; j < n; ++j) r += std::hypot(re[(size_t)i * n + j], im[(size_t)i * n + j]);
+    g = std::max(g, r);
+  }
+  return g;
+}
+
 void dof_coords(const MeshTables &m, double *xyz) {
   std::vector<double> x1(m.n);
   const int I0 = m.periodic ? 0 : 1;   // periodic unknowns start at the node x = 0

@@ -36,6 +36,12 @@ struct MeshTables {
 // 8-colour parity rule still separates cells that share a node across the wrap).
 std::string build_mesh(double L, int n_el, int p, MeshTables &m, bool periodic = false);
 
+// Largest eigenvalue (or, above 200 nodes, a Gershgorin bound of it) of the
+// 1D Bloch operator m^-1/2 (1/2 K1D - i k C1D + 1/2 k^2 m) m^-1/2 on the
+// n_el p periodic nodes of a periodic mesh; the sum over the three directions
+// plus max V bounds lambda_max(Htilde_k) (Weyl, Kronecker sum).
+double bloch_1d_max(const MeshTables &m, double k);
+
 // x,y,z of every interior node in dof order.
 void dof_coords(const MeshTables &m, double *xyz);
 
