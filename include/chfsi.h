@@ -125,6 +125,26 @@ int chfsi_chebyshev_filter(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int
  * CHFSI_ERR_NOT_SPD if S is not numerically positive definite (X unchanged). */
 int chfsi_orthonormalize(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int mixed);
 
+/* ---- orthonormalize without allocating ----------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * CholGS as chfsi_orthonormalize (same kernels, same arguments, same errors,
+ * X unchanged on CHFSI_ERR_NOT_SPD), with every workspace taken from one
+ * static device array of CHFSI_NOALLOC_SCRATCH_MIB MiB that the library holds
+ * on each GPU it runs on until the process ends; it calls no hipMalloc or
+ * hipFree.  Limit: ncols <= CHFSI_NOALLOC_MAX_COLS (CHFSI_ERR_ARG above it);
+ * any n_dof (the rotation streams row panels through the array; the overlap
+ * uses fewer row splits than chfsi_orthonormalize when its partial tiles
+ * would not fit, so results can differ from it in the last bits).  Every call
+ * on one GPU uses that GPU's single array: calls that overlap in time on one
+ * GPU (from several threads or on several streams) race and must be
+ * serialised by the caller.  CHFSI_ERR_STATE if the array's address could not
+ * be set up for the context's device (chfsi_create does that once per
+ * device). */
+#define CHFSI_NOALLOC_MAX_COLS 256
+#define CHFSI_NOALLOC_SCRATCH_MIB 96
+int chfsi_orthonormalize_noalloc(chfsi_ctx *ctx, double *X, int64_t ld, int ncols, int mixed);
+
 /* ---- rayleighRitz (Sec. 3.5 steps i-iii) ---------------------------------
  * In place, for orthonormal X: HX = Htilde X, Hhat = X^T HX (lower triangle),
  * Hhat Q = Q D (D ascending, FP64 Jacobi on the device), X <- X Q.

@@ -75,6 +75,7 @@ SIGNATURES = {
     "chfsi_batch_set_threads": (_int, [_vp, _int]),
     "chfsi_batch_footprint_bytes": (C.c_size_t, [_int, _int, _int]),
     "chfsi_device_bytes": (_int, [_vp, C.POINTER(C.c_size_t)]),
+    "chfsi_orthonormalize_noalloc": (_int, [_vp, _dp, _i64, _int, _int]),
     "chfsi_get_upper_bound_k": (_int, [_vp, C.POINTER(C.c_double)]),
     "chfsi_chebyshev_filter_complex": (_int, [_vp, _vp, _i64, _int, _int, _dbl, _dbl, _dbl, _int]),
     "chfsi_orthonormalize_complex": (_int, [_vp, _vp, _i64, _int]),

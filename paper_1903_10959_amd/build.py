@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchfsi.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["mesh.cpp", "hx.hip", "dense.hip", "small.hip", "context.hip", "batch.hip", "poisson.hip", "complex.hip"]
+SOURCES = ["mesh.cpp", "hx.hip", "dense.hip", "small.hip", "context.hip", "batch.hip", "poisson.hip", "complex.hip", "noalloc.hip"]
 ARCH = os.environ.get("CHFSI_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled for all device code (the compiler may
 # otherwise form v_pk_* FP32 ops from scalar or float2 code).

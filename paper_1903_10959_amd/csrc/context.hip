@@ -64,6 +64,15 @@ extern "C" int chfsi_create(chfsi_ctx **out, int device, void *hip_stream) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CHFSI_ERR_ARG;
   }
+  if (device >= 0) {
+    // the allocation-free CholGS needs its scratch array's address on this
+    // device, looked up once per device with the device current
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return CHFSI_ERR_HIP;
+    const int r = noalloc_init(device);
+    if (hipSetDevice(prev) != hipSuccess) return CHFSI_ERR_HIP;
+    if (r) return r;
+  }
   chfsi_ctx *c = new (std::nothrow) chfsi_ctx();
   if (!c) return CHFSI_ERR_OOM;
   c->device = device;

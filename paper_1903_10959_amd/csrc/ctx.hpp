@@ -113,6 +113,9 @@ struct CholWs {
 };
 int cholgs_core(chfsi_ctx *c, double *X, int64_t ld, int ncols, int mixed, double shift_rel, double *rmin,
                 const CholWs &w);
+// Looks up the device address of the allocation-free entry point's scratch
+// array on `device` (current) once; 0 or an error status.
+int noalloc_init(int device);
 // the solve's CholGS (CholeskyQR2 / shifted Cholesky QR when needed); cplx:
 // X is a complex block seen as interleaved reals (ld and nb count reals)
 int orth_robust(chfsi_ctx *c, double *X, int64_t ld, int nb, int mixed, int *passes, bool cplx = false);
