@@ -165,9 +165,21 @@ def batch_throughput(args):
             tiles[pr.p] = AT.tune_tile_variant(c, scratch, (0.5 * b, b, -50.0), prec="fp32", refresh=True)
             del scratch
         ctxs[i].set_tile_variant(tiles[pr.p])
+    # cells per work-group per (degree, block size): blocks of few columns pad
+    # fewer MFMA columns with more cells per tile
+    cpts = {}
+    for i, pr in enumerate(probs):
+        key = (pr.p, pr.nblock)
+        if key not in cpts:
+            c = ctxs[i]
+            scratch = Xs[i].clone()
+            b = c.upper_bound
+            cpts[key] = AT.tune_cells_per_tile(c, scratch, (0.5 * b, b, -50.0), prec="fp32", refresh=True)
+            del scratch
+        ctxs[i].set_cells_per_tile(cpts[key])
     torch.cuda.synchronize()
-    print(f"[bench] batch: tile variants per degree {tiles} (tuned in {time.time() - t_tune:.1f} s)",
-          file=sys.stderr, flush=True)
+    print(f"[bench] batch: tile variants per degree {tiles}, cells per tile per (p, N_b) {cpts} "
+          f"(tuned in {time.time() - t_tune:.1f} s)", file=sys.stderr, flush=True)
     tot_dofs = sum(pr.n_dof for pr in probs)
     print(f"[bench] batch: {len(probs)} problems, {tot_dofs} DoFs in all, setup {time.time() - t0:.1f} s",
           file=sys.stderr, flush=True)
@@ -208,23 +220,34 @@ def served_stream(args):
 
     from paper_1903_10959_amd import serve as S
 
-    reqs = S.make_stream(args.requests, args.rate, seed=5)
-    t0 = time.time()
     lt = [float(v) for v in args.ladder_tol.split(",")] if args.ladder_tol else None
-    S.serve(reqs, hbm_budget=args.hbm_budget, solves=5, tol=args.tol, degree=20, ladder=("fp32", "fp64"),
-            ladder_tol=lt, log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-    torch.cuda.synchronize()
-    wall = time.time() - t0
-    st = S.latency_stats(reqs, wall)
-    dofvecs = sum(r.problem.n_dof * r.problem.nblock * (20 + 1) * sum(r.iters) for r in reqs)
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    curve = []
+    for rate in rates:
+        reqs = S.make_stream(args.requests, rate, seed=5)
+        t0 = time.time()
+        S.serve(reqs, hbm_budget=args.hbm_budget, solves=5, tol=args.tol, degree=20, ladder=("fp32", "fp64"),
+                ladder_tol=lt, log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        st = S.latency_stats(reqs, wall)
+        st["offered_rate_setting_per_s"] = rate
+        st["throughput_dofvecs_per_s"] = sum(r.problem.n_dof * r.problem.nblock * (20 + 1) * sum(r.iters)
+                                             for r in reqs) / wall
+        st["wall_s"] = wall
+        curve.append(st)
+        print(f"[bench] serve at {rate}/s: achieved {st['achieved_rate_per_s']:.3f}/s, e2e p50 "
+              f"{st['e2e_p50_s']:.2f} s p99 {st['e2e_p99_s']:.2f} s, queue p99 {st['queue_p99_s']:.2f} s",
+              file=sys.stderr, flush=True)
+    st = curve[-1]
     out = {"metric": "served ChFSI stream: p99 end-to-end request latency (5 warm-started solves per request)",
            "value": st["e2e_p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
            "dtype": "fp32-filter->f64", "data": "synthetic",
-           "config": {"workload": f"served: {args.requests} requests, Poisson rate {args.rate}/s, sizes of the "
-                                  f"batched workload, 5 solves each to residual {args.tol} Ha, continuous batching, "
-                                  f"HBM budget {args.hbm_budget / 1e9:.0f} GB"},
-           "latency": st, "throughput_dofvecs_per_s": dofvecs / wall, "wall_s": wall,
-           "ladder_tol": lt}
+           "config": {"workload": f"served: {args.requests} requests per offered rate, Poisson arrivals, sizes of "
+                                  f"the batched workload, 5 solves each to residual {args.tol} Ha, continuous "
+                                  f"batching, HBM budget {args.hbm_budget / 1e9:.0f} GB",
+                      "rates_per_s": rates},
+           "latency": st, "curve": curve, "ladder_tol": lt}
     print(json.dumps(out), flush=True)
 
 
@@ -276,6 +299,50 @@ def time_to_solution(args, prob, bw):
         "max_abs_eval_diff_mixed_vs_fp64": float(np.max(np.abs(e64 - emx))),
     }
     print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def kpoint_solve(args, prob):
+    """ChFSI at a k-point (complex Hermitian Bloch operator, FP64) on the
+    periodic cell with the workload's element size and degree: whole passes
+    (complex filter of the workload's degree, Hermitian CholGS, Hermitian
+    Rayleigh-Ritz) on a block of N = 256 complex states (N_b = 288), timed
+    after warm-up passes.  value = complex DoF-vecs per second over the
+    passes (n_dof x N_b x (degree + 1) per pass)."""
+    import numpy as np
+    import torch
+
+    import paper_1903_10959_amd as P
+    import workload
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0).set_mesh(prob.L, prob.n_el, prob.p, periodic=True)
+    ctx.set_potential(workload.eval_wells(workload.problem_wells(prob), ctx.dof_coords()))
+    k = (0.05, 0.11, -0.08)
+    ctx.set_kpoint(k)
+    N = 256
+    nb = workload.block_size(N)
+    g = torch.Generator(device=dev).manual_seed(prob.x0_seed)
+    X = torch.randn((ctx.n_dof, nb), dtype=torch.complex128, device=dev, generator=g)
+    ctx.solve_complex(X, N, prob.degree, 1e-30, max_iter=max(1, args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.time()
+    out = ctx.solve_complex(X, N, prob.degree, 1e-30, max_iter=args.steps)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    passes = out["iters"]
+    dv = ctx.n_dof * nb * (prob.degree + 1) * passes / dt
+    res = {"metric": "ChFSI at a k-point: complex DoF-vecs/s over whole passes (filter + CholGS + RR), FP64",
+           "value": dv, "unit": "complex DoF-vecs/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+           "data": "synthetic", "dtype": "f64 (complex128)",
+           "config": {"workload": f"periodic [0,{prob.L})^3, {prob.n_el}^3 cells, p={prob.p}, {ctx.n_dof} DoFs, "
+                                  f"k={list(k)}, N={N}, N_b={nb}, Chebyshev degree {prob.degree}",
+                      "passes": passes},
+           "s_per_pass": dt / passes, "t_filter_s": out["t_filter"], "t_cholgs_s": out["t_cholgs"],
+           "t_rr_s": out["t_rr"], "max_wanted_resid": out["max_resid"],
+           "upper_bound_k": ctx.upper_bound_k}
+    print(json.dumps(res), flush=True)
+    del X
     ctx.close()
 
 
@@ -546,14 +613,18 @@ def main():
     ap.add_argument("--block-width", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=16)
-    ap.add_argument("--mode", default="step", choices=["step", "tts", "rr", "density", "kpoint", "poisson"],
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "tts", "rr", "density", "kpoint", "ksolve", "poisson"],
                     help="step: throughput of whole ChFSI iterations (default); tts: time to solution; "
                          "rr: Rayleigh-Ritz full vs spectrum splitting; density: electron density (Alg. 5); "
-                         "kpoint: complex Bloch operator on the periodic cell; poisson: electrostatics (Jacobi-PCG)")
+                         "kpoint: complex Bloch operator on the periodic cell; ksolve: ChFSI at a k-point; "
+                         "poisson: electrostatics (Jacobi-PCG)")
     ap.add_argument("--tol", type=float, default=1e-6, help="tts: residual tolerance (Ha)")
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate per second")
+    ap.add_argument("--rates", default="", help="serve: comma-separated offered rates (one run each; the last is "
+                                                "the headline); default --rate")
     ap.add_argument("--hbm-budget", type=float, default=160e9, help="serve: device bytes for admitted requests")
     ap.add_argument("--ladder", default="bf16,fp32,fp64", help="tts: filter precisions of the mixed path's ladder")
     ap.add_argument("--ladder-tol", default="",
@@ -597,6 +668,8 @@ def main():
         return density_bench(args, prob)
     if args.mode == "kpoint":
         return kpoint_bench(args, prob)
+    if args.mode == "ksolve":
+        return kpoint_solve(args, prob)
     if args.mode == "poisson":
         return poisson_bench(args, prob)
     if args.mode == "rr":

@@ -426,6 +426,15 @@ int chfsi_last_filter_timing(chfsi_ctx *ctx, double *ms_cells, int *n_launches, 
  * (set it before adding the context to a batch session).  Errors:
  * CHFSI_ERR_ARG for a null ctx or a variant outside -1..1. */
 int chfsi_set_tile_variant(chfsi_ctx *ctx, int variant);
+/* Cells per work-group of the FP64/FP32 cell-product kernel (p <= 6; one
+ * cell above): the tile's 64 columns are split over 1, 2 or 4 cells of one
+ * colour, so a block of few columns pads fewer of them (24 columns fill a
+ * 64-column tile to 37 %, and two 16-column groups of four cells to 75 %);
+ * 0 (default) picks the count that pads the fewest columns, ties to fewer
+ * cells.  Every setting computes the same products.  Applies to later
+ * filter/apply calls and to batch sweeps built after it.  Errors:
+ * CHFSI_ERR_ARG for a value other than 0, 1, 2, 4. */
+int chfsi_set_cells_per_tile(chfsi_ctx *ctx, int cpt);
 /* How rayleighRitz (both forms) obtains Htilde times the rotated columns for
  * the residuals (Sec. 3.5 step iii leaves this open): 0 = cost model
  * (default): rotate HX with X when that GEMM is cheaper than the cell

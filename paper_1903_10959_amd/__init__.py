@@ -559,6 +559,12 @@ class Context:
         self._check(self._lib.chfsi_device_bytes(self._h, C.byref(b)), "device_bytes")
         return int(b.value)
 
+    def set_cells_per_tile(self, cpt: int = 0):
+        """Cells per work-group of the cell kernel: 0 chosen from the column count, or 1, 2, 4."""
+        self._check(self._lib.chfsi_set_cells_per_tile(self._h, int(cpt)), "set_cells_per_tile")
+        self.cells_per_tile = int(cpt)
+        return self
+
     def set_rr_residual(self, mode: int = 0):
         """Ritz residuals: 0 cost model, 1 rotate HX with X, 2 apply Htilde again."""
         self._check(self._lib.chfsi_set_rr_residual(self._h, int(mode)), "set_rr_residual")

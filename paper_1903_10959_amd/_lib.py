@@ -68,6 +68,7 @@ SIGNATURES = {
     "chfsi_density": (_int, [_vp, _vp, _i64, _int, _vp, _i64, _int, _vp, _dbl, _dbl, _vp]),
     "chfsi_set_timing": (_int, [_vp, _int]),
     "chfsi_set_tile_variant": (_int, [_vp, _int]),
+    "chfsi_set_cells_per_tile": (_int, [_vp, _int]),
     "chfsi_set_rr_residual": (_int, [_vp, _int]),
     "chfsi_reset_timing": (_int, [_vp]),
     "chfsi_last_filter_timing": (_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)]),

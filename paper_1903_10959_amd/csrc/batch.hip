@@ -187,7 +187,8 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
   if (ids.empty()) return 0;
   const bool f64 = sizeof(T) == 8;
   std::vector<BatchProblem<T>> hp;
-  std::map<std::tuple<int, int, int>, std::vector<int4>> lists;  // (np, tile variant, colour) -> items
+  // (np, (tile variant + 1) * 8 + cells per tile, colour) -> work items
+  std::map<std::tuple<int, int, int>, std::vector<int4>> lists;
   for (size_t m = 0; m < ids.size(); ++m) {
     Prob &p = B->probs[ids[m]];
     chfsi_ctx *c = p.c;
@@ -203,23 +204,28 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
     P.minv = f64 ? (const T *)c->minv64.p : (const T *)c->minv32.p;
     P.V = f64 ? (const T *)c->V64.p : (const T *)c->V32.p;
     P.coef = nullptr;
+    P.cells = c->cells.as<int32_t>();
     P.n_loc = c->mesh.n_loc;
     P.q = c->mesh.q;
     P.n_el = c->mesh.n_el;
     P.ncols = nb;
     hp.push_back(P);
-    const int tw = hx_tile_width<T>(c->mesh.np, c->tile_variant);
-    if (tw <= 0) return bfail(B, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
-    const int ntiles = (nb + tw - 1) / tw;
-    for (int col = 0; col < 8; ++col)
-      for (int s = c->mesh.color_offset[col]; s < c->mesh.color_offset[col + 1]; ++s)
+    const int cpt = cells_per_tile(c, nb, hx_tile_width<T>(c->mesh.np, c->tile_variant, 1));
+    const int cw = hx_tile_width<T>(c->mesh.np, c->tile_variant, cpt);
+    if (cw <= 0) return bfail(B, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
+    const int ntiles = (nb + cw - 1) / cw;
+    for (int col = 0; col < 8; ++col) {
+      const int e0 = c->mesh.color_offset[col], e1 = c->mesh.color_offset[col + 1];
+      for (int s = e0; s < e1; s += cpt)
         for (int t = 0; t < ntiles; ++t)
-          lists[{c->mesh.np, c->tile_variant, col}].push_back(make_int4((int)m, c->mesh.cell_order[s], t, 0));
+          lists[{c->mesh.np, (c->tile_variant + 1) * 8 + cpt, col}].push_back(
+              make_int4((int)m, s, t, std::min(cpt, e1 - s)));
+    }
   }
   BCHK(B, S.coef.ensure((size_t)3 * B->degree * ids.size() * sizeof(T)));
   for (size_t m = 0; m < hp.size(); ++m) hp[m].coef = S.coef.template as<T>() + (size_t)3 * B->degree * m;
   std::vector<int4> all;
-  std::vector<std::tuple<int, int, int>> groups;  // (np, tile variant, offset)
+  std::vector<std::tuple<int, int, int>> groups;  // (np, (tile variant + 1) * 8 + cells per tile, offset)
   std::vector<int> counts;
   // colour-major launch order: every problem sees its colours in order 0..7
   for (int col = 0; col < 8; ++col)
@@ -247,8 +253,8 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
   int lerr = 0;
   for (int k = 0; k < B->degree; ++k)
     for (size_t g = 0; g < groups.size(); ++g)
-      lerr |= hx_cells_batch_launch<T>(std::get<0>(groups[g]), std::get<1>(groups[g]),
-                                       S.probs.template as<BatchProblem<T>>(),
+      lerr |= hx_cells_batch_launch<T>(std::get<0>(groups[g]), std::get<1>(groups[g]) / 8 - 1,
+                                       std::get<1>(groups[g]) % 8, S.probs.template as<BatchProblem<T>>(),
                                        S.work.template as<int4>() + std::get<2>(groups[g]), counts[g], k, cur[k],
                                        prev[k], out[k], B->stream);
   for (size_t m = 0; m < ids.size(); ++m) {

@@ -449,6 +449,30 @@ extern "C" int chfsi_set_timing(chfsi_ctx *c, int enable) {
   return 0;
 }
 
+int chfsi::cells_per_tile(const chfsi_ctx *c, int ncols, int tw) {
+  // at least 16 columns per cell; one cell per tile above p = 6
+  const int max_cpt = c->mesh.p > 6 ? 1 : (tw >= 64 ? 4 : (tw >= 32 ? 2 : 1));
+  if (c->cpt_setting > 0) return std::min(c->cpt_setting, max_cpt);
+  int best = 1;
+  int64_t best_pad = -1;
+  for (int cpt = 1; cpt <= max_cpt; cpt *= 2) {
+    const int cw = tw / cpt;
+    const int64_t pad = (int64_t)(ncols + cw - 1) / cw * cw - ncols;
+    if (best_pad < 0 || pad < best_pad) {
+      best = cpt;
+      best_pad = pad;
+    }
+  }
+  return best;
+}
+
+extern "C" int chfsi_set_cells_per_tile(chfsi_ctx *c, int cpt) {
+  if (!c) return CHFSI_ERR_ARG;
+  if (cpt != 0 && cpt != 1 && cpt != 2 && cpt != 4) return fail(c, CHFSI_ERR_ARG, "cells per tile must be 0, 1, 2 or 4");
+  c->cpt_setting = cpt;
+  return 0;
+}
+
 extern "C" int chfsi_set_tile_variant(chfsi_ctx *c, int variant) {
   if (!c) return CHFSI_ERR_ARG;
   if (variant < -1 || variant > 1) return fail(c, CHFSI_ERR_ARG, "tile variant must be -1, 0 or 1");
@@ -534,6 +558,7 @@ static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64
   a.s2 = (T)s2;
   a.shift = (T)shift;
   a.variant = c->tile_variant;
+  a.cpt = cells_per_tile(c, ncols, hx_tile_width<T>(M.np, c->tile_variant, 1));
   for (int col = 0; col < 8; ++col) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {

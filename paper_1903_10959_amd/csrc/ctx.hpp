@@ -51,6 +51,7 @@ struct chfsi_ctx {
   chfsi::DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
   int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
   int tile_variant = -1;  // cell-kernel tile configuration (-1: built-in choice)
+  int cpt_setting = 0;    // cells per work-group of the cell kernel (0: chosen from the column count)
   int rr_residual = 0;    // Ritz residuals: 0 cost model, 1 rotate HX, 2 apply Htilde again
   int jac_sweeps = 40;    // cap on Jacobi sweeps of the projected eigensolve
   // workspaces
@@ -129,6 +130,11 @@ int rr_finish(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_
 // iterate) when the projected eigensolve ran out of sweeps.
 int rr_impl(chfsi_ctx *c, double *X, int64_t ld, int ncols, double *HX, int64_t ldh, double *evals, double *resid,
             int *sweeps);
+// Cells per work-group of the real cell kernel (tile width tw columns) for
+// blocks of ncols columns: the context's setting, or (setting 0) the count
+// among 1, 2, 4 that pads the fewest columns (ties: fewer cells); at least 16
+// columns per cell either way.
+int cells_per_tile(const chfsi_ctx *c, int ncols, int tw);
 // Records the unconverged-eigensolve message and returns the warning.
 int jacobi_warning(chfsi_ctx *c);
 // Whether Rayleigh-Ritz obtains Htilde times the rotated columns by a fresh

@@ -135,67 +135,84 @@ struct LdsTile {
 // (2 NP rows): the contraction runs twice as long, and its second half
 // gathers each column's partner (col ^ 1), negated for imaginary outputs, so
 // Y_re = A Xr + B Xi and Y_im = A Xi - B Xr.
-template <typename T, int NP, int NW, int WR, int CBW, int KC, int EPD, bool CPLX = false>
+// CPT cells per work-group: the TW tile columns are split into CPT groups of
+// CW = TW / CPT columns, group s holding columns [col0, col0 + CW) of cell
+// ecells[s] (cells of one colour share no DoF, so their rows never collide);
+// necell <= CPT of the slots are filled.  CPT = 1 is one cell x TW columns.
+template <typename T, int NP, int NW, int WR, int CBW, int KC, int EPD, bool CPLX = false, int CPT = 1, int XD = 2>
 __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp,
                                               int64_t ldp, T *__restrict__ Y, int64_t ldy,
                                               const T *__restrict__ K, const int32_t *__restrict__ cmap,
-                                              int n_loc, int q, int n_el, int e, int tile,
-                                              const T *__restrict__ minv, const T *__restrict__ V, int ncols, T s1,
-                                              T s2, T shift) {
+                                              int n_loc, int q, int n_el, const int32_t *__restrict__ ecells,
+                                              int necell, int tile, const T *__restrict__ minv,
+                                              const T *__restrict__ V, int ncols, T s1, T s2, T shift) {
   typedef LdsTile<T, NP, NW, WR, CBW, KC> C;
   typedef typename acc4<T>::type acc_t;
   typedef T vec_t __attribute__((ext_vector_type(C::VEC)));
-  __shared__ int32_t dof_s[NP];
-  __shared__ T mi_s[NP];
-  __shared__ T vd_s[NP];
-  __shared__ int8_t ft_s[NP];
+  constexpr int CW = C::TW / CPT;                    // columns per cell
+  static_assert(C::TW % CPT == 0 && CW % 16 == 0, "a 16-column fragment belongs to one cell");
+  __shared__ int32_t dof_s[CPT][NP];
+  __shared__ T mi_s[CPT][NP];
+  __shared__ T vd_s[CPT][NP];
+  __shared__ int8_t ft_s[CPT][NP];
   __shared__ __align__(16) T Ks[2][KC * C::SK];
   __shared__ __align__(16) T Xs[2][KC * C::SX];
   const int t = threadIdx.x;
-  for (int r = t; r < NP; r += C::NT) {
-    int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
-    dof_s[r] = d < 0 ? 0 : d;
-    mi_s[r] = d < 0 ? T(0) : minv[d];
+  for (int sr = t; sr < CPT * NP; sr += C::NT) {
+    const int sl = sr / NP, r = sr - sl * NP;
+    const int e = sl < necell ? ecells[sl] : -1;
+    int d = (e >= 0 && r < n_loc) ? cmap[(int64_t)e * n_loc + r] : -1;
+    dof_s[sl][r] = d < 0 ? 0 : d;
+    mi_s[sl][r] = d < 0 ? T(0) : minv[d];
     const int ft = d < 0 ? 0 : first_touch(r, q, e, n_el);
-    ft_s[r] = (int8_t)ft;
-    vd_s[r] = ft ? s1 * (V[d] - shift) : T(0);
+    ft_s[sl][r] = (int8_t)ft;
+    vd_s[sl][r] = ft ? s1 * (V[d] - shift) : T(0);
   }
   __syncthreads();
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave / C::WC, wc = wave - wr * C::WC;
   const int j = lane & 15, kq = lane >> 4;
-  const int col0 = tile * C::TW;
+  const int col0 = tile * CW;
 
-  // this thread's X staging slots: chunk row xr[i], tile column xc
+  // this thread's X staging slots: chunk row xr[i], tile column xc (cell
+  // slot xs, column col0 + xc % CW of that cell)
   const int xc = t % C::TW;
+  const int xsl = xc / CW;
   const int xrow0 = t / C::TW;                       // rows xrow0 + i * (NT / TW)
-  const bool xok = col0 + xc < ncols;
-  const int xcol = xok ? col0 + xc : ncols - 1;      // clamped, in bounds
+  const bool xok = col0 + (xc - xsl * CW) < ncols && xsl < necell;
+  const int xcol = xok ? col0 + (xc - xsl * CW) : 0; // clamped, in bounds
   const T xscale = xok ? T(1) : T(0);
+  const int32_t *xdof = dof_s[xsl];
+  const T *xmi = mi_s[xsl];
 
-  // Staging: chunk c + 1 (K_ref rows and gathered X rows) is loaded into
-  // registers while chunk c is multiplied, then written to the other LDS
-  // buffer.  The X values are scaled when stored, so no wait sits at the load.
+  // Staging: K_ref rows of chunk c + 1 (from L2) are loaded into registers
+  // while chunk c is multiplied; the gathered X rows (from HBM) XD chunks
+  // ahead, in XD register sets used in turn (the loop is unrolled by XD so
+  // every set is addressed statically).  Both are written to the other half
+  // of the double-buffered LDS area after the chunk's MFMAs.  The X values
+  // are scaled when stored, so no wait sits at the load.
   vec_t kreg[C::KPT];
-  T xreg[C::XPT];
+  T xr0[C::XPT], xr1[C::XPT];
   constexpr int NCHT = CPLX ? 2 * C::NCH : C::NCH;   // contraction chunks
   // chunk c covers local nodes c KC - (second half ? NP : 0) + [0, KC)
   auto node0 = [&](int c) { return c * KC - ((CPLX && c >= C::NCH) ? NP : 0); };
-  auto load_chunk = [&](int c) {
+  auto load_k = [&](int c) {
     const vec_t *Kc = reinterpret_cast<const vec_t *>(K + (int64_t)c * KC * NP);
 #pragma unroll
     for (int i = 0; i < C::KPT; ++i) {
       const int v = t + C::NT * i;
       if (v < C::KV) kreg[i] = Kc[v];
     }
+  };
+  auto load_x = [&](int c, T(&xr)[C::XPT]) {
     const int gcol = (CPLX && c >= C::NCH) ? (xcol ^ 1) : xcol;
 #pragma unroll
     for (int i = 0; i < C::XPT; ++i) {
       const int row = node0(c) + xrow0 + i * (C::NT / C::TW);
-      xreg[i] = X[(int64_t)dof_s[row] * ldx + gcol];
+      xr[i] = X[(int64_t)xdof[row] * ldx + gcol];
     }
   };
-  auto store_chunk = [&](int buf, int c) {
+  auto store_k = [&](int buf) {
     constexpr int RV = NP / C::VEC;                 // 16-byte vectors per K row
 #pragma unroll
     for (int i = 0; i < C::KPT; ++i) {
@@ -209,11 +226,13 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
         }
       }
     }
+  };
+  auto store_x = [&](int buf, int c, const T(&xr)[C::XPT]) {
     const T sgn = (CPLX && c >= C::NCH && (xcol & 1)) ? T(-1) : T(1);
 #pragma unroll
     for (int i = 0; i < C::XPT; ++i) {
       const int rr = xrow0 + i * (C::NT / C::TW);
-      Xs[buf][rr * C::SX + xc] = xreg[i] * (mi_s[node0(c) + rr] * (xscale * sgn));
+      Xs[buf][rr * C::SX + xc] = xr[i] * (xmi[node0(c) + rr] * (xscale * sgn));
     }
   };
 
@@ -223,15 +242,19 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 #pragma unroll
     for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = acc_t{0, 0, 0, 0};
 
-  load_chunk(0);
-  store_chunk(0, 0);
+  load_k(0);
+  load_x(0, xr0);
+  store_k(0);
+  store_x(0, 0, xr0);
+  if (XD == 2 && NCHT > 1) load_x(1, xr1);
   __syncthreads();
   const int arow = wr * C::RBW * 16 + j;            // A fragment: K[k][arow + 16 r]
   const int bcol = wc * CBW * 16 + j;               // B fragment: Xs[k][bcol + 16 cb]
-#pragma unroll 1
-  for (int c = 0; c < NCHT; ++c) {
+  // chunk c: the X set xl receives chunk c + XD, the set xs holds chunk c + 1
+  auto chunk = [&](int c, T(&xl)[C::XPT], T(&xs)[C::XPT]) {
     const int buf = c & 1;
-    if (c + 1 < NCHT) load_chunk(c + 1);
+    if (c + 1 < NCHT) load_k(c + 1);
+    if (c + XD < NCHT) load_x(c + XD, xl);
     const T *Kb = Ks[buf];
     const T *Xb = Xs[buf];
     // Software pipeline over the chunk's (step, row-block pair) stages: the
@@ -280,18 +303,39 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
         }
       }
     }
-    if (c + 1 < NCHT) store_chunk(buf ^ 1, c + 1);
+    if (c + 1 < NCHT) {
+      store_k(buf ^ 1);
+      store_x(buf ^ 1, c + 1, xs);
+    }
     __syncthreads();
+  };
+  if constexpr (XD == 2) {
+    // even c: xr0 takes chunk c + 2, xr1 holds chunk c + 1; odd c: swapped
+#pragma unroll 1
+    for (int c = 0; c < NCHT; c += 2) {
+      chunk(c, xr0, xr1);
+      if (c + 1 < NCHT) chunk(c + 1, xr1, xr0);
+    }
+  } else {
+#pragma unroll 1
+    for (int c = 0; c < NCHT; ++c) chunk(c, xr0, xr0);
   }
 
-  // epilogue, software-pipelined EPD - 1 fragments ahead
-  const EpiCtx<T> ec{X, ldx, Xp, ldp, Y, ldy, dof_s, mi_s, vd_s, ft_s, n_loc, s1, s2};
+  // epilogue, software-pipelined EPD - 1 fragments ahead; fragment i's 16
+  // columns belong to cell slot frag_slot(i)
   constexpr int NF = C::RBW * CBW;
-  auto frag_col = [&](int i) { return col0 + bcol + 16 * (i % CBW); };
+  auto frag_tc = [&](int i) { return wc * CBW * 16 + 16 * (i % CBW); };   // first tile column
+  auto frag_slot = [&](int i) { return frag_tc(i) / CW; };
+  auto frag_col = [&](int i) { return col0 + (frag_tc(i) - frag_slot(i) * CW) + j; };
   auto frag_row = [&](int i) { return (wr * C::RBW + i / CBW) * 16; };
+  auto frag_ctx = [&](int i) {
+    const int sl = frag_slot(i);
+    return EpiCtx<T>{X, ldx, Xp, ldp, Y, ldy, dof_s[sl], mi_s[sl], vd_s[sl], ft_s[sl], n_loc, s1, s2};
+  };
+  auto frag_ok = [&](int i) { return frag_col(i) < ncols && frag_slot(i) < necell; };
   auto frag_load = [&](int i, EpiFrag<T> &f) {
     const int ci = frag_col(i);
-    epi_load(ec, frag_row(i), kq, ci < ncols ? ci : ncols - 1, f);
+    epi_load(frag_ctx(i), frag_row(i), kq, frag_ok(i) ? ci : 0, f);
   };
   EpiFrag<T> f[EPD];
 #pragma unroll
@@ -300,8 +344,7 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
     if (i + EPD - 1 < NF) frag_load(i + EPD - 1, f[(i + EPD - 1) % EPD]);
-    const int ci = frag_col(i);
-    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i % EPD], acc[i / CBW][i % CBW]);
+    epi_store(frag_ctx(i), frag_row(i), kq, frag_col(i), frag_ok(i), f[i % EPD], acc[i / CBW][i % CBW]);
   }
 }
 
@@ -496,8 +539,10 @@ int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hi
 //    accumulators, so four waves per SIMD instead of two.  Only where the
 //    accumulators fit 128 registers (FP64 up to p = 5, FP32 up to p = 7);
 //    elsewhere variant 1 is variant 0.
-// The built-in choice (variant -1) is variant 1 for FP64 p = 5 (measured 1.3x
-// faster there) and variant 0 otherwise; the autotuner times both.
+// The built-in choice (variant -1) is variant 1 for FP64 p = 5 and FP32
+// p = 6 (measured faster there: 1.08 against 1.30 ms and 0.59 against 0.66
+// ms per colour launch of 128 columns) and variant 0 otherwise; the
+// autotuner times both.
 template <typename T, int NP, int V>
 struct TileCfg {
   static constexpr bool w8 = V == 1 && NP >= 32 && (sizeof(T) == 8 ? NP <= 224 : NP <= 512);
@@ -513,39 +558,45 @@ struct TileCfg {
 
 template <typename T>
 static int default_variant(int np) {
-  return (sizeof(T) == 8 && np == 224) ? 1 : 0;
+  // measured at 32^3 cells p = 5 and 24^3 cells p = 6, 128-column blocks
+  if (sizeof(T) == 8) return np == 224 ? 1 : 0;
+  return np == 352 ? 1 : 0;
 }
 
-#define CHFSI_CELL_TILE(T, NP, V, ...)                                                                       \
+#define CHFSI_CELL_TILE(T, NP, V, CPT, ...)                                                                  \
   cell_tile<T, NP, TileCfg<T, NP, V>::NW, TileCfg<T, NP, V>::WR, TileCfg<T, NP, V>::CBW, TileCfg<T, NP, V>::KC, \
-            TileCfg<T, NP, V>::EPD>(__VA_ARGS__)
+            TileCfg<T, NP, V>::EPD, false, CPT>(__VA_ARGS__)
 
-template <typename T, int NP, int V>
+// Work-group = (group of CPT cells of the colour, column tile).
+template <typename T, int NP, int V, int CPT>
 __global__ __launch_bounds__((64 * TileCfg<T, NP, V>::NW))
 __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP, V>::WAVES))) void hx_cells_kernel(
     const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp, int64_t ldp, T *__restrict__ Y, int64_t ldy,
     const T *__restrict__ K, const int32_t *__restrict__ cmap, int n_loc, int q, int n_el,
-    const int32_t *__restrict__ cells, const T *__restrict__ minv, const T *__restrict__ V_, int ncols, int ntiles,
-    T s1, T s2, T shift) {
-  const int cell_slot = blockIdx.x / ntiles;
-  const int tile = blockIdx.x - cell_slot * ntiles;
-  CHFSI_CELL_TILE(T, NP, V, X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols,
-                  s1, s2, shift);
+    const int32_t *__restrict__ cells, int ncell, const T *__restrict__ minv, const T *__restrict__ V_, int ncols,
+    int ntiles, T s1, T s2, T shift) {
+  const int grp = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - grp * ntiles;
+  const int first = grp * CPT;
+  const int cnt = ncell - first < CPT ? ncell - first : CPT;
+  CHFSI_CELL_TILE(T, NP, V, CPT, X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells + first, cnt, tile, minv,
+                  V_, ncols, s1, s2, shift);
 }
 
-// Batched: work item = (problem, cell, column tile); the step's buffer roles
-// (input, previous, output) are the same for every problem, its coefficients
-// come from the problem's table (s1, s2, shift per step).
-template <typename T, int NP, int V>
+// Batched: work item = (problem, first cell in the problem's colour-sorted
+// cell list, column tile, cell count); the step's buffer roles (input,
+// previous, output) are the same for every problem, its coefficients come
+// from the problem's table (s1, s2, shift per step).
+template <typename T, int NP, int V, int CPT>
 __global__ __launch_bounds__((64 * TileCfg<T, NP, V>::NW))
 __attribute__((amdgpu_waves_per_eu(TileCfg<T, NP, V>::WAVES))) void hx_cells_batch_kernel(
     const BatchProblem<T> *__restrict__ probs, const int4 *__restrict__ work, int step, int cur, int prev, int out) {
   const int4 w = work[blockIdx.x];
   const BatchProblem<T> &P = probs[w.x];
   const T *coef = P.coef + 3 * step;
-  CHFSI_CELL_TILE(T, NP, V, P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
-                  P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el, w.y, w.z, P.minv, P.V, P.ncols, coef[0],
-                  coef[1], coef[2]);
+  CHFSI_CELL_TILE(T, NP, V, CPT, P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr,
+                  prev >= 0 ? P.ld[prev] : 0, P.buf[out], P.ld[out], P.K, P.cmap, P.n_loc, P.q, P.n_el,
+                  P.cells + w.y, w.w, w.z, P.minv, P.V, P.ncols, coef[0], coef[1], coef[2]);
 }
 
 // Complex Bloch operator on a periodic mesh (FP64): the same tile with the
@@ -563,7 +614,7 @@ __attribute__((amdgpu_waves_per_eu(TileCfg<double, NP, V>::WAVES))) void hx_cell
   const int cell_slot = blockIdx.x / ntiles;
   const int tile = blockIdx.x - cell_slot * ntiles;
   cell_tile<double, NP, CF::NW, CF::WR, CF::CBW, CF::KC, CF::EPD, true>(
-      X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V_, ncols, s1, s2, shift);
+      X, ldx, Xp, ldp, Y, ldy, K, cmap, n_loc, q, n_el, cells + cell_slot, 1, tile, minv, V_, ncols, s1, s2, shift);
 }
 
 // A group of k-points on one mesh: work item (k, cell, column tile); k's
@@ -583,19 +634,21 @@ __attribute__((amdgpu_waves_per_eu(TileCfg<double, NP, V>::WAVES))) void hx_cell
   const int tile = rest - cell_slot * ntiles;
   cell_tile<double, NP, CF::NW, CF::WR, CF::CBW, CF::KC, CF::EPD, true>(
       X + kk * xstride, ldx, nullptr, 0, Y + kk * ystride, ldy, K + kk * kstride, cmap, n_loc, q, n_el,
-      cells[cell_slot], tile, minv, V_, ncols, 1.0, 0.0, shifts[kk]);
+      cells + cell_slot, 1, tile, minv, V_, ncols, 1.0, 0.0, shifts[kk]);
 }
 #undef CHFSI_CELL_TILE
 
-template <typename T, int NP, int V>
+template <typename T, int NP, int V, int CPT>
 static void launch_cells(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
-  constexpr int TW = TileCfg<T, NP, V>::L::TW;
-  const int ntiles = (a.ncols + TW - 1) / TW;
+  constexpr int CW = TileCfg<T, NP, V>::L::TW / CPT;
+  const int ntiles = (a.ncols + CW - 1) / CW;
   const int ncell = color_end - color_begin;
   if (ncell <= 0 || ntiles <= 0) return;
-  hipLaunchKernelGGL((hx_cells_kernel<T, NP, V>), dim3((unsigned)(ncell * ntiles)),
+  const int ngrp = (ncell + CPT - 1) / CPT;
+  hipLaunchKernelGGL((hx_cells_kernel<T, NP, V, CPT>), dim3((unsigned)(ngrp * ntiles)),
                      dim3(64 * TileCfg<T, NP, V>::NW), 0, s, a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.cmap,
-                     a.n_loc, a.q, a.n_el, a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
+                     a.n_loc, a.q, a.n_el, a.cells + color_begin, ncell, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2,
+                     a.shift);
 }
 
 template <int NP, int V>
@@ -623,25 +676,46 @@ static void launch_cells_cplx_kpts(const HxArgs<double> &a, const CplxKpts &g, i
                      ntiles, ncell);
 }
 
-template <typename T, int NP, int V>
+template <typename T, int NP, int V, int CPT>
 static void launch_batch(const BatchProblem<T> *probs, const int4 *work, int nwork, int step, int cur, int prev,
                          int out, hipStream_t s) {
   if (nwork <= 0) return;
-  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP, V>), dim3((unsigned)nwork), dim3(64 * TileCfg<T, NP, V>::NW), 0,
-                     s, probs, work, step, cur, prev, out);
+  hipLaunchKernelGGL((hx_cells_batch_kernel<T, NP, V, CPT>), dim3((unsigned)nwork),
+                     dim3(64 * TileCfg<T, NP, V>::NW), 0, s, probs, work, step, cur, prev, out);
 }
 
-// Calls f.template run<NP, V>() for a supported padded cell size and tile
-// variant (-1: the built-in choice); -1 otherwise.
+// Calls f.template run<NP, V, CPT>() for a supported padded cell size, tile
+// variant (-1: the built-in choice) and cells per tile (1, 2 or 4, with at
+// least 16 columns per cell); -1 otherwise.
+template <typename T, int NP, int V, typename F>
+static int with_cpt(int cpt, F &f) {
+  constexpr int TW = TileCfg<T, NP, V>::L::TW;
+  if (cpt == 1) {
+    f.template run<NP, V, 1>();
+    return 0;
+  }
+  // (four-cell-per-tile and two-cell tiles above p = 6 would need more
+  // registers or LDS than their tiles have to spare)
+  if constexpr (TW >= 32 && NP <= 352)
+    if (cpt == 2) {
+      f.template run<NP, V, 2>();
+      return 0;
+    }
+  if constexpr (TW >= 64 && NP <= 352)
+    if (cpt == 4) {
+      f.template run<NP, V, 4>();
+      return 0;
+    }
+  return -1;
+}
+
 template <typename T, typename F>
-static int with_cfg(int np, int variant, F &&f) {
+static int with_cfg(int np, int variant, int cpt, F &&f) {
   if (variant < 0) variant = default_variant<T>(np);
   if (variant > 1) return -1;
-#define CHFSI_NP_CASE(N)                      \
-  case N:                                     \
-    if (variant == 0) f.template run<N, 0>(); \
-    else f.template run<N, 1>();              \
-    return 0;
+#define CHFSI_NP_CASE(N) \
+  case N:                \
+    return variant == 0 ? with_cpt<T, N, 0>(cpt, f) : with_cpt<T, N, 1>(cpt, f);
   switch (np) {
     CHFSI_NP_CASE(16)    // p = 1
     CHFSI_NP_CASE(32)    // p = 2
@@ -658,27 +732,27 @@ static int with_cfg(int np, int variant, F &&f) {
 template <typename T>
 struct TileWidthOp {
   int tw = 0;
-  template <int NP, int V> void run() { tw = TileCfg<T, NP, V>::L::TW; }
+  template <int NP, int V, int CPT> void run() { tw = TileCfg<T, NP, V>::L::TW / CPT; }
 };
 template <typename T>
-int hx_tile_width(int np, int variant) {
+int hx_tile_width(int np, int variant, int cpt) {
   TileWidthOp<T> op;
-  return with_cfg<T>(np, variant, op) == 0 ? op.tw : -1;
+  return with_cfg<T>(np, variant, cpt, op) == 0 ? op.tw : -1;
 }
-template int hx_tile_width<double>(int, int);
-template int hx_tile_width<float>(int, int);
+template int hx_tile_width<double>(int, int, int);
+template int hx_tile_width<float>(int, int, int);
 
 template <typename T>
 struct LaunchCellsOp {
   const HxArgs<T> &a;
   int cb, ce;
   hipStream_t s;
-  template <int NP, int V> void run() { launch_cells<T, NP, V>(a, cb, ce, s); }
+  template <int NP, int V, int CPT> void run() { launch_cells<T, NP, V, CPT>(a, cb, ce, s); }
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s) {
   LaunchCellsOp<T> op{a, color_begin, color_end, s};
-  return with_cfg<T>(a.np, a.variant, op);
+  return with_cfg<T>(a.np, a.variant, a.cpt, op);
 }
 template int hx_cells_launch<double>(const HxArgs<double> &, int, int, hipStream_t);
 template int hx_cells_launch<float>(const HxArgs<float> &, int, int, hipStream_t);
@@ -687,12 +761,14 @@ struct LaunchCellsCplxOp {
   const HxArgs<double> &a;
   int cb, ce;
   hipStream_t s;
-  template <int NP, int V> void run() { launch_cells_cplx<NP, V>(a, cb, ce, s); }
+  template <int NP, int V, int CPT> void run() {
+    if constexpr (CPT == 1) launch_cells_cplx<NP, V>(a, cb, ce, s);
+  }
 };
 int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s) {
   if (a.ncols % 2) return -1;
   LaunchCellsCplxOp op{a, color_begin, color_end, s};
-  return with_cfg<double>(a.np, a.variant, op);
+  return with_cfg<double>(a.np, a.variant, 1, op);
 }
 
 struct LaunchCellsCplxKptsOp {
@@ -700,14 +776,16 @@ struct LaunchCellsCplxKptsOp {
   const CplxKpts &g;
   int cb, ce;
   hipStream_t s;
-  template <int NP, int V> void run() { launch_cells_cplx_kpts<NP, V>(a, g, cb, ce, s); }
+  template <int NP, int V, int CPT> void run() {
+    if constexpr (CPT == 1) launch_cells_cplx_kpts<NP, V>(a, g, cb, ce, s);
+  }
 };
 int hx_cells_cplx_kpts_launch(const HxArgs<double> &a, const CplxKpts &g, int color_begin, int color_end,
                               hipStream_t s) {
   if (a.ncols % 2) return -1;
   if ((int64_t)g.nk * (color_end - color_begin) * ((a.ncols + 31) / 32) > INT32_MAX) return -1;   // TW >= 32
   LaunchCellsCplxKptsOp op{a, g, color_begin, color_end, s};
-  return with_cfg<double>(a.np, a.variant, op);
+  return with_cfg<double>(a.np, a.variant, 1, op);
 }
 
 template <typename T>
@@ -716,18 +794,20 @@ struct LaunchBatchOp {
   const int4 *work;
   int nwork, step, cur, prev, out;
   hipStream_t s;
-  template <int NP, int V> void run() { launch_batch<T, NP, V>(probs, work, nwork, step, cur, prev, out, s); }
+  template <int NP, int V, int CPT> void run() {
+    launch_batch<T, NP, V, CPT>(probs, work, nwork, step, cur, prev, out, s);
+  }
 };
 template <typename T>
-int hx_cells_batch_launch(int np, int variant, const BatchProblem<T> *probs, const int4 *work, int nwork, int step,
-                          int cur, int prev, int out, hipStream_t s) {
+int hx_cells_batch_launch(int np, int variant, int cpt, const BatchProblem<T> *probs, const int4 *work, int nwork,
+                          int step, int cur, int prev, int out, hipStream_t s) {
   LaunchBatchOp<T> op{probs, work, nwork, step, cur, prev, out, s};
-  return with_cfg<T>(np, variant, op);
+  return with_cfg<T>(np, variant, cpt, op);
 }
-template int hx_cells_batch_launch<double>(int, int, const BatchProblem<double> *, const int4 *, int, int, int, int,
-                                           int, hipStream_t);
-template int hx_cells_batch_launch<float>(int, int, const BatchProblem<float> *, const int4 *, int, int, int, int, int,
-                                          hipStream_t);
+template int hx_cells_batch_launch<double>(int, int, int, const BatchProblem<double> *, const int4 *, int, int, int,
+                                           int, int, hipStream_t);
+template int hx_cells_batch_launch<float>(int, int, int, const BatchProblem<float> *, const int4 *, int, int, int,
+                                          int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // Precision conversion and column-block copies (strided, DoF-major)
 // ---------------------------------------------------------------------------

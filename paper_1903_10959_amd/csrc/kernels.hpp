@@ -25,13 +25,15 @@ struct HxArgs {
   int ncols;
   T s1, s2, shift;
   int variant;         // tile configuration: -1 built-in choice, 0 four-wave, 1 eight-wave
+  int cpt = 1;         // cells per work-group (1, 2 or 4): the tile's columns split over that many cells
 };
 template <typename T>
 int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStream_t s);
-// Columns per work-group of the cell kernel for padded cell size np (-1 if
-// np is not supported); column tiles of the batched work list use it.
+// Columns per cell of one work-group of the cell kernel for padded cell size
+// np, tile variant and cells per tile (-1 if not supported); the column
+// tiles of the batched work list use it.
 template <typename T>
-int hx_tile_width(int np, int variant);
+int hx_tile_width(int np, int variant, int cpt);
 // Complex cell products on interleaved (re, im) columns: a.K is the
 // [A ; B^T] operator (2 np x np) and a.ncols counts real columns (even).
 int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s);
@@ -55,14 +57,16 @@ struct BatchProblem {
   const int32_t *cmap;
   const T *minv, *V;
   const T *coef;       // [degree x 3]: s1, s2, shift per step
+  const int32_t *cells;  // the problem's cells sorted by colour
   int n_loc, q, n_el, ncols;
 };
-// Launch one Chebyshev step for a list of (problem, cell, column tile) work
-// items (int4: x = problem, y = cell, z = tile) whose problems share the padded
-// cell size np.
+// Launch one Chebyshev step for a list of work items (int4: x = problem, y =
+// first cell in the problem's colour-sorted cell list, z = column tile, w =
+// number of cells, at most cpt, all of one colour) whose problems share the
+// padded cell size np, tile variant and cells per tile.
 template <typename T>
-int hx_cells_batch_launch(int np, int variant, const BatchProblem<T> *probs, const int4 *work, int nwork, int step,
-                          int cur, int prev, int out, hipStream_t s);
+int hx_cells_batch_launch(int np, int variant, int cpt, const BatchProblem<T> *probs, const int4 *work, int nwork,
+                          int step, int cur, int prev, int out, hipStream_t s);
 // BF16 cell products: FP32 X/Y/minv, K_ref as BF16 hi (and lo when split),
 // padded to npb = round_up(n_loc, 32).
 struct HxBf16Args {

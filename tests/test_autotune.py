@@ -52,3 +52,29 @@ def test_tile_variant_tuner_picks_fastest_and_caches(tmp_path):
 
 def test_tile_variant_ties_prefer_variant_zero():
     assert AT.pick({0: 1.0, 1: 1.0}) == 0
+
+
+def test_cells_per_tile_tuner_picks_fastest_per_column_count(tmp_path):
+    path = str(tmp_path / "cache.json")
+    seen = []
+
+    def timer(cpt):
+        seen.append(cpt)
+        return {1: 3.0, 2: 1.0, 4: 2.0}[cpt]
+
+    assert AT.tune_cells_per_tile(_Ctx(), 24, None, "fp32", cache_path=path, timer=timer, arch="gfx950") == 2
+    assert sorted(seen) == [1, 2, 4]
+    n = len(seen)
+    assert AT.tune_cells_per_tile(_Ctx(), 24, None, "fp32", cache_path=path, timer=timer, arch="gfx950") == 2
+    assert len(seen) == n                      # cached
+    AT.tune_cells_per_tile(_Ctx(), 40, None, "fp32", cache_path=path, timer=timer, arch="gfx950")
+    assert len(seen) > n                       # another column count is another key
+
+
+def test_cells_per_tile_tuner_keeps_one_cell_above_p6(tmp_path):
+    class _P7:
+        p = 7
+    seen = []
+    AT.tune_cells_per_tile(_P7(), 24, None, "fp32", cache_path=str(tmp_path / "c.json"),
+                           timer=lambda c: seen.append(c) or 1.0, arch="gfx950")
+    assert seen == [1]

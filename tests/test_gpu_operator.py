@@ -172,3 +172,31 @@ def test_filter_bf16_keeps_wanted_subspace_small_workload():
     assert np.max(np.abs(evs["bf16"] - evs["fp64"])) < 5e-2
     assert np.max(np.abs(evs["bf16x3"] - evs["fp64"])) < 1e-4
     c.close()
+
+
+@pytest.mark.parametrize("n_el,p", [(4, 4), (3, 5), (2, 6)])
+@pytest.mark.parametrize("cpt", [0, 1, 2, 4])
+def test_cells_per_tile_settings_match_oracle(n_el, p, cpt):
+    """Work-groups holding 1, 2 or 4 cells of a colour (16-, 32- or 64-column
+    groups) compute the same products: FP64 and FP32 apply against the
+    oracle for column counts that fill, straddle and under-fill the groups,
+    and one filter step against the default setting bit for bit."""
+    L = 2.5 * n_el
+    wells = workload.draw_wells(4, L, 41 + p, (1.0, 3.0), (0.3, 0.6))
+    c, V = make_ctx(L, n_el, p, wells=wells)
+    c.set_cells_per_tile(cpt)
+    ap = oracle_apply(L, n_el, p, V)
+    for ncols in (8, 24, 40, 65, 128):
+        X = workload.start_block(c.n_dof, ncols, 3000 + ncols)
+        Yo = ap(X)
+        assert _rel(to_host(c.apply(to_gpu(X))), Yo) < 1e-13
+        assert _rel(to_host(c.apply(to_gpu(X), prec="fp32")), Yo) < 2e-6
+    X = workload.start_block(c.n_dof, 40, 3100)
+    b = c.upper_bound
+    A = to_gpu(X)
+    c.chebyshev_filter(A, 3, 0.5 * b, b, -1.0)
+    c.set_cells_per_tile(1)
+    B = to_gpu(X)
+    c.chebyshev_filter(B, 3, 0.5 * b, b, -1.0)
+    np.testing.assert_array_equal(to_host(A), to_host(B))
+    c.close()
