@@ -206,7 +206,8 @@ def batch_throughput(args):
            "config": {"workload": "batch: 64 problems, n_el in 4..12, p in 4..7, N in 16..256, L = 2.5 n_el, "
                                   f"{tot_dofs} DoFs in all, Chebyshev degree 20"},
            "one_at_a_time_seconds": t_seq, "batch_seconds": t_batch, "speedup_vs_one_at_a_time": t_seq / t_batch,
-           "tile_variant_per_degree": {str(k): v for k, v in sorted(tiles.items())}}
+           "tile_variant_per_degree": {str(k): v for k, v in sorted(tiles.items())},
+           "cells_per_tile_per_degree_and_block": {f"p{k[0]}/nb{k[1]}": v for k, v in sorted(cpts.items())}}
     print(json.dumps(out), flush=True)
     for c in ctxs:
         c.close()

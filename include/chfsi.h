@@ -75,12 +75,15 @@ int chfsi_create(chfsi_ctx **out, int device, void *hip_stream);
 int chfsi_destroy(chfsi_ctx *ctx);
 
 /* ---- setMesh (Sec. 2.4 eq. fem, Sec. 3.1 mesh; uniform cubes only) ------
- * Build the GLL rule of degree p (1..7: the degrees the device cell kernels
- * are built for; CHFSI_ERR_ARG otherwise), the reference cell stiffness
+ * Build the GLL rule of degree p (1..12; CHFSI_ERR_ARG otherwise), the
+ * reference cell stiffness
  * 1/2 (h/2)[K1 (x) W (x) W + W (x) K1 (x) W + W (x) W (x) K1] (h = L/n_el,
  * K1 = D^T W D, W = diag of GLL weights), the cell->dof map, the 8-colour
  * cell colouring (ex&1)+2(ey&1)+4(ez&1) and the diagonal mass M (GLL rule),
- * and upload them.  Resets any potential set before.  Requires n_el*p >= 2. */
+ * and upload them.  Resets any potential set before.  Requires n_el*p >= 2.
+ * Degrees 8..12 (n_loc = 729..2197) run the FP64/FP32 cell products in groups
+ * of 224 output rows per work-group; the BF16 products, the complex
+ * k-point operator and the batch session need p <= 7 (CHFSI_ERR_ARG). */
 int chfsi_set_mesh(chfsi_ctx *ctx, double L, int n_el, int p);
 int chfsi_get_sizes(const chfsi_ctx *ctx, int64_t *n_dof, int64_t *n_cells, int *n_loc);
 /* Host copies of the tables built by set_mesh (caller-owned host buffers). */

@@ -126,8 +126,6 @@ static int set_mesh_impl(chfsi_ctx *c, double L, int n_el, int p, bool periodic)
   MeshTables m;
   std::string msg = build_mesh(L, n_el, p, m, periodic);
   if (!msg.empty()) return fail(c, CHFSI_ERR_ARG, msg);
-  if (m.np != 16 && m.np != 32 && m.np != 64 && m.np != 128 && m.np != 224 && m.np != 352 && m.np != 512)
-    return fail(c, CHFSI_ERR_ARG, "set_mesh: degree p must be in 1..7 for the device cell kernel");
   c->has_mesh = c->has_pot = false;
   c->mesh = std::move(m);
   if (c->device < 0) {
@@ -135,19 +133,22 @@ static int set_mesh_impl(chfsi_ctx *c, double L, int n_el, int p, bool periodic)
     return 0;
   }
   const MeshTables &M = c->mesh;
-  const size_t nl = M.n_loc, np = M.np;
+  // the cell matrix, padded: np x np for the single-tile kernels (p <= 7);
+  // np x npr, npr a whole number of 224-row groups, for the row-group kernel
+  // of degrees 8..12
+  const size_t nl = M.n_loc, np = M.np, npr = M.p > 7 ? (size_t)hx_rows_padded(M.n_loc) : np;
   HIPCHK(c, c->cmap.ensure(M.cmap.size() * sizeof(int32_t)));
   HIPCHK(c, c->cells.ensure(M.cell_order.size() * sizeof(int32_t)));
-  HIPCHK(c, c->K64.ensure(np * np * sizeof(double)));
-  HIPCHK(c, c->K32.ensure(np * np * sizeof(float)));
+  HIPCHK(c, c->K64.ensure(np * npr * sizeof(double)));
+  HIPCHK(c, c->K32.ensure(np * npr * sizeof(float)));
   HIPCHK(c, c->minv64.ensure(M.n_dof * sizeof(double)));
   HIPCHK(c, c->minv32.ensure(M.n_dof * sizeof(float)));
-  std::vector<double> kp(np * np, 0.0);
-  std::vector<float> kp32(np * np, 0.f);
+  std::vector<double> kp(np * npr, 0.0);
+  std::vector<float> kp32(np * npr, 0.f);
   for (size_t i = 0; i < nl; ++i)
     for (size_t j = 0; j < nl; ++j) {
-      kp[i * np + j] = M.kcell[i * nl + j];
-      kp32[i * np + j] = (float)M.kcell[i * nl + j];
+      kp[i * npr + j] = M.kcell[i * nl + j];
+      kp32[i * npr + j] = (float)M.kcell[i * nl + j];
     }
   std::vector<double> mi(M.n_dof);
   std::vector<float> mi32(M.n_dof);
@@ -162,6 +163,17 @@ static int set_mesh_impl(chfsi_ctx *c, double L, int n_el, int p, bool periodic)
   HIPCHK(c, hipMemcpyAsync(c->K32.p, kp32.data(), kp32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->minv64.p, mi.data(), mi.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->minv32.p, mi32.data(), mi32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  c->kc_stride = (int)npr;
+  if (M.p > 7) {
+    // no BF16 or complex cell kernel above p = 7
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->npb = 0;
+    c->kvec[0] = c->kvec[1] = c->kvec[2] = 0.0;
+    c->kin_k = 3.0 * c->mesh.lam1d_max;
+    c->nk = 0;
+    c->has_mesh = true;
+    return 0;
+  }
   // BF16 hi/lo split of the cell matrix, padded to a multiple of 32 (BF16 MFMA depth)
   c->npb = (int)((nl + 31) / 32 * 32);
   const size_t nb2 = (size_t)c->npb * c->npb;
@@ -220,6 +232,7 @@ static int upload_kpoint(chfsi_ctx *c) {
 extern "C" int chfsi_set_kpoint(chfsi_ctx *c, double kx, double ky, double kz) {
   if (!c) return CHFSI_ERR_ARG;
   if (!c->has_mesh || !c->mesh.periodic) return fail(c, CHFSI_ERR_STATE, "set_kpoint: needs a periodic mesh");
+  if (c->mesh.p > 7) return fail(c, CHFSI_ERR_ARG, "set_kpoint: the complex cell kernel needs p <= 7");
   if (!std::isfinite(kx) || !std::isfinite(ky) || !std::isfinite(kz))
     return fail(c, CHFSI_ERR_ARG, "set_kpoint: k must be finite");
   c->kvec[0] = kx;
@@ -243,6 +256,7 @@ extern "C" int chfsi_set_kpoint(chfsi_ctx *c, double kx, double ky, double kz) {
 extern "C" int chfsi_set_kpoints(chfsi_ctx *c, int nk, const double *k) {
   if (!c) return CHFSI_ERR_ARG;
   if (!c->has_mesh || !c->mesh.periodic) return fail(c, CHFSI_ERR_STATE, "set_kpoints: needs a periodic mesh");
+  if (c->mesh.p > 7) return fail(c, CHFSI_ERR_ARG, "set_kpoints: the complex cell kernel needs p <= 7");
   if (nk < 1 || !k) return fail(c, CHFSI_ERR_ARG, "set_kpoints: need nk >= 1 and a host array of 3 nk values");
   for (int i = 0; i < 3 * nk; ++i)
     if (!std::isfinite(k[i])) return fail(c, CHFSI_ERR_ARG, "set_kpoints: k must be finite");
@@ -566,7 +580,9 @@ static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64
       if (e0) (void)hipEventRecord(e0, c->stream);
     }
     int lr;
-    if (bf) {
+    if (M.p > 7) {
+      lr = bf ? -1 : hx_rows_launch<T>(a, c->kc_stride, M.color_offset[col], M.color_offset[col + 1], c->stream);
+    } else if (bf) {
       HxBf16Args b;
       b.X = (const float *)X;
       b.ldx = ldx;
@@ -589,11 +605,13 @@ static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64
       b.s2 = (float)s2;
       b.shift = (float)shift;
       b.split = bf == 2;
+      b.cbw = c->tile_variant == 1 ? 1 : 2;
       lr = hx_cells_bf16_launch(b, M.color_offset[col], M.color_offset[col + 1], c->stream);
     } else {
       lr = hx_cells_launch<T>(a, M.color_offset[col], M.color_offset[col + 1], c->stream);
     }
-    if (lr != 0) return fail(c, CHFSI_ERR_ARG, "no cell kernel for this degree");
+    if (lr != 0)
+      return fail(c, CHFSI_ERR_ARG, bf ? "no BF16 cell kernel for this degree (p <= 7)" : "no cell kernel for this degree");
     if (c->timing && e0) {
       e1 = next_event(c);
       if (e1) (void)hipEventRecord(e1, c->stream);
@@ -1161,12 +1179,14 @@ extern "C" int chfsi_device_bytes(const chfsi_ctx *c, size_t *bytes) {
 }
 
 extern "C" size_t chfsi_footprint_bytes(int n_el, int p, int nblock, int block_width, chfsi_prec prec) {
-  if (n_el < 1 || p < 1 || p > 7 || nblock < 1) return 0;
+  if (n_el < 1 || p < 1 || p > 12 || nblock < 1) return 0;
+  if (p > 7 && prec != CHFSI_FP64 && prec != CHFSI_FP32) return 0;   // no BF16 kernel above p = 7
   const size_t n = (size_t)n_el * p - 1, nd = n * n * n, ncell = (size_t)n_el * n_el * n_el;
   const size_t nl = (size_t)(p + 1) * (p + 1) * (p + 1), np = (nl + 15) / 16 * 16;
+  const size_t npr = p > 7 ? (size_t)hx_rows_padded((int)nl) : np, npb = p > 7 ? 0 : (nl + 31) / 32 * 32;
   const size_t bw = (size_t)std::min(block_width > 0 ? block_width : 128, nblock);
   const size_t elem = prec == CHFSI_FP64 ? 8 : 4;
-  size_t b = ncell * nl * 4 + ncell * 4 + np * np * 12 + nd * 24;  // tables, K, minv, V
+  size_t b = ncell * nl * 4 + ncell * 4 + np * npr * 12 + nd * 24 + npb * npb * 4;  // tables, K, minv, V
   b += 3 * nd * bw * elem;                                         // filter buffers
   b += nd * nblock * 8;                                            // HX
   const size_t nn = (size_t)nblock * nblock;

@@ -49,7 +49,8 @@ struct chfsi_ctx {
   double vmax = 0, ub = 0;
   // device tables
   chfsi::DevBuf cmap, cells, K64, K32, minv64, minv32, V64, V32, Kbh, Kbl;
-  int npb = 0;   // n_loc rounded up to 32 (BF16 tiles)
+  int npb = 0;   // n_loc rounded up to 32 (BF16 tiles); 0 above p = 7 (no BF16 kernel)
+  int kc_stride = 0;  // row stride of the padded cell matrix K64 / K32
   int tile_variant = -1;  // cell-kernel tile configuration (-1: built-in choice)
   int cpt_setting = 0;    // cells per work-group of the cell kernel (0: chosen from the column count)
   int rr_residual = 0;    // Ritz residuals: 0 cost model, 1 rotate HX, 2 apply Htilde again

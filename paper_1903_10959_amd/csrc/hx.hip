@@ -349,6 +349,152 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 }
 
 // ---------------------------------------------------------------------------
+// Degrees 8..12 (n_loc = 729 .. 2197): the cell matrix no longer fits one
+// work-group's accumulators, so a work-group computes RT_NR = 224 output
+// rows [r0, r0 + 224) of one cell for 64 columns, contracting over all local
+// nodes (padded to npk, a multiple of 16).  The tile is the p = 5 eight-wave
+// one (2 x 4 waves, 7 row blocks and one column block each); the cell matrix
+// is stored [npk][npr] (npr = row groups x 224, zero padded), and the chunk
+// count is a run-time value.  Rows at or beyond n_loc are computed on zero
+// padding and not stored.
+// ---------------------------------------------------------------------------
+constexpr int RT_NR = 224, RT_NW = 8, RT_WR = 2, RT_WC = 4, RT_RBW = 7, RT_KC = 8, RT_TW = 64;
+constexpr int RT_NPMAX = 2240;   // p = 12: 2197 rows in ten groups of 224
+
+template <typename T>
+__global__ __launch_bounds__(64 * RT_NW) __attribute__((amdgpu_waves_per_eu(4))) void hx_rows_kernel(
+    const T *__restrict__ X, int64_t ldx, const T *__restrict__ Xp, int64_t ldp, T *__restrict__ Y, int64_t ldy,
+    const T *__restrict__ K, int npk, int npr, const int32_t *__restrict__ cmap, int n_loc, int q, int n_el,
+    const int32_t *__restrict__ cells, const T *__restrict__ minv, const T *__restrict__ V, int ncols, int ngrp,
+    int ntiles, T s1, T s2, T shift) {
+  typedef typename acc4<T>::type acc_t;
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int NT = 64 * RT_NW, VEC = 16 / sizeof(T);
+  constexpr int SK = sizeof(T) == 4 ? RT_NR + 16 : RT_NR;      // FP32 rows padded to 16 (mod 32) words
+  constexpr int SX = sizeof(T) == 4 ? RT_TW + 16 : RT_TW;
+  constexpr int KV = RT_KC * RT_NR / VEC, KPT = (KV + NT - 1) / NT, XPT = RT_KC * RT_TW / NT;
+  __shared__ int32_t dof_s[RT_NPMAX];
+  __shared__ T mi_s[RT_NPMAX];
+  __shared__ T vd_s[RT_NR];
+  __shared__ int8_t ft_s[RT_NR];
+  __shared__ __align__(16) T Ks[2][RT_KC * SK];
+  __shared__ __align__(16) T Xs[2][RT_KC * SX];
+  const int tile = blockIdx.x % ntiles;
+  const int rest = blockIdx.x / ntiles;
+  const int rg = rest % ngrp;
+  const int e = cells[rest / ngrp];
+  const int r0 = rg * RT_NR;
+  const int t = threadIdx.x;
+  for (int r = t; r < npr; r += NT) {
+    const int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
+    dof_s[r] = d < 0 ? 0 : d;
+    mi_s[r] = d < 0 ? T(0) : minv[d];
+  }
+  for (int rr = t; rr < RT_NR; rr += NT) {
+    const int r = r0 + rr;
+    const int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
+    const int ft = d < 0 ? 0 : first_touch(r, q, e, n_el);
+    ft_s[rr] = (int8_t)ft;
+    vd_s[rr] = ft ? s1 * (V[d] - shift) : T(0);
+  }
+  __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave / RT_WC, wc = wave - wr * RT_WC;
+  const int j = lane & 15, kq = lane >> 4;
+  const int col0 = tile * RT_TW;
+  const int xc = t % RT_TW, xrow0 = t / RT_TW;
+  const bool xok = col0 + xc < ncols;
+  const int xcol = xok ? col0 + xc : 0;
+  const T xscale = xok ? T(1) : T(0);
+  const int nch = npk / RT_KC;
+  vec_t kreg[KPT];
+  T xreg[XPT];
+  auto load_chunk = [&](int c) {
+    const T *Kc = K + (int64_t)c * RT_KC * npr + r0;
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int v = t + NT * i;
+      if (v < KV) {
+        const int row = v / (RT_NR / VEC), cv = v - row * (RT_NR / VEC);
+        kreg[i] = *reinterpret_cast<const vec_t *>(Kc + (int64_t)row * npr + cv * VEC);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int row = c * RT_KC + xrow0 + i * (NT / RT_TW);
+      xreg[i] = X[(int64_t)dof_s[row] * ldx + xcol];
+    }
+  };
+  auto store_chunk = [&](int buf, int c) {
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int v = t + NT * i;
+      if (v < KV) {
+        const int row = v / (RT_NR / VEC), cv = v - row * (RT_NR / VEC);
+        *reinterpret_cast<vec_t *>(&Ks[buf][row * SK + cv * VEC]) = kreg[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int rr = xrow0 + i * (NT / RT_TW);
+      Xs[buf][rr * SX + xc] = xreg[i] * (mi_s[c * RT_KC + rr] * xscale);
+    }
+  };
+  acc_t acc[RT_RBW];
+#pragma unroll
+  for (int r = 0; r < RT_RBW; ++r) acc[r] = acc_t{0, 0, 0, 0};
+  load_chunk(0);
+  store_chunk(0, 0);
+  __syncthreads();
+  const int arow = wr * RT_RBW * 16 + j;
+  const int bcol = wc * 16 + j;
+#pragma unroll 1
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load_chunk(c + 1);
+    const T *Kb = Ks[buf];
+    const T *Xb = Xs[buf];
+#pragma unroll
+    for (int kk = 0; kk < RT_KC / 4; ++kk) {
+      const T b = Xb[(4 * kk + kq) * SX + bcol];
+#pragma unroll
+      for (int r = 0; r < RT_RBW; ++r) acc[r] = mfma16x4(Kb[(4 * kk + kq) * SK + arow + 16 * r], b, acc[r]);
+    }
+    if (c + 1 < nch) store_chunk(buf ^ 1, c + 1);
+    __syncthreads();
+  }
+  // epilogue on the group's rows (row indices local to the group)
+  const EpiCtx<T> ec{X, ldx, Xp, ldp, Y, ldy, dof_s + r0, mi_s + r0, vd_s, ft_s, n_loc - r0, s1, s2};
+  const int ci = col0 + bcol;
+  const bool cok = ci < ncols;
+#pragma unroll
+  for (int r = 0; r < RT_RBW; ++r) {
+    EpiFrag<T> f;
+    const int row0 = (wr * RT_RBW + r) * 16;
+    epi_load(ec, row0, kq, cok ? ci : 0, f);
+    epi_store(ec, row0, kq, ci, cok, f, acc[r]);
+  }
+}
+
+template <typename T>
+int hx_rows_launch(const HxArgs<T> &a, int npr, int color_begin, int color_end, hipStream_t s) {
+  const int ncell = color_end - color_begin;
+  const int ntiles = (a.ncols + RT_TW - 1) / RT_TW;
+  const int ngrp = npr / RT_NR;
+  if (ncell <= 0 || ntiles <= 0) return 0;
+  if (npr % RT_NR || npr > RT_NPMAX || a.np % 16 || a.np > npr) return -1;
+  if ((int64_t)ncell * ngrp * ntiles > INT32_MAX) return -1;
+  hipLaunchKernelGGL((hx_rows_kernel<T>), dim3((unsigned)(ncell * ngrp * ntiles)), dim3(64 * RT_NW), 0, s, a.X,
+                     a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.K, a.np, npr, a.cmap, a.n_loc, a.q, a.n_el,
+                     a.cells + color_begin, a.minv, a.V, a.ncols, ngrp, ntiles, a.s1, a.s2, a.shift);
+  return 0;
+}
+template int hx_rows_launch<double>(const HxArgs<double> &, int, int, int, hipStream_t);
+template int hx_rows_launch<float>(const HxArgs<float> &, int, int, int, hipStream_t);
+
+int hx_rows_padded(int n_loc) { return (n_loc + RT_NR - 1) / RT_NR * RT_NR; }
+
+// ---------------------------------------------------------------------------
 // BF16 cell products (FP32 state, FP32 accumulation): v_mfma_f32_16x16x32_bf16.
 // The cell's gathered, M^-1/2-scaled X rows (64 columns) are converted to BF16
 // (round to nearest even) and staged in LDS transposed, [column][local node],
@@ -357,7 +503,11 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 // hi*hi + hi*lo + lo*hi accumulated in FP32.  NPB: n_loc rounded up to 32.
 // ---------------------------------------------------------------------------
 // EPD: epilogue fragments in flight (3 measured no faster than 2).
-template <int NPB, bool SPLIT, int EPD = 2>
+// CBW: 16-column blocks per wave, so a work-group covers TWB = 32 CBW columns
+// (two blocks: every K fragment feeds two MFMAs; one block: half the LDS per
+// work-group, so more work-groups share a CU and overlap their gathers and
+// epilogues).
+template <int NPB, bool SPLIT, int CBW = 2, int EPD = 2>
 __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
                                                             const float *__restrict__ Xp, int64_t ldp,
                                                             float *__restrict__ Y, int64_t ldy,
@@ -375,13 +525,15 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   __shared__ float mi_s[NPB];
   __shared__ float vd_s[NPB];
   __shared__ int8_t ft_s[NPB];
-  __shared__ __attribute__((aligned(16))) __bf16 xs[NPART][64 * LDX];
+  constexpr int TWB = 32 * CBW;          // columns per work-group
+  constexpr int NG4 = TWB / 4;            // groups of four columns
+  __shared__ __attribute__((aligned(16))) __bf16 xs[NPART][TWB * LDX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cell_slot = blockIdx.x / ntiles;
   const int tile = blockIdx.x - cell_slot * ntiles;
   const int e = cells[cell_slot];
-  const int col0 = tile * 64;
+  const int col0 = tile * TWB;
   for (int r = threadIdx.x; r < NPB; r += blockDim.x) {
     int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
     dof_s[r] = d < 0 ? 0 : d;
@@ -395,14 +547,14 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   // aligned), SU rows per thread per round with every load issued first
   const bool vec_ok = ((ldx & 3) == 0) && ((col0 & 3) == 0) && ((((uintptr_t)X) & 15) == 0);
   constexpr int SU = 8;   // (all 22 rows at once measured no faster)
-  for (int base = threadIdx.x; base < NPB * 16; base += SU * 256) {
+  for (int base = threadIdx.x; base < NPB * NG4; base += SU * 256) {
     float v[SU][4];
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int idx = base + u * 256;
       v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.f;
-      if (idx < NPB * 16) {
-        const int r = idx >> 4, c4 = (idx & 15) * 4;
+      if (idx < NPB * NG4) {
+        const int r = idx / NG4, c4 = (idx % NG4) * 4;
         const float *src = X + (int64_t)dof_s[r] * ldx + col0 + c4;
         if (vec_ok && col0 + c4 + 3 < ncols) {
           const float4 t = *reinterpret_cast<const float4 *>(src);
@@ -416,8 +568,8 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int idx = base + u * 256;
-      if (idx < NPB * 16) {
-        const int r = idx >> 4, c4 = (idx & 15) * 4;
+      if (idx < NPB * NG4) {
+        const int r = idx / NG4, c4 = (idx % NG4) * 4;
         const float w = mi_s[r];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -436,9 +588,11 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   constexpr int RBW = RB / 2;
   const int wr = wave >> 1, wc = wave & 1;
   const int j = lane & 15, kq = lane >> 4;
-  v4f acc[RBW][2];
+  v4f acc[RBW][CBW];
 #pragma unroll
-  for (int r = 0; r < RBW; ++r) acc[r][0] = acc[r][1] = v4f{0, 0, 0, 0};
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = v4f{0, 0, 0, 0};
   typedef __attribute__((ext_vector_type(4))) int v4i;
   const __bf16 *Kh_w = Kh + (int64_t)(wr * RBW * 16 + j) * NPB + 8 * kq;   // A[i][k..k+7] = K[i][k..k+7]
   const __bf16 *Kl_w = SPLIT ? Kl + (int64_t)(wr * RBW * 16 + j) * NPB + 8 * kq : nullptr;
@@ -458,21 +612,21 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
       const int kn = kk + 32 < NPB ? kk + 32 : kk;
 #pragma unroll
       for (int r = 0; r < RBW; ++r) ah[u ^ 1][r] = load_a(Kh_w, kn, r);
-      v8bf bh[2], bl[2];
+      v8bf bh[CBW], bl[CBW];
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const int lc = wc * 32 + cb * 16 + j;
+      for (int cb = 0; cb < CBW; ++cb) {
+        const int lc = wc * 16 * CBW + cb * 16 + j;
         bh[cb] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i *>(&xs[0][lc * LDX + kk + 8 * kq]));
         if (SPLIT) bl[cb] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i *>(&xs[NPART - 1][lc * LDX + kk + 8 * kq]));
       }
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[r][cb] = mfma16x32bf(ah[u][r], bh[cb], acc[r][cb]);
+        for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = mfma16x32bf(ah[u][r], bh[cb], acc[r][cb]);
         if (SPLIT) {
           const v8bf al = load_a(Kl_w, kk, r);
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) {
+          for (int cb = 0; cb < CBW; ++cb) {
             acc[r][cb] = mfma16x32bf(ah[u][r], bl[cb], acc[r][cb]);
             acc[r][cb] = mfma16x32bf(al, bh[cb], acc[r][cb]);
           }
@@ -483,9 +637,9 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
 
   // epilogue, software-pipelined EPD - 1 fragments ahead
   const EpiCtx<float> ec{X, ldx, Xp, ldp, Y, ldy, dof_s, mi_s, vd_s, ft_s, n_loc, s1, s2};
-  constexpr int NF = RBW * 2;
-  auto frag_col = [&](int i) { return col0 + wc * 32 + 16 * (i & 1) + j; };
-  auto frag_row = [&](int i) { return (wr * RBW + i / 2) * 16; };
+  constexpr int NF = RBW * CBW;
+  auto frag_col = [&](int i) { return col0 + wc * 16 * CBW + 16 * (i % CBW) + j; };
+  auto frag_row = [&](int i) { return (wr * RBW + i / CBW) * 16; };
   auto frag_load = [&](int i, EpiFrag<float> &f) {
     const int ci = frag_col(i);
     epi_load(ec, frag_row(i), kq, ci < ncols ? ci : ncols - 1, f);
@@ -498,32 +652,38 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   for (int i = 0; i < NF; ++i) {
     if (i + EPD - 1 < NF) frag_load(i + EPD - 1, f[(i + EPD - 1) % EPD]);
     const int ci = frag_col(i);
-    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i % EPD], acc[i / 2][i & 1]);
+    epi_store(ec, frag_row(i), kq, ci, ci < ncols, f[i % EPD], acc[i / CBW][i % CBW]);
   }
 }
 
-template <int NPB, bool SPLIT>
+template <int NPB, bool SPLIT, int CBW>
 static void launch_bf16(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
-  int ntiles = (a.ncols + 63) / 64;
+  constexpr int TWB = 32 * CBW;
+  int ntiles = (a.ncols + TWB - 1) / TWB;
   int ncell = color_end - color_begin;
   if (ncell <= 0 || ntiles <= 0) return;
-  hipLaunchKernelGGL((hx_cells_bf16_kernel<NPB, SPLIT>), dim3((unsigned)(ncell * ntiles)), dim3(256), 0, s, a.X,
+  hipLaunchKernelGGL((hx_cells_bf16_kernel<NPB, SPLIT, CBW>), dim3((unsigned)(ncell * ntiles)), dim3(256), 0, s, a.X,
                      a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.Kh, a.Kl, a.cmap, a.n_loc, a.q, a.n_el,
                      a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
 }
 
-template <bool SPLIT>
-static int dispatch_bf16(const HxBf16Args &a, int cb, int ce, hipStream_t s) {
+template <bool SPLIT, int CBW>
+static int dispatch_bf16_w(const HxBf16Args &a, int cb, int ce, hipStream_t s) {
   switch (a.npb) {
-    case 32: launch_bf16<32, SPLIT>(a, cb, ce, s); break;
-    case 64: launch_bf16<64, SPLIT>(a, cb, ce, s); break;
-    case 128: launch_bf16<128, SPLIT>(a, cb, ce, s); break;
-    case 224: launch_bf16<224, SPLIT>(a, cb, ce, s); break;
-    case 352: launch_bf16<352, SPLIT>(a, cb, ce, s); break;
-    case 512: launch_bf16<512, SPLIT>(a, cb, ce, s); break;
+    case 32: launch_bf16<32, SPLIT, CBW>(a, cb, ce, s); break;
+    case 64: launch_bf16<64, SPLIT, CBW>(a, cb, ce, s); break;
+    case 128: launch_bf16<128, SPLIT, CBW>(a, cb, ce, s); break;
+    case 224: launch_bf16<224, SPLIT, CBW>(a, cb, ce, s); break;
+    case 352: launch_bf16<352, SPLIT, CBW>(a, cb, ce, s); break;
+    case 512: launch_bf16<512, SPLIT, CBW>(a, cb, ce, s); break;
     default: return -1;
   }
   return 0;
+}
+
+template <bool SPLIT>
+static int dispatch_bf16(const HxBf16Args &a, int cb, int ce, hipStream_t s) {
+  return a.cbw == 1 ? dispatch_bf16_w<SPLIT, 1>(a, cb, ce, s) : dispatch_bf16_w<SPLIT, 2>(a, cb, ce, s);
 }
 
 int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {

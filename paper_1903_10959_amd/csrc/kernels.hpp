@@ -34,6 +34,12 @@ int hx_cells_launch(const HxArgs<T> &a, int color_begin, int color_end, hipStrea
 // tiles of the batched work list use it.
 template <typename T>
 int hx_tile_width(int np, int variant, int cpt);
+// Degrees 8..12: row-group kernel, a.K stored [a.np][npr] (a.np = n_loc
+// rounded up to 16, npr = hx_rows_padded(n_loc)), zero padded; -1 for
+// arguments it does not support.
+template <typename T>
+int hx_rows_launch(const HxArgs<T> &a, int npr, int color_begin, int color_end, hipStream_t s);
+int hx_rows_padded(int n_loc);
 // Complex cell products on interleaved (re, im) columns: a.K is the
 // [A ; B^T] operator (2 np x np) and a.ncols counts real columns (even).
 int hx_cells_cplx_launch(const HxArgs<double> &a, int color_begin, int color_end, hipStream_t s);
@@ -84,6 +90,7 @@ struct HxBf16Args {
   int ncols;
   float s1, s2, shift;
   int split;
+  int cbw = 2;         // 16-column blocks per wave: 2 (64-column tiles) or 1 (32-column tiles)
 };
 int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s);
 template <typename Tin, typename Tout>

@@ -133,13 +133,16 @@ def test_filter_matches_oracle_small_workload():
     c.close()
 
 
+@pytest.mark.parametrize("variant", [-1, 1])
 @pytest.mark.parametrize("n_el,p,ncols", [(4, 4, 24), (3, 6, 70), (2, 7, 33), (4, 5, 64)])
-def test_apply_bf16_and_split_accuracy(n_el, p, ncols):
+def test_apply_bf16_and_split_accuracy(n_el, p, ncols, variant):
     """BF16 inputs with FP32 accumulation: error at the BF16 rounding level
-    (2^-8 relative per operand); the hi/lo split recovers about 2^-16."""
+    (2^-8 relative per operand); the hi/lo split recovers about 2^-16.
+    Variant 1 runs the BF16 kernel on 32-column tiles."""
     L = 2.5 * n_el
     wells = workload.draw_wells(4, L, 31 + p, (1.0, 3.0), (0.3, 0.6))
     c, V = make_ctx(L, n_el, p, wells=wells)
+    c.set_tile_variant(variant)
     X = workload.start_block(c.n_dof, ncols, 2000 + p)
     Yo = oracle_apply(L, n_el, p, V)(X)
     e_bf = _rel(to_host(c.apply(to_gpu(X), prec="bf16")), Yo)

@@ -103,16 +103,19 @@ def test_footprint_is_consistent():
     assert P.footprint_bytes(24, 6, 568, 128, "fp32") < big
 
 
-@pytest.mark.parametrize("p", [8, 9, 12])
-def test_degrees_without_a_cell_kernel_are_rejected_at_set_mesh(p):
-    """The header's range is p = 1..7 (the degrees the device cell kernels
-    are built for): a higher degree fails at set_mesh, not at the first apply."""
+@pytest.mark.parametrize("p", [8, 12])
+def test_high_degrees_build_and_have_fp64_footprints_only(p):
+    """p = 8..12 build their tables (row-group cell kernel in FP64/FP32); the
+    BF16 kernel and the batch session stop at p = 7, and p = 13 is refused."""
     P = _lib_or_skip()
-    c = P.Context(device=-1)
-    with pytest.raises(P.ChfsiError) as ei:
-        c.set_mesh(10.0, 2, p)
-    assert ei.value.status == -1
-    assert P.footprint_bytes(2, p, 8) == 0 and P.batch_footprint_bytes(2, p, 8) == 0
+    c = P.Context(device=-1).set_mesh(10.0, 2, p)
+    assert c.n_loc == (p + 1) ** 3
+    np.testing.assert_array_equal(c.cell_dof_map(), fem.cell_dof_map(2, p))
+    c.close()
+    assert P.footprint_bytes(2, p, 8) > 0 and P.footprint_bytes(2, p, 8, 0, "fp32") > 0
+    assert P.footprint_bytes(2, p, 8, 0, "bf16") == 0 and P.batch_footprint_bytes(2, p, 8) == 0
+    with pytest.raises(P.ChfsiError):
+        P.Context(device=-1).set_mesh(10.0, 2, 13)
 
 
 def test_batch_footprint_counts_every_session_buffer():
