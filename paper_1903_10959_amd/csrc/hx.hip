@@ -358,7 +358,7 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
 // count is a run-time value.  Rows at or beyond n_loc are computed on zero
 // padding and not stored.
 // ---------------------------------------------------------------------------
-constexpr int RT_NR = 224, RT_NW = 8, RT_WR = 2, RT_WC = 4, RT_RBW = 7, RT_KC = 8, RT_TW = 64;
+constexpr int RT_NR = 224, RT_NW = 8, RT_WC = 4, RT_RBW = 7, RT_KC = 8, RT_TW = 64;   // waves 2 x 4
 constexpr int RT_NPMAX = 2240;   // p = 12: 2197 rows in ten groups of 224
 
 template <typename T>

@@ -12,11 +12,19 @@
 // k the assembled 1D Laplacian stiffness (band half-width p), m the 1D GLL
 // mass.  This is the matrix-free operator in its assembled form, applied as a
 // blocked stencil that reads x about once from HBM and writes y once (16 bytes
-// per DoF).  Per CG iteration: the
-// product fused with the partial p.q, one kernel for x, r, z and the partial
-// r.z, r.r, one for the new direction, and two single-work-group reductions
-// in a fixed order that keep alpha and beta on the device.  The host reads
-// r.r every few iterations to stop.
+// per DoF).
+//
+// One CG iteration is five launches: the product fused with the partial p.q;
+// a single-work-group reduction in a fixed order (alpha = r.z / p.q); x, r, z
+// with the partials of r.z and r.r; a second reduction (beta = r.z' / r.z,
+// the iteration count, and the stop flag once r.r <= tol^2 f.f); the new
+// direction p = z + beta p.  Once the flag is up every further launch returns
+// at once, so the host launches iterations in groups and reads the flag
+// between groups.  (Forming p inside the product, where the stencil reads it,
+// saves the direction pass but reads two arrays at every halo point: measured
+// 2.3x slower per product.  Summing the partials in the last work-group of
+// each grid saves the small launches, but every work-group's device-scope
+// release then writes back its L2: slower again.)
 #include "common.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
@@ -29,9 +37,9 @@
 namespace chfsi {
 
 static constexpr int PB = 256;              // threads per work-group
-static constexpr int PR = 1024;             // threads of the final reductions
+static constexpr int PR = 1024;             // threads of the setup reduction
 static constexpr int MAXG = 2048;           // element-wise grids: at most this many work-groups (grid-stride)
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_FF, S_NSCAL };
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_FF, S_STOP, S_DONE, S_IT, S_NSCAL };
 
 template <int NT = PB>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -52,103 +60,141 @@ __device__ __forceinline__ double poisson_diag(const double *__restrict__ kb, co
   return s * (kb[I * bw + p] * m[J] * m[K] + m[I] * kb[J * bw + p] * m[K] + m[I] * m[J] * kb[K * bw + p]);
 }
 
-// y = A x with 2.5D blocking: work-group = 64 consecutive I (one wave per row)
-// x TY rows J, marching over KB planes K.  Per plane the work-group stages the
-// plane's (TX + 2P) x (TY + 2P) halo tile of x in LDS (the x- and y-direction
-// neighbours), and each thread keeps its z-window of 2P + 1 values in
-// registers, so an output costs about 6 global loads instead of 3 (2P + 1).
-// The band coefficients of the tile's I and J rows sit in LDS too.
-// Grid: ceil(n/TX) ceil(n/TY) ceil(n/KB) work-groups (1D, XCD-grouped);
-// part[block] = the block's sum of x . y over its outputs (when part is given).
-constexpr int TX = 64, TY = 4, KB = 8, PA = TX * TY;
-template <int P>
-__global__ __launch_bounds__(PA) void poisson_apply_kernel(const double *__restrict__ x, double *__restrict__ y,
-                                                           const double *__restrict__ kb, const double *__restrict__ m,
-                                                           int n, double s, double *__restrict__ part) {
-  constexpr int BW = 2 * P + 1, WX = TX + 2 * P, WY = TY + 2 * P;
-  __shared__ double sh[PA];
+// y = A x with 2.5D blocking.  Work-group = 4 waves; wave w covers 64
+// consecutive I (one lane each) and the RY rows J0 + w RY + [0, RY); the
+// work-group marches over KB planes K.  Per plane it stages the plane's
+// (64 + 2P) x (4 RY + 2P) halo tile of x in LDS (the x- and y-direction
+// neighbours); each lane keeps, per row, its z-window of 2P + 1 values in
+// registers.  The lane's x-direction band coefficients sit in registers, the
+// wave's y- and z-direction ones are wave-uniform (scalar loads), and the
+// y-direction sums of a lane's RY rows share one LDS column read of RY + 2P
+// values.  The plane tiles are fetched PD planes ahead.  DOT: part[work-group]
+// = its share of x . y.
+// Grid: ceil(n/64) ceil(n/(4 RY)) ceil(n/KB) work-groups (1D, XCD-grouped).
+constexpr int TX = 64;
+template <int P, int RY, int KB, int PD, bool DOT>
+__global__ __launch_bounds__(PB) void poisson_stencil_kernel(const double *__restrict__ x, double *__restrict__ y,
+                                                             const double *__restrict__ kb,
+                                                             const double *__restrict__ m, int n, double s,
+                                                             const double *__restrict__ scal,
+                                                             double *__restrict__ part) {
+  constexpr int BW = 2 * P + 1, TY = 4 * RY, WX = TX + 2 * P, WY = TY + 2 * P;
+  constexpr int NTL = (WY * WX + PB - 1) / PB;    // tile values per thread
+  __shared__ double sh[PB];
   __shared__ double xs[WY][WX];
-  __shared__ double kx[TX][BW], ky[TY][BW];
-  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> 6;
+  if (DOT && scal[S_DONE] != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // XCD-grouped block order: the hardware deals consecutive work-groups to the
   // 8 XCDs in turn; the logical index below is contiguous per XCD, and tiles
-  // adjacent in J (which share 12 of their 16 halo rows) get consecutive
-  // logical indices, so their shared rows are fetched into one L2
+  // adjacent in J (which share their halo rows) get consecutive logical
+  // indices, so their shared rows are fetched into one L2
   const int g = (int)gridDim.x, b = (int)blockIdx.x;
   const int lid = (b & 7) * (g >> 3) + min(b & 7, g & 7) + (b >> 3);
   const int gx = (n + TX - 1) / TX, gy = (n + TY - 1) / TY;
   const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
   const int I0 = bx * TX, J0 = by * TY, K0 = bz * KB;
-  const int I = I0 + tx, J = J0 + ty;
+  const int I = I0 + lane;
   const int64_t n2 = (int64_t)n * n;
-  for (int e = threadIdx.x; e < TX * BW; e += PA) {
-    const int i = I0 + e / BW;
-    kx[e / BW][e % BW] = i < n ? kb[(int64_t)i * BW + e % BW] : 0.0;
-  }
-  for (int e = threadIdx.x; e < TY * BW; e += PA) {
-    const int j = J0 + e / BW;
-    ky[e / BW][e % BW] = j < n ? kb[(int64_t)j * BW + e % BW] : 0.0;
-  }
-  const bool live = I < n && J < n;
-  const double mI = live ? m[I] : 0.0, mJ = live ? m[J] : 0.0;
-  // z-window: x(I, J, K - P .. K + P), zero outside the mesh (Dirichlet)
-  double win[BW];
-  const int64_t col = (int64_t)I + (int64_t)n * J;
+  const bool ilive = I < n;
+  double kx[BW];
 #pragma unroll
-  for (int d = 0; d < BW; ++d) {
-    const int k = K0 - P + d - 1;                  // shifted in at the first plane
-    win[d] = (live && k >= 0 && k < n) ? x[col + k * n2] : 0.0;
+  for (int d = 0; d < BW; ++d) kx[d] = ilive ? kb[(int64_t)I * BW + d] : 0.0;
+  const double mI = ilive ? m[I] : 0.0;
+  // this wave's rows (wave-uniform)
+  int Jr[RY];
+  bool live[RY];
+  double mJ[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    Jr[r] = J0 + w * RY + r;
+    live[r] = ilive && Jr[r] < n;
+    mJ[r] = Jr[r] < n ? m[Jr[r]] : 0.0;
   }
-  // the plane tile is loaded into registers one plane ahead (its latency
-  // hides behind the current plane's sums), then stored to LDS (two planes
-  // ahead measured no faster: the extra registers cost occupancy)
-  constexpr int NTL = (WY * WX + PA - 1) / PA;    // tile values per thread
-  double treg[NTL];
-  double wnext;
-  auto load_plane = [&](int K) {
+  // z-windows: x(I, J_r, K - P .. K + P), zero outside the mesh (Dirichlet)
+  double win[RY][BW];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int64_t col = (int64_t)I + (int64_t)n * Jr[r];
+#pragma unroll
+    for (int d = 0; d < BW; ++d) {
+      const int k = K0 - P + d - 1;                // shifted in at the first plane
+      win[r][d] = (live[r] && k >= 0 && k < n) ? x[col + k * n2] : 0.0;
+    }
+  }
+  // the plane tiles are loaded into registers PD planes ahead, in PD sets
+  // used in turn (their latency hides behind PD planes of sums), then stored
+  // to LDS
+  double treg[PD][NTL];
+  double wnext[PD][RY];
+  auto load_plane = [&](int K, double(&tr)[NTL], double(&wn)[RY]) {
 #pragma unroll
     for (int u = 0; u < NTL; ++u) {
-      const int e = threadIdx.x + u * PA;
-      const int r = e / WX, cc = e - r * WX;
-      const int i = I0 - P + cc, j = J0 - P + r;
-      treg[u] = (e < WY * WX && i >= 0 && i < n && j >= 0 && j < n) ? x[(int64_t)i + (int64_t)n * j + K * n2] : 0.0;
+      const int e = threadIdx.x + u * PB;
+      const int rr = e / WX, cc = e - rr * WX;
+      const int i = I0 - P + cc, j = J0 - P + rr;
+      tr[u] = (e < WY * WX && i >= 0 && i < n && j >= 0 && j < n) ? x[(int64_t)i + (int64_t)n * j + K * n2] : 0.0;
     }
     const int k = K + P;
-    wnext = (live && k < n) ? x[col + k * n2] : 0.0;
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+      wn[r] = (live[r] && k < n) ? x[(int64_t)I + (int64_t)n * Jr[r] + k * n2] : 0.0;
   };
   double dot = 0;
   const int K1 = min(K0 + KB, n);
-  load_plane(K0);
-  for (int K = K0; K < K1; ++K) {
+  // plane K from the set (tr, wn), which then receives plane K + PD
+  auto plane = [&](int K, double(&tr)[NTL], double(&wn)[RY]) {
     __syncthreads();                               // previous plane's tile consumed
 #pragma unroll
     for (int u = 0; u < NTL; ++u) {
-      const int e = threadIdx.x + u * PA;
-      if (e < WY * WX) xs[e / WX][e % WX] = treg[u];
+      const int e = threadIdx.x + u * PB;
+      if (e < WY * WX) xs[e / WX][e % WX] = tr[u];
     }
 #pragma unroll
-    for (int d = 0; d < BW - 1; ++d) win[d] = win[d + 1];
-    win[BW - 1] = wnext;
+    for (int r = 0; r < RY; ++r) {
+#pragma unroll
+      for (int d = 0; d < BW - 1; ++d) win[r][d] = win[r][d + 1];
+      win[r][BW - 1] = wn[r];
+    }
     __syncthreads();
-    if (K + 1 < K1) load_plane(K + 1);
-    if (live) {
+    if (K + PD < K1) load_plane(K + PD, tr, wn);
+    const double *kz = kb + (int64_t)K * BW;
+    const double mK = m[K];
+    double colv[RY + 2 * P];
+#pragma unroll
+    for (int i = 0; i < RY + 2 * P; ++i) colv[i] = xs[w * RY + i][lane + P];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (!live[r]) continue;
+      const double *ky = kb + (int64_t)Jr[r] * BW;
       double sx = 0, sy = 0, sz = 0;
-      const double *kz = kb + (int64_t)K * BW;
 #pragma unroll
       for (int d = 0; d < BW; ++d) {
-        sx += kx[tx][d] * xs[ty + P][tx + d];
-        sy += ky[ty][d] * xs[ty + d][tx + P];
-        sz += kz[d] * win[d];
+        sx += kx[d] * xs[w * RY + r + P][lane + d];
+        sy += ky[d] * colv[r + d];
+        sz += kz[d] * win[r][d];
       }
-      const double mK = m[K];
-      const double v = s * (mJ * mK * sx + mI * mK * sy + mI * mJ * sz);
-      const int64_t idx = col + K * n2;
-      y[idx] = v;
-      dot += xs[ty + P][tx + P] * v;
+      const double v = s * (mJ[r] * mK * sx + mI * mK * sy + mI * mJ[r] * sz);
+      y[(int64_t)I + (int64_t)n * Jr[r] + K * n2] = v;
+      if constexpr (DOT) dot += win[r][P] * v;
     }
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (K0 + d < K1) load_plane(K0 + d, treg[d], wnext[d]);
+  int K = K0;
+  if constexpr (PD == 2) {
+    // pairs in the loop (no branch between the halves), an odd last plane after it
+    for (; K + 1 < K1; K += 2) {
+      plane(K, treg[0], wnext[0]);
+      plane(K + 1, treg[1], wnext[1]);
+    }
+    if (K < K1) plane(K, treg[0], wnext[0]);
+  } else {
+    for (; K < K1; ++K) plane(K, treg[0], wnext[0]);
   }
-  if (part) {
-    const double bsum = block_sum<PA>(dot, sh);
+  if constexpr (DOT) {
+    const double bsum = block_sum(dot, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = bsum;
   }
 }
@@ -161,6 +207,7 @@ __global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__
                                                             const double *__restrict__ scal,
                                                             double *__restrict__ part_rz, double *__restrict__ part_rr) {
   __shared__ double sh[PB];
+  if (scal[S_DONE] != 0) return;
   double rz = 0, rr = 0;
   const double alpha = scal[S_ALPHA];
   for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB) {
@@ -183,13 +230,14 @@ __global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__
 // p = z + beta p
 __global__ __launch_bounds__(PB) void poisson_dir_kernel(double *__restrict__ pv, const double *__restrict__ z,
                                                          const double *__restrict__ scal, int64_t nd) {
+  if (scal[S_DONE] != 0) return;
   const double beta = scal[S_BETA];
   for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB)
     pv[idx] = z[idx] + beta * pv[idx];
 }
 
-// Setup: f = M rho (M = 1/minv^2) into r0's place; r = f - A x (q = A x given),
-// z = r / diag, p = z; partials of r.z, r.r and f.f.
+// Setup: r = f - A x (q = A x given), z = r / diag, p = z; partials of r.z,
+// r.r and f.f.
 __global__ __launch_bounds__(PB) void poisson_init_kernel(const double *__restrict__ f, const double *__restrict__ q,
                                                           double *__restrict__ r, double *__restrict__ z,
                                                           double *__restrict__ pv, double *__restrict__ dinv,
@@ -239,35 +287,60 @@ __global__ __launch_bounds__(PB) void poisson_charges_kernel(double *__restrict_
   if (i < nq) f[dofs[i]] += q[i];
 }
 
-// Fixed-order sums of the partials, then the scalar recurrences:
-// mode 0: pq = sum a; alpha = rz / pq.
-// mode 1: rz' = sum a, rr = sum b; beta = rz' / rz; rz = rz'.
-// mode 2 (setup): rz = sum a, rr = sum b, ff = sum c.
-__global__ __launch_bounds__(PR) void poisson_reduce_kernel(const double *__restrict__ a, const double *__restrict__ b,
-                                                            const double *__restrict__ c, int nparts, int mode,
-                                                            double *__restrict__ scal) {
+// Setup sums in a fixed order: r.z, r.r, f.f; the stop threshold
+// tol^2 f.f, beta = 0, the iteration count and the stop flag (raised at once
+// when the initial guess already meets the tolerance).
+__global__ __launch_bounds__(PR) void poisson_setup_reduce_kernel(const double *__restrict__ a,
+                                                                  const double *__restrict__ b,
+                                                                  const double *__restrict__ c, int nparts,
+                                                                  double tol2, double *__restrict__ scal) {
   __shared__ double sh[PR];
   double sa = 0, sb = 0, sc = 0;
   for (int i = threadIdx.x; i < nparts; i += PR) {
     sa += a[i];
-    if (mode >= 1) sb += b[i];
-    if (mode == 2) sc += c[i];
+    sb += b[i];
+    sc += c[i];
   }
   sa = block_sum<PR>(sa, sh);
-  if (mode >= 1) sb = block_sum<PR>(sb, sh);
-  if (mode == 2) sc = block_sum<PR>(sc, sh);
+  sb = block_sum<PR>(sb, sh);
+  sc = block_sum<PR>(sc, sh);
+  if (threadIdx.x == 0) {
+    scal[S_RZ] = sa;
+    scal[S_RR] = sb;
+    scal[S_FF] = sc;
+    scal[S_STOP] = tol2 * sc;
+    scal[S_BETA] = 0.0;
+    scal[S_ALPHA] = 0.0;
+    scal[S_IT] = 0.0;
+    scal[S_DONE] = sb <= tol2 * sc ? 1.0 : 0.0;
+  }
+}
+
+// The iteration's scalar recurrences, partials summed in a fixed order:
+// mode 0: p.q = sum a; alpha = r.z / p.q.
+// mode 1: r.z' = sum a, r.r = sum b; beta = r.z' / r.z; the iteration count;
+//         the stop flag when r.r <= tol^2 f.f.
+__global__ __launch_bounds__(PR) void poisson_reduce_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                                                            int nparts, int mode, double *__restrict__ scal) {
+  __shared__ double sh[PR];
+  if (scal[S_DONE] != 0) return;
+  double sa = 0, sb = 0;
+  for (int i = threadIdx.x; i < nparts; i += PR) {
+    sa += a[i];
+    if (mode == 1) sb += b[i];
+  }
+  sa = block_sum<PR>(sa, sh);
+  if (mode == 1) sb = block_sum<PR>(sb, sh);
   if (threadIdx.x == 0) {
     if (mode == 0) {
       scal[S_PQ] = sa;
       scal[S_ALPHA] = sa != 0 ? scal[S_RZ] / sa : 0.0;
-    } else if (mode == 1) {
+    } else {
       scal[S_BETA] = scal[S_RZ] != 0 ? sa / scal[S_RZ] : 0.0;
       scal[S_RZ] = sa;
       scal[S_RR] = sb;
-    } else {
-      scal[S_RZ] = sa;
-      scal[S_RR] = sb;
-      scal[S_FF] = sc;
+      scal[S_IT] += 1.0;
+      if (sb <= scal[S_STOP]) scal[S_DONE] = 1.0;
     }
   }
 }
@@ -323,18 +396,29 @@ static int poisson_ready(chfsi_ctx *c) {
 
 static const double kInv4Pi = 0.25 / 3.14159265358979323846;
 
+// stencil tile: rows per wave, planes per work-group, planes loaded ahead
+// (measured at the 143^3 and 159^3 interior meshes)
+constexpr int POIS_RY = 2, POIS_KB = 8, POIS_PD = 1;
+
 static dim3 apply_grid(int n) {
-  return dim3((unsigned)((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + KB - 1) / KB));
+  constexpr int TY = 4 * POIS_RY;
+  return dim3((unsigned)((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + POIS_KB - 1) / POIS_KB));
 }
 
-// y = A x (part: per-work-group x . y, when given); -1 for an unsupported degree
-static int poisson_apply_launch(const MeshTables &M, const double *x, double *y, const double *kb, const double *m,
-                                double *part, hipStream_t s) {
-  const dim3 g = apply_grid(M.n), b(PA);
+// y = A x; with part (and scal): the partials of x . y (skipped once the
+// stop flag in scal is up).  -1 for an unsupported degree.
+static int poisson_stencil_launch(const MeshTables &M, const double *x, double *y, const double *kb, const double *m,
+                                  const double *scal, double *part, hipStream_t s) {
+  const dim3 g = apply_grid(M.n), b(PB);
   switch (M.p) {
-#define CHFSI_POIS_P(P)                                                                                  \
-  case P:                                                                                                \
-    hipLaunchKernelGGL((poisson_apply_kernel<P>), g, b, 0, s, x, y, kb, m, M.n, kInv4Pi, part);          \
+#define CHFSI_POIS_P(P)                                                                                        \
+  case P:                                                                                                      \
+    if (part)                                                                                                  \
+      hipLaunchKernelGGL((poisson_stencil_kernel<P, POIS_RY, POIS_KB, POIS_PD, true>), g, b, 0, s, x, y, kb, m, M.n,       \
+                         kInv4Pi, scal, part);                                                                 \
+    else                                                                                                       \
+      hipLaunchKernelGGL((poisson_stencil_kernel<P, POIS_RY, POIS_KB, POIS_PD, false>), g, b, 0, s, x, y, kb, m, M.n,      \
+                         kInv4Pi, nullptr, nullptr);                                                           \
     return 0;
     CHFSI_POIS_P(1) CHFSI_POIS_P(2) CHFSI_POIS_P(3) CHFSI_POIS_P(4) CHFSI_POIS_P(5) CHFSI_POIS_P(6)
     CHFSI_POIS_P(7)
@@ -350,7 +434,8 @@ using namespace chfsi;
 extern "C" int chfsi_poisson_apply(chfsi_ctx *c, const double *x, double *y) {
   if (int r = poisson_ready(c)) return r;
   if (!x || !y || x == y) return fail(c, CHFSI_ERR_ARG, "poisson_apply: x and y must be separate device arrays");
-  if (poisson_apply_launch(c->mesh, x, y, c->pois_kb.as<double>(), c->pois_m.as<double>(), nullptr, c->stream))
+  if (poisson_stencil_launch(c->mesh, x, y, c->pois_kb.as<double>(), c->pois_m.as<double>(), nullptr, nullptr,
+                             c->stream))
     return fail(c, CHFSI_ERR_ARG, "poisson_apply: degree p must be in 1..7");
   HIPCHK(c, hipGetLastError());
   return 0;
@@ -400,41 +485,42 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
                        (int)qd.size());
     HIPCHK(c, hipStreamSynchronize(s));            // the host staging vectors go out of scope
   }
-  poisson_apply_launch(M, phi, q, kb, m, nullptr, s);
+  poisson_stencil_launch(M, phi, q, kb, m, nullptr, nullptr, s);
   hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
                      pc);
-  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, 2, scal);
+  hipLaunchKernelGGL(poisson_setup_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, tol * tol, scal);
+  // iterations in groups; the device counts them and stops itself, the host
+  // reads the flag between groups (a group started after the stop costs only
+  // its empty launches)
+  constexpr int GROUP = 8;
   double hs[S_NSCAL];
+  int launched = 0;
+  while (launched < max_iter) {
+    const int k = std::min(GROUP, max_iter - launched);
+    for (int i = 0; i < k; ++i, ++launched) {
+      poisson_stencil_launch(M, pv, q, kb, m, scal, pa, s);
+      hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, (int)na, 0, scal);
+      hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pa, pb);
+      hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, (int)nb, 1, scal);
+      hipLaunchKernelGGL(poisson_dir_kernel, grid, block, 0, s, pv, z, scal, nd);
+    }
+    HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (hs[S_DONE] != 0) break;
+  }
   HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  const double ff = hs[S_FF];
-  double rr = hs[S_RR];
-  int it = 0;
-  constexpr int CHECK = 4;                          // iterations between host reads of r.r
-  const double stop = tol * tol * ff;
-  while (rr > stop && it < max_iter) {
-    poisson_apply_launch(M, pv, q, kb, m, pa, s);
-    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)na, 0, scal);
-    hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pa, pb);
-    hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, 1, scal);
-    ++it;
-    if (it % CHECK == 0 || it == max_iter) {
-      HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      rr = hs[S_RR];
-      if (rr <= stop) break;
-    }
-    hipLaunchKernelGGL(poisson_dir_kernel, grid, block, 0, s, pv, z, scal, nd);
-  }
+  const int it = (int)hs[S_IT];
   // the true residual of the returned phi
-  poisson_apply_launch(M, phi, q, kb, m, nullptr, s);
+  poisson_stencil_launch(M, phi, q, kb, m, nullptr, nullptr, s);
   hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
                      pc);
-  hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, 2, scal);
+  hipLaunchKernelGGL(poisson_setup_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, tol * tol, scal);
   HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   HIPCHK(c, hipGetLastError());
   if (iters) *iters = it;
+  const double ff = hs[S_FF];
   const double res = ff > 0 ? std::sqrt(hs[S_RR] / ff) : 0.0;
   if (rel_resid) *rel_resid = res;
   return res <= tol ? 0 : CHFSI_WARN_NOT_CONVERGED;
