@@ -253,11 +253,12 @@ def served_stream(args):
 
 
 def time_to_solution(args, prob, bw):
-    os.environ.setdefault("CHFSI_VERBOSE", "1")   # the solve prints one line per pass
     """Wall time of chfsi_solve from the seeded start block until every wanted
     residual is <= tol (|Ritz value - exact eigenvalue| <= residual for a
-    symmetric operator), FP64 path vs the mixed path (FP32 filter falling back
-    to FP64 when the residual stalls, mixed-precision CholGS)."""
+    symmetric operator), FP64 path vs the mixed path (the filter precision
+    ladder, default BF16 -> FP32 -> FP64, each rung left when the residual
+    stalls or falls below its precision's floor; mixed-precision CholGS)."""
+    os.environ.setdefault("CHFSI_VERBOSE", "1")   # the solve prints one line per pass
     import numpy as np
     import torch
 

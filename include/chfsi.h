@@ -345,7 +345,8 @@ int chfsi_solve_complex(chfsi_ctx *ctx, const chfsi_opts *o, void *X, int64_t ld
  * ctxs[i] holds problem i's mesh and potential (one context per problem, all
  * on the same device; distinct streams let the per-problem CholGS/RR overlap).
  * Every problem uses the same Chebyshev degree; each follows its own ladder
- * of FP32/FP64 filter rungs (CholGS/RR are FP64).  Each pass runs one
+ * of BF16, BF16X3, FP32 and FP64 filter rungs (CholGS/RR are FP64; BF16 rungs
+ * need p <= 7, else CHFSI_ERR_ARG).  Each pass runs one
  * Chebyshev step of all active problems in shared launches (one per padded
  * cell size and colour) captured once per active set in a HIP graph, then
  * CholGS + RR per problem on host threads; a problem leaves the batch when its
@@ -364,12 +365,13 @@ int chfsi_solve_batch(chfsi_ctx *const *ctxs, int n, const chfsi_opts *opts, dou
  * block and host result arrays must stay valid until it leaves); it starts at
  * the next pass with CholGS + RR of its block (a warm start needs nothing
  * else).  chfsi_batch_pass runs one pass for every problem in the session:
- * a degree-m filter (problems on their FP32 rung share one graph-captured
- * sweep, problems on the FP64 rung another), then CholGS + RR per problem;
+ * a degree-m filter (problems on a BF16 or BF16X3 rung share one
+ * graph-captured sweep, problems on their FP32 rung another, problems on the
+ * FP64 rung a third), then CholGS + RR per problem;
  * problems whose wanted residuals are <= tol, or that reached max_iter, leave
  * and their ids are written to done_ids (at most max_done; the rest are
  * reported by later calls).  Each problem follows its own precision ladder
- * (FP32 and FP64 rungs only; rung thresholds as in chfsi_solve).
+ * (rung thresholds as in chfsi_solve).
  * A problem's results do not depend on which other problems share its passes.
  * A problem whose own step fails leaves the session with that status in its
  * report (rep.status < 0) and its id in done_ids, while the others go on:

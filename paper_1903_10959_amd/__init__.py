@@ -128,10 +128,31 @@ class BatchSession:
             out.append((pid, d))
         return rem, out
 
+    def run(self):
+        """Passes until no problem remains; returns {id: result dict} of every
+        problem that left during them."""
+        out = {}
+        while True:
+            rem, done = self.step()
+            out.update(done)
+            if rem == 0:
+                while True:                 # ids the last pass could not report at once
+                    rem, done = self.step()
+                    if not done:
+                        return out
+                    out.update(done)
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.chfsi_batch_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:
@@ -141,9 +162,11 @@ class BatchSession:
 
 
 def solve_batch(contexts, blocks, nstates, degree: int, tol: float, max_iter: int = 200, prec: str = "fp32",
-                mixed_cholgs: bool = False):
+                mixed_cholgs: bool = False, ladder=None):
     """chfsi_solve_batch over problems i (context contexts[i], block blocks[i],
-    nstates[i] wanted states).  Returns a list of per-problem result dicts."""
+    nstates[i] wanted states), every problem on the filter precision prec or,
+    when given, on the precision ladder (e.g. ("bf16", "fp32", "fp64")).
+    Returns a list of per-problem result dicts."""
     lib = _lib.load()
     n = len(contexts)
     if len(blocks) != n or len(nstates) != n:
@@ -159,7 +182,7 @@ def solve_batch(contexts, blocks, nstates, degree: int, tol: float, max_iter: in
     reps = (Report * n)()
     for i, (c, X, N) in enumerate(zip(contexts, blocks, nstates)):
         px, ld, nb = Context._block(X)
-        opts[i] = _opts(N, nb, degree, tol, max_iter, 0, (prec,), None, mixed_cholgs)
+        opts[i] = _opts(N, nb, degree, tol, max_iter, 0, tuple(ladder) if ladder else (prec,), None, mixed_cholgs)
         ctxs[i] = c._h.value
         xs[i] = px.value
         lds[i] = ld

@@ -1,8 +1,9 @@
 // Batched ChFSI over many independent problems (the paper's k-point groups,
 // placed on one device), as a session whose membership changes between passes
 // (continuous batching).  One Chebyshev step of every problem in a precision
-// group runs in shared launches, one per (padded cell size, colour), from a
-// device work list of (problem, cell, column tile) items.  The degree-m sweep
+// group (BF16 / BF16x3, FP32, FP64) runs in shared launches, one per (padded
+// cell size, colour), from a device work list of (problem, cell, column tile)
+// items.  The degree-m sweep
 // of a group is captured once per membership in a HIP graph and replayed each
 // pass; only the per-problem recursion coefficients change between passes and
 // are copied to the device before the replay.  CholGS and Rayleigh-Ritz run
@@ -70,9 +71,12 @@ int n_rungs(const Prob &p) { return std::max(1, std::min(p.o.n_ladder, 4)); }
 int mixed_now(const Prob &p) {
   return (p.o.mixed_cholgs && (p.o.n_ladder <= 1 || p.rung + 1 < n_rungs(p))) ? 1 : 0;
 }
+bool bf16_rung(const Prob &p) { return rung_prec(p) == CHFSI_BF16 || rung_prec(p) == CHFSI_BF16X3; }
 double rung_tol(const Prob &p) {
   if (p.o.ladder_tol[p.rung] > 0) return p.o.ladder_tol[p.rung];
-  return rung_prec(p) == CHFSI_FP32 ? 4.0 * 0x1p-24 * p.c->ub : 0.0;
+  const chfsi_prec pr = rung_prec(p);
+  const double u = pr == CHFSI_BF16 ? 0x1p-8 : pr == CHFSI_BF16X3 ? 0x1p-16 : pr == CHFSI_FP32 ? 0x1p-24 : 0.0;
+  return 4.0 * u * p.c->ub;
 }
 double max_wanted(const Prob &p) {
   double m = 0;
@@ -101,7 +105,7 @@ void roles(int degree, std::vector<int> &cur, std::vector<int> &prev, std::vecto
 template <typename T>
 struct Sweep {
   DevBuf probs, work, coef;
-  std::vector<int> members;      // problem ids of the captured graph
+  std::vector<int> members;      // problem ids of the captured graph (BF16: 2 id + split)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<T> hcoef;
@@ -131,6 +135,7 @@ struct chfsi_batch {
   std::deque<int> finished;      // ids that left and are not reported yet
   Sweep<double> s64;
   Sweep<float> s32;
+  Sweep<float> sbf;              // BF16 and BF16x3 rungs (FP32 recursion state)
   bool verbose = false;
   int threads = 8;               // host threads for the per-problem CholGS / Rayleigh-Ritz
   // shared Jacobi eigensolve of the projected Hamiltonians
@@ -182,7 +187,7 @@ std::vector<std::vector<int>> stream_groups(chfsi_batch *B, const std::vector<in
   } while (0)
 
 template <typename T>
-int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
+int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, const std::vector<int> &key) {
   S.drop_graph();
   if (ids.empty()) return 0;
   const bool f64 = sizeof(T) == 8;
@@ -270,17 +275,110 @@ int build_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids) {
   if (ce != hipSuccess) return bfail(B, CHFSI_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
   if (lerr) return bfail(B, CHFSI_ERR_ARG, "batch: no cell kernel for a problem's degree");
   BCHK(B, hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
-  S.members = ids;
+  S.members = key;
   return 0;
 }
 
+// The BF16 sweep: BF16 (or hi/lo split) cell products on FP32 recursion
+// state, one launch per (padded size, split, colour) and step; one cell x 64
+// columns per work item.
+int build_sweep_bf16(chfsi_batch *B, Sweep<float> &S, const std::vector<int> &ids, const std::vector<int> &key) {
+  S.drop_graph();
+  if (ids.empty()) return 0;
+  constexpr int TWB = 64;
+  std::vector<BatchProblemBf16> hp;
+  // (npb, split, colour) -> work items
+  std::map<std::tuple<int, int, int>, std::vector<int4>> lists;
+  for (size_t m = 0; m < ids.size(); ++m) {
+    Prob &p = B->probs[ids[m]];
+    chfsi_ctx *c = p.c;
+    const int nb = p.o.nblock;
+    if (c->npb <= 0) return bfail(B, CHFSI_ERR_ARG, "batch: no BF16 cell kernel for a problem's degree");
+    BatchProblemBf16 P;
+    for (int k = 0; k < 3; ++k) {
+      P.buf[k] = c->fbuf[k].as<float>();
+      P.ld[k] = nb;
+    }
+    P.Kh = c->Kbh.as<const __bf16>();
+    P.Kl = c->Kbl.as<const __bf16>();
+    P.cmap = c->cmap.as<int32_t>();
+    P.cells = c->cells.as<int32_t>();
+    P.minv = c->minv32.as<float>();
+    P.V = c->V32.as<float>();
+    P.coef = nullptr;
+    P.n_loc = c->mesh.n_loc;
+    P.q = c->mesh.q;
+    P.n_el = c->mesh.n_el;
+    P.ncols = nb;
+    hp.push_back(P);
+    const int split = rung_prec(p) == CHFSI_BF16X3 ? 1 : 0;
+    const int ntiles = (nb + TWB - 1) / TWB;
+    for (int col = 0; col < 8; ++col)
+      for (int e = c->mesh.color_offset[col]; e < c->mesh.color_offset[col + 1]; ++e)
+        for (int t = 0; t < ntiles; ++t) lists[{c->npb, split, col}].push_back(make_int4((int)m, e, t, 1));
+  }
+  BCHK(B, S.coef.ensure((size_t)3 * B->degree * ids.size() * sizeof(float)));
+  for (size_t m = 0; m < hp.size(); ++m) hp[m].coef = S.coef.as<float>() + (size_t)3 * B->degree * m;
+  std::vector<int4> all;
+  std::vector<std::tuple<int, int, int>> groups;  // (npb, split, offset)
+  std::vector<int> counts;
+  for (int col = 0; col < 8; ++col)
+    for (auto &kv : lists)
+      if (std::get<2>(kv.first) == col) {
+        groups.push_back({std::get<0>(kv.first), std::get<1>(kv.first), (int)all.size()});
+        counts.push_back((int)kv.second.size());
+        all.insert(all.end(), kv.second.begin(), kv.second.end());
+      }
+  BCHK(B, S.probs.ensure(hp.size() * sizeof(BatchProblemBf16)));
+  BCHK(B, S.work.ensure(all.size() * sizeof(int4)));
+  BCHK(B, hipMemcpyAsync(S.probs.p, hp.data(), hp.size() * sizeof(BatchProblemBf16), hipMemcpyHostToDevice,
+                         B->stream));
+  BCHK(B, hipMemcpyAsync(S.work.p, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, B->stream));
+  BCHK(B, hipStreamSynchronize(B->stream));
+  std::vector<int> cur, prev, out;
+  int final_buf = 0;
+  roles(B->degree, cur, prev, out, final_buf);
+  BCHK(B, hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+  for (int id : ids) {
+    Prob &p = B->probs[id];
+    copy_cols_launch<double, float>(p.X, p.ld, p.c->fbuf[0].as<float>(), p.o.nblock, p.c->mesh.n_dof, p.o.nblock,
+                                    B->stream);
+  }
+  int lerr = 0;
+  for (int k = 0; k < B->degree; ++k)
+    for (size_t g = 0; g < groups.size(); ++g)
+      lerr |= hx_cells_bf16_batch_launch(std::get<0>(groups[g]), std::get<1>(groups[g]),
+                                         S.probs.as<BatchProblemBf16>(), S.work.as<int4>() + std::get<2>(groups[g]),
+                                         counts[g], k, cur[k], prev[k], out[k], B->stream);
+  for (size_t m = 0; m < ids.size(); ++m) {
+    Prob &p = B->probs[ids[m]];
+    copy_cols_launch<float, double>((const float *)hp[m].buf[final_buf], hp[m].ld[final_buf], p.X, p.ld,
+                                    p.c->mesh.n_dof, p.o.nblock, B->stream);
+  }
+  hipError_t ce = hipStreamEndCapture(B->stream, &S.graph);
+  if (ce != hipSuccess) return bfail(B, CHFSI_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  if (lerr) return bfail(B, CHFSI_ERR_ARG, "batch: no BF16 cell kernel for a problem's degree");
+  BCHK(B, hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
+  S.members = key;
+  return 0;
+}
+
+// One pass of a precision group's sweep: (re)captures the graph when the
+// membership (for the BF16 group: with each member's split) changed, then
+// uploads the recursion coefficients and replays it.
 template <typename T>
-int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *ms_out) {
+int run_sweep(chfsi_batch *B, Sweep<T> &S, const std::vector<int> &ids, float *ms_out, bool bf16 = false) {
   *ms_out = 0;
   if (ids.empty()) return 0;
-  if (ids != S.members) {
+  std::vector<int> key(ids);
+  if (bf16)
+    for (size_t m = 0; m < ids.size(); ++m) key[m] = 2 * ids[m] + (rung_prec(B->probs[ids[m]]) == CHFSI_BF16X3);
+  if (key != S.members) {
     const auto t0 = std::chrono::steady_clock::now();
-    if (int r = build_sweep<T>(B, S, ids)) return r;
+    int r;
+    if constexpr (sizeof(T) == 4) r = bf16 ? build_sweep_bf16(B, S, ids, key) : build_sweep<T>(B, S, ids, key);
+    else r = build_sweep<T>(B, S, ids, key);
+    if (r) return r;
     B->build_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   const int m_deg = B->degree;
@@ -416,6 +514,7 @@ extern "C" int chfsi_batch_destroy(chfsi_batch *b) {
   (void)hipStreamSynchronize(b->stream);
   b->s64.release();
   b->s32.release();
+  b->sbf.release();
   b->jac_table.release();
   b->jac_norms.release();
   (void)hipStreamDestroy(b->stream);
@@ -437,12 +536,15 @@ extern "C" int chfsi_batch_add(chfsi_batch *b, chfsi_ctx *c, const chfsi_opts *o
   if (o->degree != b->degree) return bfail(b, CHFSI_ERR_ARG, "batch: every problem needs the session's degree");
   for (int k = 0; k < std::max(1, std::min(o->n_ladder, 4)); ++k) {
     const chfsi_prec pr = o->n_ladder > 0 ? o->ladder[k] : CHFSI_FP64;
-    if (pr != CHFSI_FP64 && pr != CHFSI_FP32) return bfail(b, CHFSI_ERR_ARG, "batch: ladder rungs must be FP32/FP64");
+    if (pr != CHFSI_FP64 && pr != CHFSI_FP32 && pr != CHFSI_BF16 && pr != CHFSI_BF16X3)
+      return bfail(b, CHFSI_ERR_ARG, "batch: unknown ladder precision");
+    if ((pr == CHFSI_BF16 || pr == CHFSI_BF16X3) && c->npb <= 0)
+      return bfail(b, CHFSI_ERR_ARG, "batch: BF16 rungs need degree p <= 7");
   }
   for (const Prob &p : b->probs)
     if (!p.done && p.c == c) return bfail(b, CHFSI_ERR_ARG, "batch: the context is already in the session");
   if (int r = ensure_small(c, o->nblock)) return bfail(b, r, "batch: " + c->err);
-  const size_t bytes = (size_t)c->mesh.n_dof * o->nblock * sizeof(double);  // FP64 or FP32 rungs
+  const size_t bytes = (size_t)c->mesh.n_dof * o->nblock * sizeof(double);  // FP64-sized for any rung
   for (int k = 0; k < 3; ++k)
     if (c->fbuf[k].ensure(bytes) != hipSuccess) return bfail(b, CHFSI_ERR_OOM, "batch: filter buffers");
   if (c->HX.ensure(bytes) != hipSuccess) return bfail(b, CHFSI_ERR_OOM, "batch: HX buffer");
@@ -480,7 +582,7 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
   }
   // 2. filter sweeps, one per precision group; a problem whose Ritz values do
   // not give valid filter bounds (a0 < a < b) leaves with CHFSI_ERR_NONFINITE
-  std::vector<int> g32, g64;
+  std::vector<int> gbf, g32, g64;
   for (Prob &p : b->probs) {
     if (p.done) continue;
     const int nb = p.o.nblock;
@@ -489,20 +591,21 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
       finish_prob(b, p, CHFSI_ERR_NONFINITE);
       continue;
     }
-    (rung_prec(p) == CHFSI_FP32 ? g32 : g64).push_back(p.id);
+    (bf16_rung(p) ? gbf : rung_prec(p) == CHFSI_FP32 ? g32 : g64).push_back(p.id);
   }
-  float ms32 = 0, ms64 = 0;
+  float msbf = 0, ms32 = 0, ms64 = 0;
   b->build_ms = 0;
   const auto t_sw = std::chrono::steady_clock::now();
+  if (int r = run_sweep<float>(b, b->sbf, gbf, &msbf, true)) return r;
   if (int r = run_sweep<float>(b, b->s32, g32, &ms32)) return r;
   if (int r = run_sweep<double>(b, b->s64, g64, &ms64)) return r;
   // 3. CholGS + RR of every swept problem
-  std::vector<int> swept(g32);
+  std::vector<int> swept(gbf);
+  swept.insert(swept.end(), g32.begin(), g32.end());
   swept.insert(swept.end(), g64.begin(), g64.end());
   for (int id : swept) {
     Prob &p = b->probs[id];
-    const bool f32 = rung_prec(p) == CHFSI_FP32;
-    p.rep.t_filter += (f32 ? ms32 : ms64) * 1e-3;
+    p.rep.t_filter += (bf16_rung(p) ? msbf : rung_prec(p) == CHFSI_FP32 ? ms32 : ms64) * 1e-3;
     p.rep.dofvecs += p.c->mesh.n_dof * (int64_t)p.o.nblock * b->degree;
   }
   const auto t_ss = std::chrono::steady_clock::now();
@@ -519,9 +622,9 @@ extern "C" int chfsi_batch_pass(chfsi_batch *b, int *done_ids, int *n_done, int 
     double worst = 0;
     for (int id : swept) worst = std::max(worst, b->probs[id].res);
     std::fprintf(stderr,
-                 "[chfsi] batch pass: %zu FP32 + %zu FP64 problems swept (%.2f + %.2f ms on the device, %.2f ms wall "
-                 "incl. %.2f ms graph builds), CholGS/RR %.2f ms, %d remain, max residual %.3e\n",
-                 g32.size(), g64.size(), ms32, ms64,
+                 "[chfsi] batch pass: %zu BF16 + %zu FP32 + %zu FP64 problems swept (%.2f + %.2f + %.2f ms on the "
+                 "device, %.2f ms wall incl. %.2f ms graph builds), CholGS/RR %.2f ms, %d remain, max residual %.3e\n",
+                 gbf.size(), g32.size(), g64.size(), msbf, ms32, ms64,
                  std::chrono::duration<double, std::milli>(t_ss - t_sw).count(), b->build_ms,
                  std::chrono::duration<double, std::milli>(t_end - t_ss).count(), remaining, worst);
     std::fflush(stderr);

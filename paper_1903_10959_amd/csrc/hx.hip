@@ -507,17 +507,14 @@ int hx_rows_padded(int n_loc) { return (n_loc + RT_NR - 1) / RT_NR * RT_NR; }
 // (two blocks: every K fragment feeds two MFMAs; one block: half the LDS per
 // work-group, so more work-groups share a CU and overlap their gathers and
 // epilogues).
+// One work-group = one cell e x TWB columns from tile * TWB.
 template <int NPB, bool SPLIT, int CBW = 2, int EPD = 2>
-__global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
-                                                            const float *__restrict__ Xp, int64_t ldp,
-                                                            float *__restrict__ Y, int64_t ldy,
-                                                            const __bf16 *__restrict__ Kh,
-                                                            const __bf16 *__restrict__ Kl,
-                                                            const int32_t *__restrict__ cmap, int n_loc, int q,
-                                                            int n_el, const int32_t *__restrict__ cells,
-                                                            const float *__restrict__ minv,
-                                                            const float *__restrict__ V, int ncols, int ntiles,
-                                                            float s1, float s2, float shift) {
+__device__ __forceinline__ void bf16_tile(const float *__restrict__ X, int64_t ldx, const float *__restrict__ Xp,
+                                          int64_t ldp, float *__restrict__ Y, int64_t ldy,
+                                          const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
+                                          const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, int e,
+                                          int tile, const float *__restrict__ minv, const float *__restrict__ V,
+                                          int ncols, float s1, float s2, float shift) {
   constexpr int RB = NPB / 16;
   constexpr int LDX = NPB + 8;            // row of the transposed tile, 16-byte aligned
   constexpr int NPART = SPLIT ? 2 : 1;
@@ -530,9 +527,6 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
   __shared__ __attribute__((aligned(16))) __bf16 xs[NPART][TWB * LDX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int cell_slot = blockIdx.x / ntiles;
-  const int tile = blockIdx.x - cell_slot * ntiles;
-  const int e = cells[cell_slot];
   const int col0 = tile * TWB;
   for (int r = threadIdx.x; r < NPB; r += blockDim.x) {
     int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
@@ -657,6 +651,38 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restr
 }
 
 template <int NPB, bool SPLIT, int CBW>
+__global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
+                                                            const float *__restrict__ Xp, int64_t ldp,
+                                                            float *__restrict__ Y, int64_t ldy,
+                                                            const __bf16 *__restrict__ Kh,
+                                                            const __bf16 *__restrict__ Kl,
+                                                            const int32_t *__restrict__ cmap, int n_loc, int q,
+                                                            int n_el, const int32_t *__restrict__ cells,
+                                                            const float *__restrict__ minv,
+                                                            const float *__restrict__ V, int ncols, int ntiles,
+                                                            float s1, float s2, float shift) {
+  const int cell_slot = blockIdx.x / ntiles;
+  const int tile = blockIdx.x - cell_slot * ntiles;
+  bf16_tile<NPB, SPLIT, CBW>(X, ldx, Xp, ldp, Y, ldy, Kh, Kl, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V,
+                             ncols, s1, s2, shift);
+}
+
+// Batched: work item = (problem, cell position in the problem's colour-sorted
+// list, column tile); the step's buffer roles are shared, the coefficients
+// come from the problem's table (s1, s2, shift per step).
+template <int NPB, bool SPLIT>
+__global__ __launch_bounds__(256) void hx_cells_bf16_batch_kernel(const BatchProblemBf16 *__restrict__ probs,
+                                                                  const int4 *__restrict__ work, int step, int cur,
+                                                                  int prev, int out) {
+  const int4 w = work[blockIdx.x];
+  const BatchProblemBf16 &P = probs[w.x];
+  const float *coef = P.coef + 3 * step;
+  bf16_tile<NPB, SPLIT, 2>(P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
+                           P.buf[out], P.ld[out], P.Kh, P.Kl, P.cmap, P.n_loc, P.q, P.n_el, P.cells[w.y], w.z,
+                           P.minv, P.V, P.ncols, coef[0], coef[1], coef[2]);
+}
+
+template <int NPB, bool SPLIT, int CBW>
 static void launch_bf16(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
   constexpr int TWB = 32 * CBW;
   int ntiles = (a.ncols + TWB - 1) / TWB;
@@ -688,6 +714,29 @@ static int dispatch_bf16(const HxBf16Args &a, int cb, int ce, hipStream_t s) {
 
 int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
   return a.split ? dispatch_bf16<true>(a, color_begin, color_end, s) : dispatch_bf16<false>(a, color_begin, color_end, s);
+}
+
+template <bool SPLIT>
+static int bf16_batch_dispatch(int npb, const BatchProblemBf16 *probs, const int4 *work, int nwork, int step, int cur,
+                               int prev, int out, hipStream_t s) {
+  const dim3 g((unsigned)nwork), b(256);
+  switch (npb) {
+#define CHFSI_BF16_BATCH(NPB)                                                                                   \
+  case NPB:                                                                                                     \
+    hipLaunchKernelGGL((hx_cells_bf16_batch_kernel<NPB, SPLIT>), g, b, 0, s, probs, work, step, cur, prev, out); \
+    return 0;
+    CHFSI_BF16_BATCH(32) CHFSI_BF16_BATCH(64) CHFSI_BF16_BATCH(128) CHFSI_BF16_BATCH(224) CHFSI_BF16_BATCH(352)
+    CHFSI_BF16_BATCH(512)
+#undef CHFSI_BF16_BATCH
+    default: return -1;
+  }
+}
+
+int hx_cells_bf16_batch_launch(int npb, int split, const BatchProblemBf16 *probs, const int4 *work, int nwork,
+                               int step, int cur, int prev, int out, hipStream_t s) {
+  if (nwork <= 0) return 0;
+  return split ? bf16_batch_dispatch<true>(npb, probs, work, nwork, step, cur, prev, out, s)
+               : bf16_batch_dispatch<false>(npb, probs, work, nwork, step, cur, prev, out, s);
 }
 
 // Tile configurations per padded cell size: waves per work-group, the split

@@ -93,6 +93,20 @@ struct HxBf16Args {
   int cbw = 2;         // 16-column blocks per wave: 2 (64-column tiles) or 1 (32-column tiles)
 };
 int hx_cells_bf16_launch(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s);
+// One problem of a batched BF16 sweep: its three recursion buffers (FP32), the
+// BF16 hi/lo cell matrix (npb x npb), maps and per-step coefficients.
+struct BatchProblemBf16 {
+  float *buf[3];
+  int64_t ld[3];
+  const __bf16 *Kh, *Kl;
+  const int32_t *cmap, *cells;
+  const float *minv, *V, *coef;
+  int n_loc, q, n_el, ncols;
+};
+// work items (problem, cell position, 64-column tile, unused) of one padded
+// size npb (32 .. 512) and one colour; -1 for an unsupported npb
+int hx_cells_bf16_batch_launch(int npb, int split, const BatchProblemBf16 *probs, const int4 *work, int nwork,
+                               int step, int cur, int prev, int out, hipStream_t s);
 template <typename Tin, typename Tout>
 void copy_cols_launch(const Tin *in, int64_t ldi, Tout *out, int64_t ldo, int64_t nrows, int ncols,
                       hipStream_t s);

@@ -48,6 +48,62 @@ def test_batch_fp64_equals_single_solves_and_dense_eigh():
         p["ctx_single"].close()
 
 
+def test_batch_bf16_ladder_equals_single_solves_and_dense_eigh():
+    """Problems on the BF16 -> FP32 -> FP64 ladder share the batched BF16
+    sweep: each result is bitwise the single-context solve on the same ladder
+    (the same kernel arithmetic, coefficients and rung switches) and its
+    eigenvalues match the dense eigensolve to 1e-10 relative."""
+    import paper_1903_10959_amd as P
+    probs = _problems()
+    lad = ("bf16", "fp32", "fp64")
+    Xb = [to_gpu(p["X0"]) for p in probs]
+    res = P.solve_batch([p["ctx"] for p in probs], Xb, [p["N"] for p in probs], 20, 1e-9, max_iter=300,
+                        ladder=lad)
+    for p, r, X in zip(probs, res, Xb):
+        assert r["converged"], r
+        N = p["N"]
+        err = np.abs(r["evals"][:N] - p["ev"][:N]) / np.maximum(np.abs(p["ev"][:N]), 1.0)
+        assert np.max(err) < 1e-10
+        Xs = to_gpu(p["X0"])
+        s = p["ctx_single"].solve(Xs, N, 20, 1e-9, max_iter=300, block_width=p["nb"], ladder=lad)
+        assert s["iters"] == r["iters"]
+        np.testing.assert_array_equal(s["evals"], r["evals"])
+        np.testing.assert_array_equal(to_host(Xs), to_host(X))
+    for p in probs:
+        p["ctx"].close()
+        p["ctx_single"].close()
+
+
+def test_session_mixes_bf16_and_bf16x3_rungs():
+    """One session with half of the problems on BF16X3 -> FP64 and half on
+    BF16 -> FP32 -> FP64 (so both BF16 kernels and the FP32 and FP64 sweeps
+    run in the same passes): every problem converges to the dense eigenvalues,
+    bitwise as when it runs alone in a session."""
+    import paper_1903_10959_amd as P
+    probs = _problems()
+    lads = [("bf16x3", "fp64") if i % 2 else ("bf16", "fp32", "fp64") for i in range(len(probs))]
+    Xm = [to_gpu(p["X0"]) for p in probs]
+    with P.BatchSession(0) as sess:
+        ids = [sess.add(p["ctx"], X, p["N"], 20, 1e-9, max_iter=300, ladder=lad) for p, X, lad in zip(probs, Xm, lads)]
+        mixed = sess.run()
+    for i, (p, lad) in enumerate(zip(probs, lads)):
+        r = mixed[ids[i]]
+        assert r["converged"], r
+        N = p["N"]
+        err = np.abs(r["evals"][:N] - p["ev"][:N]) / np.maximum(np.abs(p["ev"][:N]), 1.0)
+        assert np.max(err) < 1e-10
+        Xa = to_gpu(p["X0"])
+        with P.BatchSession(0) as alone:
+            aid = alone.add(p["ctx_single"], Xa, N, 20, 1e-9, max_iter=300, ladder=lad)
+            ra = alone.run()[aid]
+        assert ra["iters"] == r["iters"]
+        np.testing.assert_array_equal(ra["evals"], r["evals"])
+        np.testing.assert_array_equal(to_host(Xa), to_host(Xm[i]))
+    for p in probs:
+        p["ctx"].close()
+        p["ctx_single"].close()
+
+
 def test_batch_fp32_filter_within_its_floor():
     import paper_1903_10959_amd as P
     probs = _problems()

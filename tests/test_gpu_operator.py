@@ -203,3 +203,49 @@ def test_cells_per_tile_settings_match_oracle(n_el, p, cpt):
     c.chebyshev_filter(B, 3, 0.5 * b, b, -1.0)
     np.testing.assert_array_equal(to_host(A), to_host(B))
     c.close()
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7])
+def test_single_cell_mesh(p):
+    """One cell (n_el = 1: colour 0 holds the only cell, colours 1..7 are
+    empty launches) with (p - 1)^3 interior DoFs: the product against the
+    oracle in FP64, FP32 and BF16, and at p = 4 the full solve against the dense
+    eigensolve."""
+    L = 3.0
+    c, V = make_ctx(L, 1, p, wells=workload.draw_wells(1, L, 70 + p, (1.0, 2.0), (0.4, 0.5)))
+    ncols = 5
+    X = workload.start_block(c.n_dof, ncols, 70 + p)
+    Yo = oracle_apply(L, 1, p, V)(X)
+    assert _rel(to_host(c.apply(to_gpu(X))), Yo) < 1e-13
+    # reduced formats per output against (k u + n_loc u32) (|H||x|): the kinetic
+    # and potential parts cancel in part, so a relative max-norm would not bound them
+    HabsX = fem.apply_kron(np.abs(fem.operator_1d(L, 1, p)), np.abs(V), np.abs(X))
+    n_loc = (p + 1) ** 3
+    for prec, u in (("fp32", 2.0 ** -24), ("bf16", 2.0 ** -8), ("bf16x3", 2.0 ** -16)):
+        err = np.abs(to_host(c.apply(to_gpu(X), prec=prec)) - Yo)
+        assert np.all(err <= (3.0 * u + n_loc * 2.0 ** -24) * HabsX), prec
+    if p == 4:
+        ev = np.linalg.eigvalsh(fem.htilde_csr(L, 1, p, V).toarray())
+        Xs = to_gpu(workload.start_block(c.n_dof, 8, 7))
+        out = c.solve(Xs, 4, 10, 1e-10, max_iter=200)
+        assert out["converged"], out
+        np.testing.assert_allclose(out["evals"][:4], ev[:4], rtol=0, atol=1e-10 * max(1.0, abs(ev[0])))
+    c.close()
+
+
+def test_empty_and_malformed_blocks_are_rejected():
+    """ncols < 1, ld < ncols and null pointers return CHFSI_ERR_ARG before any
+    launch; the context stays usable."""
+    import ctypes
+    import torch
+    prob = workload.PROBLEMS["small"]
+    c, V = make_ctx(prob.L, prob.n_el, prob.p, wells=workload.problem_wells(prob))
+    X = torch.zeros((c.n_dof, 4), dtype=torch.float64, device="cuda:0")
+    Y = torch.zeros_like(X)
+    px, py = ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr())
+    assert c._lib.chfsi_apply(c._h, px, py, 4, 0, 0) == -1          # ncols = 0
+    assert c._lib.chfsi_apply(c._h, px, py, 3, 4, 0) == -1          # ld < ncols
+    assert c._lib.chfsi_apply(c._h, None, py, 4, 4, 0) == -1        # null input
+    Xr = workload.start_block(c.n_dof, 4, 3)
+    assert _rel(to_host(c.apply(to_gpu(Xr))), oracle_apply(prob.L, prob.n_el, prob.p, V)(Xr)) < 1e-13
+    c.close()
