@@ -543,7 +543,8 @@ def kpoint_bench(args, prob):
            "config": {"workload": f"periodic [0,{prob.L})^3, {prob.n_el}^3 cells, p={prob.p}, {ctx.n_dof} DoFs, "
                                   f"k={list(k)}, {nc} complex vectors", "steps": args.steps},
            "roofline": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6,
-                        "traffic": None, "kernel": "hx_cells_cplx_kernel", "avg_apply_ms": ms,
+                        "traffic": profiled_traffic(f"hx_cells_cplx_periodic_p{prob.p}"),
+                        "kernel": "hx_cells_cplx_kernel", "avg_apply_ms": ms, "launches_per_apply": 8,
                         "flop_per_cell_complex_vec": 8 * ctx.n_loc ** 2},
            "kpoint_group": {"mesh": f"periodic [0,{Lg})^3, {neg}^3 cells, p={pg}", "nk": len(kk),
                             "complex_vectors_per_k": nc, "ms_group": ms_group, "ms_one_context_per_k": ms_single,

@@ -507,14 +507,78 @@ int hx_rows_padded(int n_loc) { return (n_loc + RT_NR - 1) / RT_NR * RT_NR; }
 // (two blocks: every K fragment feeds two MFMAs; one block: half the LDS per
 // work-group, so more work-groups share a CU and overlap their gathers and
 // epilogues).
+// One kernel for both launch forms, so that the tile body sits directly in
+// the kernel (the same body inlined from a device function gets a register
+// allocation of up to 296 per lane at p = 6 and one wave per SIMD):
+//  * single problem: work-group = (cell of the colour list, column tile),
+//    operands from the kernel arguments;
+//  * BATCH: work item (problem, cell position in the problem's colour-sorted
+//    list, column tile) from a device list, operands from the problem's
+//    descriptor, coefficients from its table (s1, s2, shift per step).
 // One work-group = one cell e x TWB columns from tile * TWB.
-template <int NPB, bool SPLIT, int CBW = 2, int EPD = 2>
-__device__ __forceinline__ void bf16_tile(const float *__restrict__ X, int64_t ldx, const float *__restrict__ Xp,
-                                          int64_t ldp, float *__restrict__ Y, int64_t ldy,
-                                          const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
-                                          const int32_t *__restrict__ cmap, int n_loc, int q, int n_el, int e,
-                                          int tile, const float *__restrict__ minv, const float *__restrict__ V,
-                                          int ncols, float s1, float s2, float shift) {
+template <int NPB, bool SPLIT, int CBW, bool BATCH>
+__global__ __launch_bounds__(256) void hx_cells_bf16_kernel(
+    const float *__restrict__ X_, int64_t ldx_, const float *__restrict__ Xp_, int64_t ldp_, float *__restrict__ Y_,
+    int64_t ldy_, const __bf16 *__restrict__ Kh_, const __bf16 *__restrict__ Kl_, const int32_t *__restrict__ cmap_,
+    int n_loc_, int q_, int n_el_, const int32_t *__restrict__ cells_, const float *__restrict__ minv_,
+    const float *__restrict__ V_, int ncols_, int ntiles, float s1_, float s2_, float shift_,
+    const BatchProblemBf16 *__restrict__ probs, const int4 *__restrict__ work, int step, int cur, int prev, int out) {
+  const float *X, *Xp, *minv, *V;
+  float *Y;
+  int64_t ldx, ldp, ldy;
+  const __bf16 *Kh, *Kl;
+  const int32_t *cmap;
+  int n_loc, q, n_el, ncols, e, tile;
+  float s1, s2, shift;
+  if constexpr (BATCH) {
+    const int4 w = work[blockIdx.x];
+    const BatchProblemBf16 &P = probs[w.x];
+    const float *coef = P.coef + 3 * step;
+    X = P.buf[cur];
+    ldx = P.ld[cur];
+    Xp = prev >= 0 ? P.buf[prev] : nullptr;
+    ldp = prev >= 0 ? P.ld[prev] : 0;
+    Y = P.buf[out];
+    ldy = P.ld[out];
+    Kh = P.Kh;
+    Kl = P.Kl;
+    cmap = P.cmap;
+    n_loc = P.n_loc;
+    q = P.q;
+    n_el = P.n_el;
+    minv = P.minv;
+    V = P.V;
+    ncols = P.ncols;
+    e = P.cells[w.y];
+    tile = w.z;
+    s1 = coef[0];
+    s2 = coef[1];
+    shift = coef[2];
+  } else {
+    X = X_;
+    ldx = ldx_;
+    Xp = Xp_;
+    ldp = ldp_;
+    Y = Y_;
+    ldy = ldy_;
+    Kh = Kh_;
+    Kl = Kl_;
+    cmap = cmap_;
+    n_loc = n_loc_;
+    q = q_;
+    n_el = n_el_;
+    minv = minv_;
+    V = V_;
+    ncols = ncols_;
+    const int cell_slot = blockIdx.x / ntiles;
+    tile = blockIdx.x - cell_slot * ntiles;
+    e = cells_[cell_slot];
+    s1 = s1_;
+    s2 = s2_;
+    shift = shift_;
+  }
+  constexpr int EPD = 2;                   // epilogue fragments in flight (3 measured no faster)
+
   constexpr int RB = NPB / 16;
   constexpr int LDX = NPB + 8;            // row of the transposed tile, 16-byte aligned
   constexpr int NPART = SPLIT ? 2 : 1;
@@ -523,11 +587,11 @@ __device__ __forceinline__ void bf16_tile(const float *__restrict__ X, int64_t l
   __shared__ float vd_s[NPB];
   __shared__ int8_t ft_s[NPB];
   constexpr int TWB = 32 * CBW;          // columns per work-group
+  const int col0 = tile * TWB;
   constexpr int NG4 = TWB / 4;            // groups of four columns
   __shared__ __attribute__((aligned(16))) __bf16 xs[NPART][TWB * LDX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int col0 = tile * TWB;
   for (int r = threadIdx.x; r < NPB; r += blockDim.x) {
     int d = r < n_loc ? cmap[(int64_t)e * n_loc + r] : -1;
     dof_s[r] = d < 0 ? 0 : d;
@@ -651,46 +715,15 @@ __device__ __forceinline__ void bf16_tile(const float *__restrict__ X, int64_t l
 }
 
 template <int NPB, bool SPLIT, int CBW>
-__global__ __launch_bounds__(256) void hx_cells_bf16_kernel(const float *__restrict__ X, int64_t ldx,
-                                                            const float *__restrict__ Xp, int64_t ldp,
-                                                            float *__restrict__ Y, int64_t ldy,
-                                                            const __bf16 *__restrict__ Kh,
-                                                            const __bf16 *__restrict__ Kl,
-                                                            const int32_t *__restrict__ cmap, int n_loc, int q,
-                                                            int n_el, const int32_t *__restrict__ cells,
-                                                            const float *__restrict__ minv,
-                                                            const float *__restrict__ V, int ncols, int ntiles,
-                                                            float s1, float s2, float shift) {
-  const int cell_slot = blockIdx.x / ntiles;
-  const int tile = blockIdx.x - cell_slot * ntiles;
-  bf16_tile<NPB, SPLIT, CBW>(X, ldx, Xp, ldp, Y, ldy, Kh, Kl, cmap, n_loc, q, n_el, cells[cell_slot], tile, minv, V,
-                             ncols, s1, s2, shift);
-}
-
-// Batched: work item = (problem, cell position in the problem's colour-sorted
-// list, column tile); the step's buffer roles are shared, the coefficients
-// come from the problem's table (s1, s2, shift per step).
-template <int NPB, bool SPLIT>
-__global__ __launch_bounds__(256) void hx_cells_bf16_batch_kernel(const BatchProblemBf16 *__restrict__ probs,
-                                                                  const int4 *__restrict__ work, int step, int cur,
-                                                                  int prev, int out) {
-  const int4 w = work[blockIdx.x];
-  const BatchProblemBf16 &P = probs[w.x];
-  const float *coef = P.coef + 3 * step;
-  bf16_tile<NPB, SPLIT, 2>(P.buf[cur], P.ld[cur], prev >= 0 ? P.buf[prev] : nullptr, prev >= 0 ? P.ld[prev] : 0,
-                           P.buf[out], P.ld[out], P.Kh, P.Kl, P.cmap, P.n_loc, P.q, P.n_el, P.cells[w.y], w.z,
-                           P.minv, P.V, P.ncols, coef[0], coef[1], coef[2]);
-}
-
-template <int NPB, bool SPLIT, int CBW>
 static void launch_bf16(const HxBf16Args &a, int color_begin, int color_end, hipStream_t s) {
   constexpr int TWB = 32 * CBW;
   int ntiles = (a.ncols + TWB - 1) / TWB;
   int ncell = color_end - color_begin;
   if (ncell <= 0 || ntiles <= 0) return;
-  hipLaunchKernelGGL((hx_cells_bf16_kernel<NPB, SPLIT, CBW>), dim3((unsigned)(ncell * ntiles)), dim3(256), 0, s, a.X,
-                     a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.Kh, a.Kl, a.cmap, a.n_loc, a.q, a.n_el,
-                     a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift);
+  hipLaunchKernelGGL((hx_cells_bf16_kernel<NPB, SPLIT, CBW, false>), dim3((unsigned)(ncell * ntiles)), dim3(256), 0, s,
+                     a.X, a.ldx, a.Xp, a.ldp, a.Y, a.ldy, a.Kh, a.Kl, a.cmap, a.n_loc, a.q, a.n_el,
+                     a.cells + color_begin, a.minv, a.V, a.ncols, ntiles, a.s1, a.s2, a.shift, nullptr, nullptr, 0, 0,
+                     0, 0);
 }
 
 template <bool SPLIT, int CBW>
@@ -723,7 +756,9 @@ static int bf16_batch_dispatch(int npb, const BatchProblemBf16 *probs, const int
   switch (npb) {
 #define CHFSI_BF16_BATCH(NPB)                                                                                   \
   case NPB:                                                                                                     \
-    hipLaunchKernelGGL((hx_cells_bf16_batch_kernel<NPB, SPLIT>), g, b, 0, s, probs, work, step, cur, prev, out); \
+    hipLaunchKernelGGL((hx_cells_bf16_kernel<NPB, SPLIT, 2, true>), g, b, 0, s, nullptr, 0, nullptr, 0, nullptr, 0,   \
+                       nullptr, nullptr, nullptr, 0, 0, 0, nullptr, nullptr, nullptr, 0, 1, 0.f, 0.f, 0.f, probs,     \
+                       work, step, cur, prev, out);                                                             \
     return 0;
     CHFSI_BF16_BATCH(32) CHFSI_BF16_BATCH(64) CHFSI_BF16_BATCH(128) CHFSI_BF16_BATCH(224) CHFSI_BF16_BATCH(352)
     CHFSI_BF16_BATCH(512)
