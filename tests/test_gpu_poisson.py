@@ -15,7 +15,8 @@ def _t(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda:0")
 
 
-@pytest.mark.parametrize("L,n_el,p", [(6.0, 2, 1), (6.0, 2, 3), (8.0, 3, 4), (10.0, 4, 6), (7.0, 2, 7)])
+@pytest.mark.parametrize("L,n_el,p", [(6.0, 2, 1), (6.0, 2, 3), (8.0, 3, 4), (10.0, 4, 6), (7.0, 2, 7),
+                                      (30.0, 12, 6), (26.0, 13, 5)])   # 71^3, 64^3: several ragged tiles
 def test_poisson_apply_matches_oracle(L, n_el, p):
     c = P.Context(0).set_mesh(L, n_el, p)
     A, _ = poisson.poisson_matrix(L, n_el, p)
@@ -69,3 +70,27 @@ def test_poisson_warm_start_and_argument_checks():
     with pytest.raises(P.ChfsiError):
         cp.poisson_solve(torch.zeros(cp.n_dof, dtype=torch.float64, device="cuda:0"))
     cp.close()
+
+
+@pytest.mark.parametrize("cap", [1, 2, 7, 19])
+def test_poisson_iterates_follow_the_oracle_pcg_step_by_step(cap):
+    """With the iteration cap below convergence, the solve stops after exactly
+    `cap` iterations, reports non-convergence, and its iterate equals the
+    oracle's Jacobi-PCG iterate after the same number of steps (the same
+    recurrences; only the summation order differs) -- a check of alpha, beta
+    and the direction update, not only of the converged answer.  The returned
+    relative residual is that of the returned iterate."""
+    L, n_el, p = 8.0, 3, 4
+    c = P.Context(0).set_mesh(L, n_el, p)
+    xyz = fem.dof_coords(L, n_el, p)
+    rho = -workload.eval_wells(workload.draw_wells(3, L, 6, (0.5, 1.0), (0.5, 1.0)), xyz)
+    out = c.poisson_solve(_t(rho), charges=[(17, -2.0)], tol=1e-14, max_iter=cap)
+    assert not out["converged"] and out["iters"] == cap
+    A, M = poisson.poisson_matrix(L, n_el, p)
+    f = poisson.load_vector(M, rho, [17], [-2.0])
+    x_o, it_o, hist = poisson.jacobi_pcg(A, f, tol=1e-14, max_iter=cap)
+    assert it_o == cap
+    phi = out["phi"].cpu().numpy()
+    assert np.max(np.abs(phi - x_o)) < 1e-11 * np.max(np.abs(x_o))
+    np.testing.assert_allclose(out["rel_resid"], np.linalg.norm(f - A @ phi) / np.linalg.norm(f), rtol=1e-8)
+    c.close()
