@@ -14,17 +14,18 @@
 // blocked stencil that reads x about once from HBM and writes y once (16 bytes
 // per DoF).
 //
-// One CG iteration is five launches: the product fused with the partial p.q;
-// a single-work-group reduction in a fixed order (alpha = r.z / p.q); x, r, z
-// with the partials of r.z and r.r; a second reduction (beta = r.z' / r.z,
-// the iteration count, and the stop flag once r.r <= tol^2 f.f); the new
+// One CG iteration is four launches: the product fused with the partial p.q;
+// x, r, z with the partials of r.z and r.r (every work-group first sums the
+// product's partials in the same fixed order, so all of them hold the same
+// alpha = r.z / p.q); a single-work-group reduction (beta = r.z' / r.z, the
+// iteration count, and the stop flag once r.r <= tol^2 f.f); the new
 // direction p = z + beta p.  Once the flag is up every further launch returns
 // at once, so the host launches iterations in groups and reads the flag
 // between groups.  (Forming p inside the product, where the stencil reads it,
 // saves the direction pass but reads two arrays at every halo point: measured
-// 2.3x slower per product.  Summing the partials in the last work-group of
-// each grid saves the small launches, but every work-group's device-scope
-// release then writes back its L2: slower again.)
+// 2.3x slower per product.  Summing partials in the last work-group of each
+// grid saves the small launches, but every work-group's device-scope release
+// then writes back its L2: slower still.)
 #include "common.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
@@ -37,9 +38,9 @@
 namespace chfsi {
 
 static constexpr int PB = 256;              // threads per work-group
-static constexpr int PR = 1024;             // threads of the setup reduction
+static constexpr int PR = 1024;             // threads of the single-work-group reductions
 static constexpr int MAXG = 2048;           // element-wise grids: at most this many work-groups (grid-stride)
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_FF, S_STOP, S_DONE, S_IT, S_NSCAL };
+enum { S_RZ = 0, S_BETA, S_RR, S_FF, S_STOP, S_DONE, S_IT, S_NSCAL };
 
 template <int NT = PB>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -199,17 +200,23 @@ __global__ __launch_bounds__(PB) void poisson_stencil_kernel(const double *__res
   }
 }
 
-// x += alpha p, r -= alpha q, z = r / diag(A); partials of r.z and r.r
+// alpha = r.z / p.q from the product's partials (summed in a fixed order by
+// every work-group); x += alpha p, r -= alpha q, z = r / diag(A); partials of
+// r.z and r.r
 __global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__ x, double *__restrict__ r,
                                                             double *__restrict__ z, const double *__restrict__ pv,
                                                             const double *__restrict__ q,
                                                             const double *__restrict__ dinv, int64_t nd,
                                                             const double *__restrict__ scal,
+                                                            const double *__restrict__ part_pq, int npq,
                                                             double *__restrict__ part_rz, double *__restrict__ part_rr) {
   __shared__ double sh[PB];
   if (scal[S_DONE] != 0) return;
+  double pq = 0;
+  for (int i = threadIdx.x; i < npq; i += PB) pq += part_pq[i];
+  pq = block_sum(pq, sh);
+  const double alpha = pq != 0 ? scal[S_RZ] / pq : 0.0;
   double rz = 0, rr = 0;
-  const double alpha = scal[S_ALPHA];
   for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB) {
     x[idx] += alpha * pv[idx];
     const double rv = r[idx] - alpha * q[idx];
@@ -310,38 +317,31 @@ __global__ __launch_bounds__(PR) void poisson_setup_reduce_kernel(const double *
     scal[S_FF] = sc;
     scal[S_STOP] = tol2 * sc;
     scal[S_BETA] = 0.0;
-    scal[S_ALPHA] = 0.0;
     scal[S_IT] = 0.0;
     scal[S_DONE] = sb <= tol2 * sc ? 1.0 : 0.0;
   }
 }
 
-// The iteration's scalar recurrences, partials summed in a fixed order:
-// mode 0: p.q = sum a; alpha = r.z / p.q.
-// mode 1: r.z' = sum a, r.r = sum b; beta = r.z' / r.z; the iteration count;
-//         the stop flag when r.r <= tol^2 f.f.
-__global__ __launch_bounds__(PR) void poisson_reduce_kernel(const double *__restrict__ a, const double *__restrict__ b,
-                                                            int nparts, int mode, double *__restrict__ scal) {
+// The iteration's beta, partials summed in a fixed order: r.z' = sum a,
+// r.r = sum b; beta = r.z' / r.z; the iteration count; the stop flag when
+// r.r <= tol^2 f.f.
+__global__ __launch_bounds__(PR) void poisson_beta_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                                                          int nparts, double *__restrict__ scal) {
   __shared__ double sh[PR];
   if (scal[S_DONE] != 0) return;
   double sa = 0, sb = 0;
   for (int i = threadIdx.x; i < nparts; i += PR) {
     sa += a[i];
-    if (mode == 1) sb += b[i];
+    sb += b[i];
   }
   sa = block_sum<PR>(sa, sh);
-  if (mode == 1) sb = block_sum<PR>(sb, sh);
+  sb = block_sum<PR>(sb, sh);
   if (threadIdx.x == 0) {
-    if (mode == 0) {
-      scal[S_PQ] = sa;
-      scal[S_ALPHA] = sa != 0 ? scal[S_RZ] / sa : 0.0;
-    } else {
-      scal[S_BETA] = scal[S_RZ] != 0 ? sa / scal[S_RZ] : 0.0;
-      scal[S_RZ] = sa;
-      scal[S_RR] = sb;
-      scal[S_IT] += 1.0;
-      if (sb <= scal[S_STOP]) scal[S_DONE] = 1.0;
-    }
+    scal[S_BETA] = scal[S_RZ] != 0 ? sa / scal[S_RZ] : 0.0;
+    scal[S_RZ] = sa;
+    scal[S_RR] = sb;
+    scal[S_IT] += 1.0;
+    if (sb <= scal[S_STOP]) scal[S_DONE] = 1.0;
   }
 }
 
@@ -498,10 +498,10 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
   while (launched < max_iter) {
     const int k = std::min(GROUP, max_iter - launched);
     for (int i = 0; i < k; ++i, ++launched) {
-      poisson_stencil_launch(M, pv, q, kb, m, scal, pa, s);
-      hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, (int)na, 0, scal);
-      hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pa, pb);
-      hipLaunchKernelGGL(poisson_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, (int)nb, 1, scal);
+      poisson_stencil_launch(M, pv, q, kb, m, scal, pc, s);
+      hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pc, (int)na, pa,
+                         pb);
+      hipLaunchKernelGGL(poisson_beta_kernel, dim3(1), dim3(PR), 0, s, pa, pb, (int)nb, scal);
       hipLaunchKernelGGL(poisson_dir_kernel, grid, block, 0, s, pv, z, scal, nd);
     }
     HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
