@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import paper_1903_10959_amd as P
-from oracle import fem, kpoint
+from oracle import kpoint
 import workload
 
 pytestmark = pytest.mark.gpu

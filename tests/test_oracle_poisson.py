@@ -1,7 +1,6 @@
 """Pins of the oracle's discrete Poisson problem (Sec. 2.4 eq.
 phiTotDiscreteSolve, Dirichlet), CPU only."""
 import numpy as np
-import pytest
 import scipy.sparse.linalg as spla
 
 from oracle import fem, poisson

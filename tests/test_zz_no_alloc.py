@@ -7,7 +7,6 @@ import ctypes as C
 import numpy as np
 import pytest
 
-from oracle import chfsi as och
 import workload
 from gpu_util import make_ctx, to_gpu, to_host
 
