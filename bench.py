@@ -558,9 +558,10 @@ def poisson_bench(args, prob):
     mesh: Jacobi-PCG to a 1e-10 relative residual for the density of the
     workload's wells plus point charges at two nodes.  Roofline of the
     matrix-free product: HBM, algorithmic bytes = 16 per DoF (read x, write y).
-    A whole CG iteration moves 104 algorithmic bytes per DoF: the product
-    reads p and writes q, the update reads x, p, r, q and 1/diag(A) and writes
-    x, r and z, the new direction reads z and p and writes p."""
+    A whole CG iteration moves 80 algorithmic bytes per DoF: the product reads
+    p and writes q, the update reads r and q and writes r, the direction pass
+    reads x, p and r and writes x and p (z = r / diag(A) is recomputed where it
+    is used)."""
     import numpy as np
     import torch
 
@@ -600,7 +601,7 @@ def poisson_bench(args, prob):
            "config": {"workload": f"Dirichlet [0,{prob.L}]^3, {prob.n_el}^3 cells, p={prob.p}, {prob.n_dof} DoFs; "
                                   f"density of the workload's 64 wells + 2 point charges", "steps": args.steps},
            "iterations": its[-1], "ms_per_iteration": 1e3 * t / max(1, its[-1]), "rel_resid": out["rel_resid"],
-           "iteration_hbm_gbs": 104.0 * prob.n_dof * max(1, its[-1]) / t / 1e9,
+           "iteration_hbm_gbs": 80.0 * prob.n_dof * max(1, its[-1]) / t / 1e9,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
                         "traffic": profiled_traffic(f"poisson_{prob.name}", ("poisson.hip",)),
                         "kernel": "poisson_stencil_kernel", "avg_launch_ms": ms,

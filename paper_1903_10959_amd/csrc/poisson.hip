@@ -14,18 +14,25 @@
 // blocked stencil that reads x about once from HBM and writes y once (16 bytes
 // per DoF).
 //
-// One CG iteration is four launches: the product fused with the partial p.q;
-// x, r, z with the partials of r.z and r.r (every work-group first sums the
-// product's partials in the same fixed order, so all of them hold the same
-// alpha = r.z / p.q); a single-work-group reduction (beta = r.z' / r.z, the
-// iteration count, and the stop flag once r.r <= tol^2 f.f); the new
-// direction p = z + beta p.  Once the flag is up every further launch returns
-// at once, so the host launches iterations in groups and reads the flag
-// between groups.  (Forming p inside the product, where the stencil reads it,
-// saves the direction pass but reads two arrays at every halo point: measured
-// 2.3x slower per product.  Summing partials in the last work-group of each
-// grid saves the small launches, but every work-group's device-scope release
-// then writes back its L2: slower still.)
+// One CG iteration is three launches: the product fused with the partial
+// p.q; r -= alpha q with the partials of r.z and r.r; x += alpha p and the new
+// direction p = z + beta p.  The two global sums each iteration needs are
+// formed where they are used: every work-group of the update sums the
+// product's partials (alpha = r.z / p.q), every work-group of the direction
+// pass sums the update's (beta = r.z' / r.z and the stop test r.r <=
+// tol^2 f.f), each in the same fixed order, so all work-groups hold the same
+// bits.  Work-group 0 keeps the results for later launches in slots that no
+// work-group of the same launch reads (r.z alternates between two slots by
+// iteration parity).  Neither z nor diag(A)^-1 is stored: diag(A) at a node is
+// three products of 1D values, so both vector passes recompute z = r /
+// diag(A), and an iteration moves eight arrays of n_dof values.  The
+// iteration that meets the tolerance records its number; launches of later
+// iterations return at once, so the host launches iterations in groups and
+// reads that number between groups.  (Forming p inside the product, where
+// the stencil reads it, saves the direction pass but reads two arrays at
+// every halo point: measured 2.3x slower per product.  Summing partials in
+// the last work-group of each grid instead, every work-group's device-scope
+// release writes back its L2: slower still.)
 #include "common.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
@@ -40,25 +47,26 @@ namespace chfsi {
 static constexpr int PB = 256;              // threads per work-group
 static constexpr int PR = 1024;             // threads of the single-work-group reductions
 static constexpr int MAXG = 2048;           // element-wise grids: at most this many work-groups (grid-stride)
-enum { S_RZ = 0, S_BETA, S_RR, S_FF, S_STOP, S_DONE, S_IT, S_NSCAL };
+// scalars: r.z of the last two iterations (slot by parity), r.r, f.f, the
+// stop threshold tol^2 f.f, the number of iterations done when the tolerance
+// was met (kNever until then), alpha of the last update
+enum { S_RZ = 0, S_RR = 2, S_FF, S_STOP, S_STOPAT, S_ALPHA, S_NSCAL };
+static constexpr double kNever = 9.0e15;
 
+// Sum over the work-group in a fixed order (butterfly within each wave, then
+// the wave sums in wave order), so every work-group that sums the same
+// values gets the same bits.
 template <int NT = PB>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double s = sh[0];
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) s += sh[w];
   __syncthreads();
   return s;
-}
-
-__device__ __forceinline__ double poisson_diag(const double *__restrict__ kb, const double *__restrict__ m, int p,
-                                               int I, int J, int K, double s) {
-  const int bw = 2 * p + 1;
-  return s * (kb[I * bw + p] * m[J] * m[K] + m[I] * kb[J * bw + p] * m[K] + m[I] * m[J] * kb[K * bw + p]);
 }
 
 // y = A x with 2.5D blocking.  Work-group = 4 waves; wave w covers 64
@@ -77,13 +85,13 @@ template <int P, int RY, int KB, int PD, bool DOT>
 __global__ __launch_bounds__(PB) void poisson_stencil_kernel(const double *__restrict__ x, double *__restrict__ y,
                                                              const double *__restrict__ kb,
                                                              const double *__restrict__ m, int n, double s,
-                                                             const double *__restrict__ scal,
+                                                             const double *__restrict__ scal, int it,
                                                              double *__restrict__ part) {
   constexpr int BW = 2 * P + 1, TY = 4 * RY, WX = TX + 2 * P, WY = TY + 2 * P;
   constexpr int NTL = (WY * WX + PB - 1) / PB;    // tile values per thread
   __shared__ double sh[PB];
   __shared__ double xs[WY][WX];
-  if (DOT && scal[S_DONE] != 0) return;
+  if (DOT && it >= scal[S_STOPAT]) return;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // XCD-grouped block order: the hardware deals consecutive work-groups to the
@@ -200,31 +208,109 @@ __global__ __launch_bounds__(PB) void poisson_stencil_kernel(const double *__res
   }
 }
 
-// alpha = r.z / p.q from the product's partials (summed in a fixed order by
-// every work-group); x += alpha p, r -= alpha q, z = r / diag(A); partials of
-// r.z and r.r
-__global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__ x, double *__restrict__ r,
-                                                            double *__restrict__ z, const double *__restrict__ pv,
-                                                            const double *__restrict__ q,
-                                                            const double *__restrict__ dinv, int64_t nd,
-                                                            const double *__restrict__ scal,
+// The two vector passes run by rows of the mesh: wave w of work-group b
+// takes the 64 consecutive I of its I-chunk in VR consecutive rows (J, K), so
+// the J- and K-dependent factors of diag(A) are wave-uniform and each lane
+// keeps its I-dependent ones.  The loads of the partials a pass sums are
+// issued first, then all of the rows' loads, so the global sum is formed
+// while the rows are in flight.
+constexpr int VR = 16;
+constexpr int PU = 4;   // partials per thread loaded ahead (the rest, if any, after)
+static dim3 vec_grid(int n) {
+  const int64_t rows = (int64_t)n * n;
+  return dim3((unsigned)(((n + 63) / 64) * ((rows + 4 * VR - 1) / (4 * VR))));
+}
+struct VecPos {
+  int I;           // this lane's node index along x
+  int row0;        // first row of the wave's run (row = J + n K < n^2 < 2^31)
+  int J0, K0;      // its J and K (wave-uniform)
+  bool ilive;
+};
+__device__ __forceinline__ VecPos vec_pos(int n) {
+  const int gx = (n + 63) / 64;
+  const int b = (int)blockIdx.x;
+  const int bx = b % gx, br = b / gx;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  VecPos v;
+  v.I = bx * 64 + ((int)threadIdx.x & 63);
+  v.row0 = (br * 4 + w) * VR;
+  v.K0 = v.row0 / n;
+  v.J0 = v.row0 - v.K0 * n;
+  v.ilive = v.I < n;
+  return v;
+}
+// z = r / diag(A) at (I, J, K): the lane's I factors and the row's J, K ones
+__device__ __forceinline__ double jacobi_z(double rv, double kdI, double mI, double kdJ, double mJ, double kdK,
+                                           double mK, double s) {
+  return __dmul_rn(rv, 1.0 / (s * (kdI * mJ * mK + mI * kdJ * mK + mI * mJ * kdK)));
+}
+// Sum of a[0 .. na) in a fixed order, in two steps: parts_load issues the
+// thread's first PU loads, parts_sum adds them, then the rest, then sums over
+// the work-group.
+__device__ __forceinline__ void parts_load(const double *__restrict__ a, int na, double (&v)[PU]) {
+#pragma unroll
+  for (int u = 0; u < PU; ++u) {
+    const int i = (int)threadIdx.x + u * PB;
+    v[u] = i < na ? a[i] : 0.0;
+  }
+}
+__device__ __forceinline__ double parts_sum(const double *__restrict__ a, int na, const double (&v)[PU],
+                                            double *sh) {
+  double t = 0;
+#pragma unroll
+  for (int u = 0; u < PU; ++u) t += v[u];
+  for (int i = (int)threadIdx.x + PU * PB; i < na; i += PB) t += a[i];
+  return block_sum(t, sh);
+}
+
+// Iteration it: alpha = r.z / p.q from the product's partials (work-group 0
+// keeps it for the direction pass); r -= alpha q; partials of r.z
+// (z = r / diag(A)) and r.r.
+__global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__ r, const double *__restrict__ q,
+                                                            const double *__restrict__ kb,
+                                                            const double *__restrict__ m, int n, int p, double s,
+                                                            double *__restrict__ scal, int it,
                                                             const double *__restrict__ part_pq, int npq,
                                                             double *__restrict__ part_rz, double *__restrict__ part_rr) {
-  __shared__ double sh[PB];
-  if (scal[S_DONE] != 0) return;
-  double pq = 0;
-  for (int i = threadIdx.x; i < npq; i += PB) pq += part_pq[i];
-  pq = block_sum(pq, sh);
-  const double alpha = pq != 0 ? scal[S_RZ] / pq : 0.0;
+  __shared__ double sh[PB / 64];
+  if (it >= scal[S_STOPAT]) return;
+  double pp[PU];
+  parts_load(part_pq, npq, pp);
+  const int bw = 2 * p + 1;
+  const int64_t rows = (int64_t)n * n;
+  const VecPos vp = vec_pos(n);
+  const double kdI = vp.ilive ? kb[(int64_t)vp.I * bw + p] : 0.0, mI = vp.ilive ? m[vp.I] : 0.0;
+  double rv[VR], qv[VR];
+#pragma unroll
+  for (int u = 0; u < VR; ++u) {
+    const int64_t row = vp.row0 + u;
+    const bool ok = vp.ilive && row < rows;
+    const int64_t idx = vp.I + n * row;
+    rv[u] = ok ? r[idx] : 0.0;
+    qv[u] = ok ? q[idx] : 0.0;
+  }
+  const double pq = parts_sum(part_pq, npq, pp, sh);
+  const double alpha = pq != 0 ? scal[S_RZ + (it & 1)] / pq : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
   double rz = 0, rr = 0;
-  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB) {
-    x[idx] += alpha * pv[idx];
-    const double rv = r[idx] - alpha * q[idx];
-    r[idx] = rv;
-    const double zv = rv * dinv[idx];
-    z[idx] = zv;
-    rz += rv * zv;
-    rr += rv * rv;
+  int J = vp.J0, K = vp.K0;
+#pragma unroll
+  for (int u = 0; u < VR; ++u, ++J) {
+    const int64_t row = vp.row0 + u;
+    if (row >= rows) break;                         // wave-uniform
+    if (J == n) {
+      J = 0;
+      ++K;
+    }
+    const double kdJ = kb[(int64_t)J * bw + p], mJ = m[J], kdK = kb[(int64_t)K * bw + p], mK = m[K];
+    if (vp.ilive) {
+      const int64_t idx = vp.I + n * row;
+      const double v = rv[u] - alpha * qv[u];
+      r[idx] = v;
+      const double zv = jacobi_z(v, kdI, mI, kdJ, mJ, kdK, mK, s);
+      rz += v * zv;
+      rr += v * v;
+    }
   }
   const double a = block_sum(rz, sh);
   const double b = block_sum(rr, sh);
@@ -234,36 +320,90 @@ __global__ __launch_bounds__(PB) void poisson_update_kernel(double *__restrict__
   }
 }
 
-// p = z + beta p
-__global__ __launch_bounds__(PB) void poisson_dir_kernel(double *__restrict__ pv, const double *__restrict__ z,
-                                                         const double *__restrict__ scal, int64_t nd) {
-  if (scal[S_DONE] != 0) return;
-  const double beta = scal[S_BETA];
-  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB)
-    pv[idx] = z[idx] + beta * pv[idx];
+// Iteration it: r.z' and r.r from the update's partials; x += alpha p (the
+// update's alpha); unless r.r meets the tolerance, p = z + beta p with
+// z = r / diag(A), beta = r.z' / r.z.  Work-group 0 keeps r.z' (the other
+// parity slot), r.r, and the iteration count once the tolerance is met.
+__global__ __launch_bounds__(PB) void poisson_dir_kernel(double *__restrict__ x, double *__restrict__ pv,
+                                                         const double *__restrict__ r,
+                                                         const double *__restrict__ kb,
+                                                         const double *__restrict__ m, int n, int p, double s,
+                                                         double *__restrict__ scal, int it,
+                                                         const double *__restrict__ part_rz,
+                                                         const double *__restrict__ part_rr, int nparts) {
+  __shared__ double sh[PB / 64];
+  if (it >= scal[S_STOPAT]) return;
+  double pz[PU], pr[PU];
+  parts_load(part_rz, nparts, pz);
+  parts_load(part_rr, nparts, pr);
+  const double alpha = scal[S_ALPHA], rz_old = scal[S_RZ + (it & 1)], stop = scal[S_STOP];
+  const int bw = 2 * p + 1;
+  const int64_t rows = (int64_t)n * n;
+  const VecPos vp = vec_pos(n);
+  const double kdI = vp.ilive ? kb[(int64_t)vp.I * bw + p] : 0.0, mI = vp.ilive ? m[vp.I] : 0.0;
+  double pw[VR], rw[VR];
+  {
+    double xw[VR];
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int64_t row = vp.row0 + u;
+      const bool ok = vp.ilive && row < rows;
+      const int64_t idx = vp.I + n * row;
+      pw[u] = ok ? pv[idx] : 0.0;
+      xw[u] = ok ? x[idx] : 0.0;
+      rw[u] = ok ? r[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int64_t row = vp.row0 + u;
+      if (vp.ilive && row < rows) x[vp.I + n * row] = fma(alpha, pw[u], xw[u]);
+    }
+  }
+  const double rz = parts_sum(part_rz, nparts, pz, sh);
+  const double rr = parts_sum(part_rr, nparts, pr, sh);
+  const bool last = rr <= stop;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_RZ + ((it + 1) & 1)] = rz;
+    scal[S_RR] = rr;
+    if (last) scal[S_STOPAT] = it + 1;
+  }
+  if (last) return;
+  const double beta = rz_old != 0 ? rz / rz_old : 0.0;
+  int J = vp.J0, K = vp.K0;
+#pragma unroll
+  for (int u = 0; u < VR; ++u, ++J) {
+    const int64_t row = vp.row0 + u;
+    if (row >= rows) break;                         // wave-uniform
+    if (J == n) {
+      J = 0;
+      ++K;
+    }
+    if (vp.ilive) {
+      const double zv = jacobi_z(rw[u], kdI, mI, kb[(int64_t)J * bw + p], m[J], kb[(int64_t)K * bw + p], m[K], s);
+      pv[vp.I + n * row] = fma(beta, pw[u], zv);
+    }
+  }
 }
 
-// Setup: r = f - A x (q = A x given), z = r / diag, p = z; partials of r.z,
+// Setup: r = f - A x (q = A x given), p = z = r / diag(A); partials of r.z,
 // r.r and f.f.
 __global__ __launch_bounds__(PB) void poisson_init_kernel(const double *__restrict__ f, const double *__restrict__ q,
-                                                          double *__restrict__ r, double *__restrict__ z,
-                                                          double *__restrict__ pv, double *__restrict__ dinv,
+                                                          double *__restrict__ r, double *__restrict__ pv,
                                                           const double *__restrict__ kb,
                                                           const double *__restrict__ m, int n, int p, double s,
                                                           double *__restrict__ part_rz, double *__restrict__ part_rr,
                                                           double *__restrict__ part_ff) {
   __shared__ double sh[PB];
   const int64_t nd = (int64_t)n * n * n;
+  const int bw = 2 * p + 1;
   double rz = 0, rr = 0, ff = 0;
   for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < nd; idx += (int64_t)gridDim.x * PB) {
-    const int I = (int)(idx % n), J = (int)((idx / n) % n), K = (int)(idx / ((int64_t)n * n));
     const double fv = f[idx];
     const double rv = fv - q[idx];
-    const double di = 1.0 / poisson_diag(kb, m, p, I, J, K, s);
-    dinv[idx] = di;
-    const double zv = rv * di;
+    const int I = (int)(idx % n), J = (int)((idx / n) % n), K = (int)(idx / ((int64_t)n * n));
+    const double zv = jacobi_z(rv, kb[(int64_t)I * bw + p], m[I], kb[(int64_t)J * bw + p], m[J],
+                               kb[(int64_t)K * bw + p], m[K], s);
     r[idx] = rv;
-    z[idx] = zv;
     pv[idx] = zv;
     rz += rv * zv;
     rr += rv * rv;
@@ -294,9 +434,9 @@ __global__ __launch_bounds__(PB) void poisson_charges_kernel(double *__restrict_
   if (i < nq) f[dofs[i]] += q[i];
 }
 
-// Setup sums in a fixed order: r.z, r.r, f.f; the stop threshold
-// tol^2 f.f, beta = 0, the iteration count and the stop flag (raised at once
-// when the initial guess already meets the tolerance).
+// Setup sums in a fixed order: r.z (the slot of iteration 0), r.r, f.f; the
+// stop threshold tol^2 f.f and the stop count (0 when the initial guess
+// already meets the tolerance).
 __global__ __launch_bounds__(PR) void poisson_setup_reduce_kernel(const double *__restrict__ a,
                                                                   const double *__restrict__ b,
                                                                   const double *__restrict__ c, int nparts,
@@ -313,35 +453,12 @@ __global__ __launch_bounds__(PR) void poisson_setup_reduce_kernel(const double *
   sc = block_sum<PR>(sc, sh);
   if (threadIdx.x == 0) {
     scal[S_RZ] = sa;
+    scal[S_RZ + 1] = 0.0;
     scal[S_RR] = sb;
     scal[S_FF] = sc;
     scal[S_STOP] = tol2 * sc;
-    scal[S_BETA] = 0.0;
-    scal[S_IT] = 0.0;
-    scal[S_DONE] = sb <= tol2 * sc ? 1.0 : 0.0;
-  }
-}
-
-// The iteration's beta, partials summed in a fixed order: r.z' = sum a,
-// r.r = sum b; beta = r.z' / r.z; the iteration count; the stop flag when
-// r.r <= tol^2 f.f.
-__global__ __launch_bounds__(PR) void poisson_beta_kernel(const double *__restrict__ a, const double *__restrict__ b,
-                                                          int nparts, double *__restrict__ scal) {
-  __shared__ double sh[PR];
-  if (scal[S_DONE] != 0) return;
-  double sa = 0, sb = 0;
-  for (int i = threadIdx.x; i < nparts; i += PR) {
-    sa += a[i];
-    sb += b[i];
-  }
-  sa = block_sum<PR>(sa, sh);
-  sb = block_sum<PR>(sb, sh);
-  if (threadIdx.x == 0) {
-    scal[S_BETA] = scal[S_RZ] != 0 ? sa / scal[S_RZ] : 0.0;
-    scal[S_RZ] = sa;
-    scal[S_RR] = sb;
-    scal[S_IT] += 1.0;
-    if (sb <= scal[S_STOP]) scal[S_DONE] = 1.0;
+    scal[S_ALPHA] = 0.0;
+    scal[S_STOPAT] = sb <= tol2 * sc ? 0.0 : kNever;
   }
 }
 
@@ -405,20 +522,20 @@ static dim3 apply_grid(int n) {
   return dim3((unsigned)((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + POIS_KB - 1) / POIS_KB));
 }
 
-// y = A x; with part (and scal): the partials of x . y (skipped once the
-// stop flag in scal is up).  -1 for an unsupported degree.
+// y = A x; with part (and scal, it): the partials of x . y for iteration it
+// (skipped once the solve has stopped).  -1 for an unsupported degree.
 static int poisson_stencil_launch(const MeshTables &M, const double *x, double *y, const double *kb, const double *m,
-                                  const double *scal, double *part, hipStream_t s) {
+                                  const double *scal, int it, double *part, hipStream_t s) {
   const dim3 g = apply_grid(M.n), b(PB);
   switch (M.p) {
 #define CHFSI_POIS_P(P)                                                                                        \
   case P:                                                                                                      \
     if (part)                                                                                                  \
       hipLaunchKernelGGL((poisson_stencil_kernel<P, POIS_RY, POIS_KB, POIS_PD, true>), g, b, 0, s, x, y, kb, m, M.n,       \
-                         kInv4Pi, scal, part);                                                                 \
+                         kInv4Pi, scal, it, part);                                                                 \
     else                                                                                                       \
       hipLaunchKernelGGL((poisson_stencil_kernel<P, POIS_RY, POIS_KB, POIS_PD, false>), g, b, 0, s, x, y, kb, m, M.n,      \
-                         kInv4Pi, nullptr, nullptr);                                                           \
+                         kInv4Pi, nullptr, 0, nullptr);                                                           \
     return 0;
     CHFSI_POIS_P(1) CHFSI_POIS_P(2) CHFSI_POIS_P(3) CHFSI_POIS_P(4) CHFSI_POIS_P(5) CHFSI_POIS_P(6)
     CHFSI_POIS_P(7)
@@ -434,7 +551,7 @@ using namespace chfsi;
 extern "C" int chfsi_poisson_apply(chfsi_ctx *c, const double *x, double *y) {
   if (int r = poisson_ready(c)) return r;
   if (!x || !y || x == y) return fail(c, CHFSI_ERR_ARG, "poisson_apply: x and y must be separate device arrays");
-  if (poisson_stencil_launch(c->mesh, x, y, c->pois_kb.as<double>(), c->pois_m.as<double>(), nullptr, nullptr,
+  if (poisson_stencil_launch(c->mesh, x, y, c->pois_kb.as<double>(), c->pois_m.as<double>(), nullptr, 0, nullptr,
                              c->stream))
     return fail(c, CHFSI_ERR_ARG, "poisson_apply: degree p must be in 1..7");
   HIPCHK(c, hipGetLastError());
@@ -458,13 +575,14 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
     qmap[charge_dofs[i]] += charges[i];
   }
   const int64_t nb = std::min<int64_t>((nd + PB - 1) / PB, MAXG);   // element-wise grids (grid-stride)
+  const int64_t nv = vec_grid(M.n).x;                // the two vector passes
   const dim3 ga = apply_grid(M.n);
   const int64_t na = (int64_t)ga.x * ga.y * ga.z;  // product grid
-  const int64_t npart = nb > na ? nb : na;
-  // workspace: f, r, z, p, q, 1/diag(A) (nd each), partials (3 npart), scalars
-  HIPCHK(c, c->pois_work.ensure((size_t)(6 * nd + 3 * npart + S_NSCAL) * sizeof(double)));
-  double *f = c->pois_work.as<double>(), *r = f + nd, *z = r + nd, *pv = z + nd, *q = pv + nd, *dinv = q + nd;
-  double *pa = dinv + nd, *pb = pa + npart, *pc = pb + npart, *scal = pc + npart;
+  const int64_t npart = std::max(std::max(nb, na), nv);
+  // workspace: f, r, p, q (nd each), partials (3 npart), scalars
+  HIPCHK(c, c->pois_work.ensure((size_t)(4 * nd + 3 * npart + S_NSCAL) * sizeof(double)));
+  double *f = c->pois_work.as<double>(), *r = f + nd, *pv = r + nd, *q = pv + nd;
+  double *pa = q + nd, *pb = pa + npart, *pc = pb + npart, *scal = pc + npart;
   const double *kb = c->pois_kb.as<double>(), *m = c->pois_m.as<double>();
   const dim3 grid((unsigned)nb), block(PB);
   hipStream_t s = c->stream;
@@ -485,36 +603,34 @@ extern "C" int chfsi_poisson_solve(chfsi_ctx *c, const double *rho, int ncharges
                        (int)qd.size());
     HIPCHK(c, hipStreamSynchronize(s));            // the host staging vectors go out of scope
   }
-  poisson_stencil_launch(M, phi, q, kb, m, nullptr, nullptr, s);
-  hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
-                     pc);
+  poisson_stencil_launch(M, phi, q, kb, m, nullptr, 0, nullptr, s);
+  hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, pv, kb, m, M.n, M.p, kInv4Pi, pa, pb, pc);
   hipLaunchKernelGGL(poisson_setup_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, tol * tol, scal);
-  // iterations in groups; the device counts them and stops itself, the host
-  // reads the flag between groups (a group started after the stop costs only
-  // its empty launches)
+  // iterations in groups; the device records the iteration that met the
+  // tolerance, the host reads it between groups (a group started after the
+  // stop costs only its empty launches)
   constexpr int GROUP = 8;
   double hs[S_NSCAL];
   int launched = 0;
   while (launched < max_iter) {
     const int k = std::min(GROUP, max_iter - launched);
     for (int i = 0; i < k; ++i, ++launched) {
-      poisson_stencil_launch(M, pv, q, kb, m, scal, pc, s);
-      hipLaunchKernelGGL(poisson_update_kernel, grid, block, 0, s, phi, r, z, pv, q, dinv, nd, scal, pc, (int)na, pa,
-                         pb);
-      hipLaunchKernelGGL(poisson_beta_kernel, dim3(1), dim3(PR), 0, s, pa, pb, (int)nb, scal);
-      hipLaunchKernelGGL(poisson_dir_kernel, grid, block, 0, s, pv, z, scal, nd);
+      poisson_stencil_launch(M, pv, q, kb, m, scal, launched, pc, s);
+      hipLaunchKernelGGL(poisson_update_kernel, dim3((unsigned)nv), block, 0, s, r, q, kb, m, M.n, M.p, kInv4Pi, scal,
+                         launched, pc, (int)na, pa, pb);
+      hipLaunchKernelGGL(poisson_dir_kernel, dim3((unsigned)nv), block, 0, s, phi, pv, r, kb, m, M.n, M.p, kInv4Pi,
+                         scal, launched, pa, pb, (int)nv);
     }
     HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    if (hs[S_DONE] != 0) break;
+    if (hs[S_STOPAT] <= launched) break;
   }
   HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  const int it = (int)hs[S_IT];
+  const int it = hs[S_STOPAT] < launched ? (int)hs[S_STOPAT] : launched;
   // the true residual of the returned phi
-  poisson_stencil_launch(M, phi, q, kb, m, nullptr, nullptr, s);
-  hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, z, pv, dinv, kb, m, M.n, M.p, kInv4Pi, pa, pb,
-                     pc);
+  poisson_stencil_launch(M, phi, q, kb, m, nullptr, 0, nullptr, s);
+  hipLaunchKernelGGL(poisson_init_kernel, grid, block, 0, s, f, q, r, pv, kb, m, M.n, M.p, kInv4Pi, pa, pb, pc);
   hipLaunchKernelGGL(poisson_setup_reduce_kernel, dim3(1), dim3(PR), 0, s, pa, pb, pc, (int)nb, tol * tol, scal);
   HIPCHK(c, hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
