@@ -40,9 +40,10 @@ def test_poisson_solve_matches_oracle_with_point_charges():
     phi_o = poisson.solve(L, n_el, p, rho, [d for d, _ in charges], [q for _, q in charges])
     phi = out["phi"].cpu().numpy()
     assert np.max(np.abs(phi - phi_o)) < 1e-10 * np.max(np.abs(phi_o))
-    # the same algorithm: iteration counts agree (the host checks every 4th)
+    # the same algorithm: the device records the iteration at which its own
+    # test first held (sums in another order can move that by one at most)
     _, it_o, _ = poisson.jacobi_pcg(A, f, tol=1e-12)
-    assert it_o <= out["iters"] <= it_o + 4, (out["iters"], it_o)
+    assert abs(out["iters"] - it_o) <= 1, (out["iters"], it_o)
     c.close()
 
 
@@ -72,15 +73,15 @@ def test_poisson_warm_start_and_argument_checks():
     cp.close()
 
 
-@pytest.mark.parametrize("cap", [1, 2, 7, 19])
-def test_poisson_iterates_follow_the_oracle_pcg_step_by_step(cap):
+@pytest.mark.parametrize("L,n_el,p,cap", [(8.0, 3, 4, 1), (8.0, 3, 4, 2), (8.0, 3, 4, 7), (8.0, 3, 4, 19),
+                                          (30.0, 12, 6, 5)])   # 71^3: two I-chunks, rows wrapping across waves
+def test_poisson_iterates_follow_the_oracle_pcg_step_by_step(L, n_el, p, cap):
     """With the iteration cap below convergence, the solve stops after exactly
     `cap` iterations, reports non-convergence, and its iterate equals the
     oracle's Jacobi-PCG iterate after the same number of steps (the same
     recurrences; only the summation order differs) -- a check of alpha, beta
     and the direction update, not only of the converged answer.  The returned
     relative residual is that of the returned iterate."""
-    L, n_el, p = 8.0, 3, 4
     c = P.Context(0).set_mesh(L, n_el, p)
     xyz = fem.dof_coords(L, n_el, p)
     rho = -workload.eval_wells(workload.draw_wells(3, L, 6, (0.5, 1.0), (0.5, 1.0)), xyz)
