@@ -168,7 +168,7 @@ int cheb_step_c(chfsi_ctx *c, const double *X, int64_t ldx, const double *Xp, in
   for (int col = 0; col < 8; ++col)
     if (hx_cells_cplx_launch(a, M.color_offset[col], M.color_offset[col + 1], c->stream) != 0)
       return fail(c, CHFSI_ERR_ARG, "complex step: unsupported cell size");
-  c->cell_vecs += (int64_t)M.n_cells * 2 * ncols;
+  if (c->timing) c->cell_vecs += (int64_t)M.n_cells * 2 * ncols;
   HIPCHK(c, hipGetLastError());
   return 0;
 }

@@ -617,7 +617,7 @@ static int cheb_step_t(chfsi_ctx *c, const T *X, int64_t ldx, const T *Xp, int64
       if (e1) (void)hipEventRecord(e1, c->stream);
     }
   }
-  c->cell_vecs += (int64_t)M.n_cells * ncols;
+  if (c->timing) c->cell_vecs += (int64_t)M.n_cells * ncols;   // the work of the timed launches
   HIPCHK(c, hipGetLastError());
   return 0;
 }
