@@ -671,6 +671,30 @@ __global__ __launch_bounds__(256) void hx_cells_bf16_kernel(
 #pragma unroll
     for (int r = 0; r < RBW; ++r) al[0][r] = load_a(Kl_w, 0, r);
   }
+  if constexpr (!SPLIT && NPB == 224) {
+    // p = 5: the seven k-steps fully unrolled (same ping-pong, no loop):
+    // 0.435 against 0.465 ms per colour launch at 32^3 cells, 128 columns; a
+    // three-deep ring measured the same, and at p = 6 full unrolling costs a
+    // work-group per CU (0.436 against 0.362 ms)
+    constexpr int NKS = NPB / 32;
+#pragma unroll
+    for (int t = 0; t < NKS; ++t) {
+      if (t + 1 < NKS) {
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) ah[(t + 1) & 1][r] = load_a(Kh_w, 32 * (t + 1), r);
+      }
+      v8bf bh[CBW];
+#pragma unroll
+      for (int cb = 0; cb < CBW; ++cb) {
+        const int lc = wc * 16 * CBW + cb * 16 + j;
+        bh[cb] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i *>(&xs[0][lc * LDX + 32 * t + 8 * kq]));
+      }
+#pragma unroll
+      for (int r = 0; r < RBW; ++r)
+#pragma unroll
+        for (int cb = 0; cb < CBW; ++cb) acc[r][cb] = mfma16x32bf(ah[t & 1][r], bh[cb], acc[r][cb]);
+    }
+  } else
 #pragma unroll 1
   for (int k = 0; k < NPB; k += 64) {
 #pragma unroll
