@@ -21,11 +21,14 @@
 // product's partials (alpha = r.z / p.q), every work-group of the direction
 // pass sums the update's (beta = r.z' / r.z and the stop test r.r <=
 // tol^2 f.f), each in the same fixed order, so all work-groups hold the same
-// bits.  Work-group 0 keeps the results for later launches in slots that no
-// work-group of the same launch reads (r.z alternates between two slots by
-// iteration parity).  Neither z nor diag(A)^-1 is stored: diag(A) at a node is
-// three products of 1D values, so both vector passes recompute z = r /
-// diag(A), and an iteration moves eight arrays of n_dof values.  The
+// bits.  Work-group 0 keeps the results for later launches: r.z alternates
+// between two slots by iteration parity, so no work-group reads the slot its
+// own launch writes; the stop count, which every work-group of the same
+// launch also reads, can only change from "never" to this iteration's number
+// plus one, and both values let iteration it run.  Neither z nor diag(A)^-1
+// is stored: diag(A) at a node is a sum of three products of 1D values, so
+// both vector passes recompute z = r / diag(A), and an iteration moves eight
+// arrays of n_dof values.  The
 // iteration that meets the tolerance records its number; launches of later
 // iterations return at once, so the host launches iterations in groups and
 // reads that number between groups.  (Forming p inside the product, where
