@@ -310,8 +310,16 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
     __syncthreads();
   };
   if constexpr (XD == 2) {
-    // even c: xr0 takes chunk c + 2, xr1 holds chunk c + 1; odd c: swapped
-#pragma unroll 1
+    // even c: xr0 takes chunk c + 2, xr1 holds chunk c + 1; odd c: swapped.
+    // Chunk pairs per loop iteration, measured per precision and cell size
+    // (128-column blocks, ms per colour launch): FP64 p = 5 and FP32 p = 6
+    // the whole loop unrolled (1.031 against 1.066 with two pairs and 1.081
+    // with one; 0.568 against 0.590 and 0.595); FP32 p = 5 and FP64 p = 6
+    // two pairs (0.594 against 0.626 whole and 0.602 one; 1.122 against
+    // 1.124 and 1.126); the complex tile one pair
+    constexpr bool WHOLE = !CPLX && ((sizeof(T) == 8 && NP == 224) || (sizeof(T) == 4 && NP == 352));
+    constexpr int UP = CPLX ? 1 : (WHOLE ? (NCHT + 1) / 2 : 2);
+#pragma unroll UP
     for (int c = 0; c < NCHT; c += 2) {
       chunk(c, xr0, xr1);
       if (c + 1 < NCHT) chunk(c + 1, xr1, xr0);
