@@ -318,9 +318,11 @@ __device__ __forceinline__ void cell_tile(const T *__restrict__ X, int64_t ldx, 
     // two pairs (0.594 against 0.626 whole and 0.602 one; 1.122 against
     // 1.124 and 1.126); p = 4 two pairs (FP64 0.199 against 0.215 with one,
     // FP32 0.122 against 0.126); FP32 p = 7 one pair (0.167 against 0.181
-    // with two); the complex tile one pair
-    constexpr bool WHOLE = !CPLX && ((sizeof(T) == 8 && NP == 224) || (sizeof(T) == 4 && NP == 352));
-    constexpr bool ONE = CPLX || (sizeof(T) == 4 && NP == 512);
+    // with two); the complex tile whole (ms per apply of 64 complex vectors:
+    // p = 5 14.10 against 14.64 with two pairs and 15.08 with one; p = 6
+    // 15.72 against 19.17 and 15.85)
+    constexpr bool WHOLE = CPLX || (sizeof(T) == 8 && NP == 224) || (sizeof(T) == 4 && NP == 352);
+    constexpr bool ONE = sizeof(T) == 4 && NP == 512;
     constexpr int UP = ONE ? 1 : (WHOLE ? (NCHT + 1) / 2 : 2);
 #pragma unroll UP
     for (int c = 0; c < NCHT; c += 2) {
